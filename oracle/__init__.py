@@ -1,0 +1,520 @@
+"""FP64 CPU oracle for the Wilson-clover operator and its solvers.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py``, never by the product library. It shares no code with
+the HIP path; the two meet only in the seeded inputs of ``paper_2202_07388_amd.synthetic``.
+
+Contents, each written from its definition (stencil loops live in ``oracle.c``):
+
+* ``Operator``: D and D^+ (explicit adjoint stencil), block-restricted D_b, clover term;
+* ``dense_matrix``: brute-force D as a dense matrix, for tiny lattices;
+* ``cgne``: textbook conjugate gradient on D^+ D (Sec. 2 of the paper: ``cgne()``),
+  returning the number of CG steps (``status``) and the diagnostics of the paper's
+  Fig. 1 (exact residual, recursive residual, A-orthogonality of successive directions);
+* ``fgcr``: flexible GCR with restarts (Sec. 3.1, Table 2 settings res, nmx, nkv);
+* ``sap`` / ``mr_blocks``: Schwarz alternating procedure (Sec. 3, Fig. 2 and 3): chessboard
+  blocks, grey then white, ``nmr`` minimal-residual steps per block, ``ncy`` cycles;
+* ``sap_adaptive``: the adaptive variant of Sec. 3.2;
+* ``nn_*``: a gauge-covariant linear network of parallel-transport layers, forward and
+  analytic adjoint (not from the paper).
+
+Parity status: see each function's docstring; the only unpinned conventions are the
+U(1) charge in the clover term (q = 1, single c_sw for the combined U(3) link) and the
+iteration counts of mixed-precision and learned solves.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c into liboracle.so with gcc (plain C99, -O2)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", _SRC,
+                               "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        L.oracle_gamma.argtypes = [P]
+        L.oracle_neighbours.argtypes = [P, P]
+        L.oracle_clover.argtypes = [P, P, ctypes.c_double, ctypes.c_double, P]
+        for f in (L.oracle_dw, L.oracle_dw_dag):
+            f.argtypes = [P, ctypes.c_int, P, P, P, P]
+        L.oracle_dw_blocks.argtypes = [P, P, ctypes.c_int, P, P, P, P]
+        L.oracle_u3_links.argtypes = [ctypes.c_long, P, P, P]
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _dims(d):
+    return np.ascontiguousarray(np.asarray(d, dtype=np.int32))
+
+
+def gamma() -> np.ndarray:
+    out = np.zeros((4, 4, 4), dtype=np.complex128)
+    lib().oracle_gamma(_p(out))
+    return out
+
+
+def neighbours(dims) -> np.ndarray:
+    V = int(np.prod(dims))
+    nb = np.zeros((V, 8), dtype=np.int64)
+    lib().oracle_neighbours(_p(_dims(dims)), _p(nb))
+    return nb
+
+
+def u3_links(su3: np.ndarray, theta: np.ndarray) -> np.ndarray:
+    su3 = np.ascontiguousarray(su3, dtype=np.complex128)
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    u = np.empty_like(su3)
+    lib().oracle_u3_links(su3.shape[0], _p(su3), _p(theta), _p(u))
+    return u
+
+
+def clover(dims, u: np.ndarray, m0: float, csw: float) -> np.ndarray:
+    """A(x) as [V, 12, 12] (index spin*3 + colour)."""
+    V = int(np.prod(dims))
+    A = np.zeros((V, 12, 12), dtype=np.complex128)
+    lib().oracle_clover(_p(_dims(dims)), _p(np.ascontiguousarray(u)), m0, csw, _p(A))
+    return A
+
+
+class Operator:
+    """The Wilson-clover operator on one gauge field (links kept as full U(3) matrices)."""
+
+    def __init__(self, dims, su3, theta, m0, csw, bc_t=-1):
+        self.dims = tuple(int(v) for v in dims)
+        self.V = int(np.prod(self.dims))
+        self.bc_t = int(bc_t)
+        self.m0, self.csw = float(m0), float(csw)
+        self.u = u3_links(su3, theta)
+        self.A = clover(self.dims, self.u, self.m0, self.csw)
+        self._d = _dims(self.dims)
+
+    def _apply(self, fn, psi, *extra):
+        psi = np.ascontiguousarray(psi, dtype=np.complex128).reshape(self.V, 4, 3)
+        out = np.empty_like(psi)
+        fn(_p(self._d), *extra, self.bc_t, _p(self.u), _p(self.A), _p(psi), _p(out))
+        return out
+
+    def dw(self, psi):
+        return self._apply(lib().oracle_dw, psi)
+
+    def dw_dag(self, psi):
+        return self._apply(lib().oracle_dw_dag, psi)
+
+    def dw_blocks(self, psi, bs):
+        return self._apply(lib().oracle_dw_blocks, psi, _p(_dims(bs)))
+
+    def normal(self, psi):
+        return self.dw_dag(self.dw(psi))
+
+
+def dense_matrix(op: Operator, which: str = "dw") -> np.ndarray:
+    """Brute force: column j of D is D applied to the j-th unit vector."""
+    n = op.V * 12
+    f = {"dw": op.dw, "dag": op.dw_dag}[which]
+    M = np.zeros((n, n), dtype=np.complex128)
+    e = np.zeros(n, dtype=np.complex128)
+    for j in range(n):
+        e[j] = 1.0
+        M[:, j] = f(e).reshape(-1)
+        e[j] = 0.0
+    return M
+
+
+def dense_block_matrix(op: Operator, bs) -> np.ndarray:
+    n = op.V * 12
+    M = np.zeros((n, n), dtype=np.complex128)
+    e = np.zeros(n, dtype=np.complex128)
+    for j in range(n):
+        e[j] = 1.0
+        M[:, j] = op.dw_blocks(e, bs).reshape(-1)
+        e[j] = 0.0
+    return M
+
+
+def _dot(a, b) -> complex:
+    return complex(np.vdot(a.reshape(-1), b.reshape(-1)))
+
+
+def _norm(a) -> float:
+    return float(np.sqrt(np.vdot(a.reshape(-1), a.reshape(-1)).real))
+
+
+# --------------------------------------------------------------------------- CGNE
+
+def cgne(op: Operator, eta, res: float, nmx: int, history: bool = False):
+    """Conjugate gradient on A = D^+ D from psi = 0 (paper Sec. 2, ``cgne()``).
+
+    Stops when the recursive residual |r| <= res*|eta|, then confirms with the true
+    residual eta - D^+ D psi and continues from it if the check fails. ``status`` is the
+    number of CG steps, -1 when nmx steps did not suffice. The recursive residual uses
+    r_i = r_{i-1} - alpha_{i-1} A p_{i-1} (the sign of Fig. 1's caption is a convention).
+    Diagnostics per step (Fig. 1): exact relative residual, recursive relative residual,
+    and p_{i-1}^+ A p_i.
+    """
+    eta = np.asarray(eta, dtype=np.complex128).reshape(op.V, 4, 3)
+    neta = _norm(eta)
+    x = np.zeros_like(eta)
+    r = eta.copy()
+    p = r.copy()
+    rr = _norm(r) ** 2
+    hist = {"exact": [], "recursive": [], "a_orth": []}
+    q_prev = None
+    status = 0
+    while True:
+        q = op.dw(p)
+        w = op.dw_dag(q)
+        pap = _norm(q) ** 2
+        if history and q_prev is not None:
+            hist["a_orth"].append(_dot(q_prev, q))
+        q_prev = q
+        alpha = rr / pap
+        x = x + alpha * p
+        r = r - alpha * w
+        rr_new = _norm(r) ** 2
+        status += 1
+        if history:
+            hist["exact"].append(_norm(eta - op.normal(x)) / neta)
+            hist["recursive"].append(np.sqrt(rr_new) / neta)
+        if np.sqrt(rr_new) <= res * neta:
+            rt = eta - op.normal(x)
+            if _norm(rt) <= res * neta:
+                break
+            r = rt
+            rr_new = _norm(r) ** 2
+        if status >= nmx:
+            status = -1
+            break
+        beta = rr_new / rr
+        p = r + beta * p
+        rr = rr_new
+    return (x, status, hist) if history else (x, status)
+
+
+# --------------------------------------------------------------------------- FGCR
+
+def fgcr(op: Operator, eta, res: float, nmx: int, nkv: int, precond=None,
+         history: bool = False):
+    """Flexible GCR with restart after nkv Krylov vectors (paper Sec. 3.1, Table 2).
+
+    psi = 0, rho = eta. Within a cycle, for k < nkv: phi_k = M(rho); chi_k = D phi_k;
+    Gram-Schmidt of chi_k against chi_0..chi_{k-1} (a_lk = chi_l^+ chi_k, chi_k -= a_lk
+    chi_l), b_k = |chi_k|, chi_k /= b_k, c_k = chi_k^+ rho, rho -= c_k chi_k. At the end of
+    a cycle (nkv vectors, convergence or nmx), solve the upper-triangular R alpha = c
+    (R_lk = a_lk, R_kk = b_k), psi += sum alpha_l phi_l and recompute rho = eta - D psi
+    in FP64 (the restart step). ``precond`` is M (None: identity). Returns psi, status
+    (GCR steps, -1 when nmx steps did not suffice) and, if asked, the recursive residual
+    norm after every step.
+    """
+    eta = np.asarray(eta, dtype=np.complex128).reshape(op.V, 4, 3)
+    M = precond if precond is not None else (lambda v: v.copy())
+    neta = _norm(eta)
+    tol = res * neta
+    psi = np.zeros_like(eta)
+    rho = eta.copy()
+    status = 0
+    hist = []
+    while True:
+        phis, chis = [], []
+        R = np.zeros((nkv, nkv), dtype=np.complex128)
+        c = np.zeros(nkv, dtype=np.complex128)
+        k = 0
+        rn = _norm(rho)
+        while k < nkv and status < nmx and rn > tol:
+            phi = M(rho)
+            chi = op.dw(phi)
+            for l in range(k):
+                a = _dot(chis[l], chi)
+                R[l, k] = a
+                chi = chi - a * chis[l]
+            b = _norm(chi)
+            R[k, k] = b
+            chi = chi / b
+            c[k] = _dot(chi, rho)
+            rho = rho - c[k] * chi
+            phis.append(phi)
+            chis.append(chi)
+            k += 1
+            status += 1
+            rn = _norm(rho)
+            hist.append(rn / neta)
+        if k > 0:
+            alpha = _back_substitute(R[:k, :k], c[:k])
+            for l in range(k):
+                psi = psi + alpha[l] * phis[l]
+            rho = eta - op.dw(psi)
+            rn = _norm(rho)
+        if rn <= tol:
+            break
+        if status >= nmx:
+            status = -1
+            break
+    return (psi, status, hist) if history else (psi, status)
+
+
+def _back_substitute(R, c):
+    n = len(c)
+    a = np.zeros(n, dtype=np.complex128)
+    for i in range(n - 1, -1, -1):
+        s = c[i] - sum(R[i, j] * a[j] for j in range(i + 1, n))
+        a[i] = s / R[i, i]
+    return a
+
+
+# --------------------------------------------------------------------------- SAP
+
+def block_ids(dims, bs):
+    """Linear block index and block colour (sum of block coordinates mod 2) per site."""
+    x = np.indices(tuple(dims)).reshape(4, -1)
+    nb = [dims[m] // bs[m] for m in range(4)]
+    b = [x[m] // bs[m] for m in range(4)]
+    bid = ((b[0] * nb[1] + b[1]) * nb[2] + b[2]) * nb[3] + b[3]
+    colour = (b[0] + b[1] + b[2] + b[3]) % 2
+    return bid, colour, int(np.prod(nb))
+
+
+def _block_sum(vals_per_site, bid, nblk):
+    re = np.bincount(bid, weights=vals_per_site.real, minlength=nblk)
+    im = np.bincount(bid, weights=vals_per_site.imag, minlength=nblk)
+    return re + 1j * im
+
+
+def mr_blocks(op: Operator, r, bs, colour: int, nmr: int, bid=None, col=None,
+              nblk=None, history=False):
+    """nmr minimal-residual steps from zero on every block of one colour at once.
+
+    For each block b: v = D_b r_b, omega = (v^+ r_b)/(v^+ v), chi_b += omega r_b,
+    r_b -= omega v (paper Sec. 3: the block problems D_i chi = r_i are solved
+    approximately by MR). Returns chi (zero outside the colour) and the final block
+    residuals r_b.
+    """
+    if bid is None:
+        bid, col, nblk = block_ids(op.dims, bs)
+    mask = (col == colour)[:, None, None]
+    rb = np.where(mask, r, 0)
+    chi = np.zeros_like(rb)
+    norms = []
+    for _ in range(nmr):
+        v = np.where(mask, op.dw_blocks(rb, bs), 0)
+        num = _block_sum(np.sum(np.conj(v) * rb, axis=(1, 2)), bid, nblk)
+        den = _block_sum(np.sum(np.abs(v) ** 2, axis=(1, 2)).astype(np.complex128), bid,
+                         nblk).real
+        omega = np.where(den > 0, num / np.where(den > 0, den, 1.0), 0.0)
+        w = omega[bid][:, None, None]
+        chi = chi + w * rb
+        rb = rb - w * v
+        if history:
+            norms.append(np.sqrt(_block_sum(np.sum(np.abs(rb) ** 2, axis=(1, 2))
+                                            .astype(np.complex128), bid, nblk).real))
+    return (chi, rb, norms) if history else (chi, rb)
+
+
+def sap(op: Operator, rho, bs, ncy: int, nmr: int):
+    """Schwarz alternating procedure (paper Sec. 3, Fig. 2 and 3) as a preconditioner.
+
+    psi = 0, r = rho. One cycle solves all colour-0 ("grey"/"black") blocks, then all
+    colour-1 ("white") blocks, each approximately by nmr MR steps on the block-restricted
+    operator D_b (Dirichlet: hops leaving the block dropped), adds the block solutions to
+    psi and recomputes the full residual r = rho - D psi after each colour. ncy = 0
+    returns rho unchanged (no preconditioning, the (0, 0) setting).
+    """
+    rho = np.asarray(rho, dtype=np.complex128).reshape(op.V, 4, 3)
+    if ncy == 0:
+        return rho.copy()
+    bid, col, nblk = block_ids(op.dims, bs)
+    psi = np.zeros_like(rho)
+    r = rho.copy()
+    for _ in range(ncy):
+        for colour in (0, 1):
+            chi, _rb = mr_blocks(op, r, bs, colour, nmr, bid, col, nblk)
+            psi = psi + chi
+            r = rho - op.dw(psi)
+    return psi
+
+
+def sap_adaptive(op: Operator, rho, bs, ncy_max: int, nmr_max: int, alpha: float,
+                 tol: float):
+    """Adaptive SAP (paper Sec. 3.2).
+
+    Cycles stop when a cycle did not lower |r| (at least one cycle runs) or after ncy_max.
+    Each block's MR loop stops (1) after at least 4 steps when |r_b| > alpha * (|r_b| of
+    the previous step), (2) at once when |r_b| grew over the previous step, (3) when
+    |r_b| < tol (tol = res |eta| / n_b), or after nmr_max steps. The step that triggered
+    an exit is kept. Returns psi and the list of (cycles, per-block MR step counts).
+    """
+    rho = np.asarray(rho, dtype=np.complex128).reshape(op.V, 4, 3)
+    bid, col, nblk = block_ids(op.dims, bs)
+    psi = np.zeros_like(rho)
+    r = rho.copy()
+    rn = _norm(r)
+    steps = []
+    cycles = 0
+    for _ in range(ncy_max):
+        for colour in (0, 1):
+            mask = (col == colour)[:, None, None]
+            rb = np.where(mask, r, 0)
+            chi = np.zeros_like(rb)
+            prev = np.sqrt(_block_sum(np.sum(np.abs(rb) ** 2, axis=(1, 2))
+                                      .astype(np.complex128), bid, nblk).real)
+            active = np.zeros(nblk, dtype=bool)
+            active[np.unique(bid[col == colour])] = True
+            active &= prev >= tol
+            nsteps = np.zeros(nblk, dtype=np.int64)
+            for k in range(nmr_max):
+                if not active.any():
+                    break
+                act = active[bid][:, None, None] & mask
+                v = np.where(act, op.dw_blocks(np.where(act, rb, 0), bs), 0)
+                num = _block_sum(np.sum(np.conj(v) * rb, axis=(1, 2)), bid, nblk)
+                den = _block_sum(np.sum(np.abs(v) ** 2, axis=(1, 2)).astype(np.complex128),
+                                 bid, nblk).real
+                omega = np.where(active & (den > 0), num / np.where(den > 0, den, 1.0), 0.0)
+                w = omega[bid][:, None, None]
+                chi = chi + w * rb
+                rb = rb - w * v
+                nsteps += active
+                cur = np.sqrt(_block_sum(np.sum(np.abs(rb) ** 2, axis=(1, 2))
+                                         .astype(np.complex128), bid, nblk).real)
+                stop = ((k + 1 >= 4) & (cur > alpha * prev)) | (cur > prev) | (cur < tol)
+                active &= ~stop
+                prev = np.where(active, cur, prev)
+            steps.append(nsteps[np.unique(bid[col == colour])])
+            psi = psi + chi
+            r = rho - op.dw(psi)
+        cycles += 1
+        rn_new = _norm(r)
+        if rn_new >= rn:
+            break
+        rn = rn_new
+    return psi, cycles, steps
+
+
+# --------------------------------------------------------------------------- NN
+
+NPATH = 9  # identity, then +mu and -mu for mu = 0..3
+
+
+def nn_transport(op: Operator, v, path: int):
+    """Parallel transport of a [V, 4, 3] field along one path of the network.
+
+    path 0: identity; path 1 + 2*mu: (T v)(x) = s U_mu(x) v(x + mu); path 2 + 2*mu:
+    (T v)(x) = s U_mu(x - mu)^+ v(x - mu), with s the same fermion boundary sign as in D.
+    Spin is untouched.
+    """
+    if path == 0:
+        return v.copy()
+    mu = (path - 1) // 2
+    fwd = (path - 1) % 2 == 0
+    dims = op.dims
+    x = np.indices(dims).reshape(4, -1)
+    shift = x.copy()
+    shift[mu] = (x[mu] + (1 if fwd else -1)) % dims[mu]
+    nbr = ((shift[0] * dims[1] + shift[1]) * dims[2] + shift[2]) * dims[3] + shift[3]
+    T = dims[0]
+    if fwd:
+        U = op.u[:, mu]
+        s = np.where((mu == 0) & (x[0] == T - 1), op.bc_t, 1.0)
+        out = np.einsum("xij,xsj->xsi", U, v[nbr])
+    else:
+        U = op.u[nbr, mu]
+        s = np.where((mu == 0) & (shift[0] == T - 1), op.bc_t, 1.0)
+        out = np.einsum("xji,xsj->xsi", np.conj(U), v[nbr])
+    return s[:, None, None] * out
+
+
+def nn_transport_adj(op: Operator, v, path: int):
+    """Adjoint of nn_transport (path +mu and -mu are each other's adjoint)."""
+    if path == 0:
+        return v.copy()
+    mu = (path - 1) // 2
+    fwd = (path - 1) % 2 == 0
+    return nn_transport(op, v, 2 + 2 * mu if fwd else 1 + 2 * mu)
+
+
+def nn_layer(op: Operator, W, x):
+    """out_a = sum_p sum_b W[p, a, b] (4x4 spin matrix) applied to T_p x_b.
+
+    W: [9, Cout, Cin, 4, 4] complex; x: [Cin, V, 4, 3].
+    """
+    t = np.stack([np.stack([nn_transport(op, x[b], p) for b in range(x.shape[0])])
+                  for p in range(NPATH)])          # [9, Cin, V, 4, 3]
+    return np.einsum("pabst,pbxtc->axsc", W, t), t
+
+
+def nn_forward(op: Operator, weights, r):
+    """Network N(r) = L3(L2(L1(r))): linear layers 1 -> 8 -> 8 -> 1 channels.
+
+    Returns the output [V, 4, 3] and the list of layer inputs (for the backward pass).
+    """
+    x = np.asarray(r, dtype=np.complex128).reshape(1, op.V, 4, 3)
+    acts = []
+    for W in weights:
+        acts.append(x)
+        x, _ = nn_layer(op, W, x)
+    return x[0], acts
+
+
+def nn_backward(op: Operator, weights, acts, g_out):
+    """Analytic adjoint. g_out = dL/d conj(out) ([V, 4, 3]).
+
+    Returns (grads, g_in): grads[l] = dL/dRe W + i dL/dIm W = 2 dL/d conj(W), and
+    g_in = dL/d conj(r).
+    """
+    g = np.asarray(g_out).reshape(1, op.V, 4, 3)
+    grads = [None] * len(weights)
+    for l in range(len(weights) - 1, -1, -1):
+        W, x = weights[l], acts[l]
+        t = np.stack([np.stack([nn_transport(op, x[b], p) for b in range(x.shape[0])])
+                      for p in range(NPATH)])
+        grads[l] = 2.0 * np.einsum("axsc,pbxtc->pabst", g, np.conj(t))
+        gt = np.einsum("pabst,axsc->pbxtc", np.conj(W), g)   # W^+ applied per path
+        g = np.stack([sum(nn_transport_adj(op, gt[p, b], p) for p in range(NPATH))
+                      for b in range(x.shape[0])])
+    return grads, g[0]
+
+
+def nn_loss(op: Operator, weights, r, e):
+    """L = |N(r) - e|^2 / |e|^2 and dL/d conj(out)."""
+    out, acts = nn_forward(op, weights, r)
+    e = np.asarray(e).reshape(op.V, 4, 3)
+    ne2 = _norm(e) ** 2
+    d = out - e
+    return _norm(d) ** 2 / ne2, d / ne2, acts
+
+
+def nn_identity_weights(channels=(1, 8, 8, 1), seed=None, scale=0.0):
+    """Weights whose network is the identity map: layer l maps channel 0 to channel 0
+    through the identity path with the 4x4 unit spin matrix; optional small noise."""
+    rng = np.random.Generator(np.random.PCG64(seed)) if seed is not None else None
+    ws = []
+    for cin, cout in zip(channels[:-1], channels[1:]):
+        W = np.zeros((NPATH, cout, cin, 4, 4), dtype=np.complex128)
+        W[0, 0, 0] = np.eye(4)
+        if rng is not None and scale:
+            W += scale * (rng.standard_normal(W.shape) + 1j * rng.standard_normal(W.shape))
+        ws.append(W)
+    return ws

@@ -1,0 +1,484 @@
+"""Pins of the FP64 CPU oracle against facts fixed by mathematics and the paper.
+
+None of these re-types an oracle formula: each check goes through an independent
+route (closed forms, brute-force dense matrices, algebraic identities, optimality
+properties of the Krylov methods) chosen so that a dropped term, a wrong sign or index,
+or a transposed operand in the oracle fails at least one of them.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2202_07388_amd import synthetic as syn
+
+D44 = (4, 4, 4, 4)
+
+
+def _op(dims, m0=0.1, csw=1.5, eps=0.3, seed=7388, bc=-1):
+    su3, th = syn.gauge_field(dims, eps, 0.1, seed)
+    return oracle.Operator(dims, su3, th, m0, csw, bc)
+
+
+@pytest.fixture(scope="module")
+def op44():
+    return _op(D44)
+
+
+@pytest.fixture(scope="module")
+def dense44(op44):
+    return oracle.dense_matrix(op44)
+
+
+def spin(m, v):
+    return np.einsum("st,xtc->xsc", m, v)
+
+
+# ----------------------------------------------------------------- basis, geometry
+
+def test_gamma_clifford_and_chiral_basis():
+    g = oracle.gamma()
+    for m in range(4):
+        assert np.allclose(g[m], g[m].conj().T)
+        for n in range(4):
+            assert np.allclose(g[m] @ g[n] + g[n] @ g[m], 2.0 * (m == n) * np.eye(4))
+    g5 = g[0] @ g[1] @ g[2] @ g[3]
+    assert np.allclose(g5, np.diag([1, 1, -1, -1]))
+    # every sigma_{mu nu} is block diagonal in this basis (chirality is conserved)
+    for m in range(4):
+        for n in range(4):
+            s = 0.5j * (g[m] @ g[n] - g[n] @ g[m])
+            assert np.allclose(s[:2, 2:], 0) and np.allclose(s[2:, :2], 0)
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 2, 4, 8)])
+def test_neighbours_round_trip(dims):
+    nb = oracle.neighbours(dims)
+    V = int(np.prod(dims))
+    idx = np.arange(V)
+    x = np.indices(dims).reshape(4, -1)
+    for mu in range(4):
+        f, b = nb[:, 2 * mu], nb[:, 2 * mu + 1]
+        assert np.array_equal(nb[f, 2 * mu + 1], idx)
+        assert np.array_equal(nb[b, 2 * mu], idx)
+        y = x.copy()
+        y[mu] = (y[mu] + 1) % dims[mu]
+        lex = ((y[0] * dims[1] + y[1]) * dims[2] + y[2]) * dims[3] + y[3]
+        assert np.array_equal(f, lex)
+    par = x.sum(axis=0) % 2
+    assert (par == 0).sum() == V // 2
+
+
+def test_generator_links_in_su3_times_u1():
+    su3, th = syn.gauge_field(D44, 0.3, 0.1, 1)
+    u = su3.reshape(-1, 3, 3)
+    err = np.abs(u @ np.conj(np.swapaxes(u, 1, 2)) - np.eye(3)).max()
+    assert err < 1e-14
+    assert np.abs(np.linalg.det(u) - 1).max() < 1e-14
+    # the third row is exactly what a compressed two-row link rebuilds
+    assert np.abs(u[:, 2] - np.conj(np.cross(u[:, 0], u[:, 1]))).max() < 1e-15
+    full = oracle.u3_links(su3, th).reshape(-1, 3, 3)
+    assert np.allclose(np.linalg.det(full), np.exp(3j * th.reshape(-1)))
+
+
+# ----------------------------------------------------------------- free field
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (16, 8, 8, 8)])
+def test_free_field_plane_waves(dims):
+    """D e^{ipx} u = [m0 + sum(1 - cos p) + i sum gamma sin p] e^{ipx} u, with
+    antiperiodic time momenta p0 = pi(2n+1)/T and periodic p_k = 2 pi n / L_k."""
+    su3, th = syn.unit_gauge_field(dims)
+    m0 = 0.1
+    op = oracle.Operator(dims, su3, th, m0, 1.5, -1)
+    g = oracle.gamma()
+    rng = np.random.default_rng(3)
+    for _ in range(4):
+        n = [rng.integers(0, d) for d in dims]
+        p = np.array([np.pi * (2 * n[0] + 1) / dims[0]] +
+                     [2 * np.pi * n[k] / dims[k] for k in (1, 2, 3)])
+        u = rng.standard_normal((4, 3)) + 1j * rng.standard_normal((4, 3))
+        psi = syn.plane_wave(dims, p, u)
+        Dp = (m0 + np.sum(1 - np.cos(p))) * np.eye(4) + 1j * sum(
+            g[m] * np.sin(p[m]) for m in range(4))
+        got = op.dw(psi)
+        assert np.abs(got - spin(Dp, psi)).max() < 1e-13 * np.abs(psi).max()
+        got_d = op.dw_dag(psi)
+        assert np.abs(got_d - spin(Dp.conj().T, psi)).max() < 1e-13 * np.abs(psi).max()
+
+
+def test_periodic_time_plane_wave():
+    """With bc_t = +1 the time momenta are 2 pi n / T instead."""
+    dims = (4, 4, 4, 4)
+    su3, th = syn.unit_gauge_field(dims)
+    op = oracle.Operator(dims, su3, th, -0.3, 1.0, +1)
+    g = oracle.gamma()
+    p = np.array([2 * np.pi / 4, 0, 2 * np.pi * 3 / 4, 2 * np.pi / 4])
+    u = np.arange(12).reshape(4, 3) + 0.5j
+    psi = syn.plane_wave(dims, p, u)
+    Dp = (-0.3 + np.sum(1 - np.cos(p))) * np.eye(4) + 1j * sum(
+        g[m] * np.sin(p[m]) for m in range(4))
+    assert np.abs(op.dw(psi) - spin(Dp, psi)).max() < 1e-13 * np.abs(psi).max()
+
+
+# ----------------------------------------------------------------- gamma5, gauge
+
+def test_gamma5_hermiticity(op44):
+    x = syn.gaussian_spinor(D44, 11)
+    y = syn.gaussian_spinor(D44, 12)
+    g5 = np.diag([1.0, 1.0, -1.0, -1.0])
+    lhs = np.vdot(y, op44.dw(x))
+    rhs = np.vdot(op44.dw_dag(y), x)
+    assert abs(lhs - rhs) < 1e-13 * abs(lhs)
+    g5dg5 = spin(g5, op44.dw(spin(g5, x)))
+    assert np.abs(g5dg5 - op44.dw_dag(x)).max() < 1e-14 * np.abs(x).max()
+
+
+def test_gauge_covariance():
+    dims = (4, 4, 2, 6)
+    su3, th = syn.gauge_field(dims, 0.3, 0.1, 5)
+    G = syn.random_gauge_transform(dims, 6)
+    op = oracle.Operator(dims, su3, th, 0.2, 1.3, -1)
+    u = op.u
+    nb = oracle.neighbours(dims)
+    # U^g_mu(x) = G(x) U_mu(x) G(x + mu)^+ , split back into SU(3) x U(1)
+    ug = np.einsum("xij,xmjk,xmlk->xmil", G, u, np.conj(G[nb[:, 0::2]]))
+    det = np.linalg.det(ug)
+    thg = np.angle(det) / 3.0
+    su3g = ug * np.exp(-1j * thg)[..., None, None]
+    opg = oracle.Operator(dims, su3g, thg, 0.2, 1.3, -1)
+    assert np.abs(opg.u - ug).max() < 1e-13
+    psi = syn.gaussian_spinor(dims, 7)
+    Gpsi = np.einsum("xij,xsj->xsi", G, psi)
+    lhs = opg.dw(Gpsi)
+    rhs = np.einsum("xij,xsj->xsi", G, op.dw(psi))
+    assert np.abs(lhs - rhs).max() < 1e-13 * np.abs(rhs).max()
+    # clover term transforms as A -> G A G^+ (G acting on colour)
+    Gs = np.einsum("st,xij->xsitj", np.eye(4), G).reshape(-1, 12, 12)
+    assert np.abs(opg.A - Gs @ op.A @ np.conj(np.swapaxes(Gs, 1, 2))).max() < 1e-13
+
+
+# ----------------------------------------------------------------- clover term
+
+def test_clover_hermitian_chiral_trace(op44):
+    A = op44.A
+    assert np.abs(A - np.conj(np.swapaxes(A, 1, 2))).max() < 1e-14
+    assert np.abs(A[:, :6, 6:]).max() == 0 and np.abs(A[:, 6:, :6]).max() == 0
+    # sigma_{mu nu} is traceless within each chirality: tr A_+- = 6 (4 + m0)
+    tr_p = np.trace(A[:, :6, :6], axis1=1, axis2=2)
+    tr_m = np.trace(A[:, 6:, 6:], axis1=1, axis2=2)
+    assert np.abs(tr_p - 6 * 4.1).max() < 1e-13
+    assert np.abs(tr_m - 6 * 4.1).max() < 1e-13
+    # and it is not trivial on this rough field
+    assert np.abs(A - 4.1 * np.eye(12)).max() > 0.1
+
+
+def test_clover_unit_field():
+    su3, th = syn.unit_gauge_field(D44)
+    op = oracle.Operator(D44, su3, th, -0.05, 1.7, -1)
+    assert np.abs(op.A - 3.95 * np.eye(12)).max() < 1e-15
+
+
+@pytest.mark.parametrize("plane,diag", [((1, 2), [1, -1, 1, -1]), ((0, 3), [-1, 1, 1, -1])])
+def test_clover_constant_abelian_flux(plane, diag):
+    """Constant flux phi in one plane: every leaf is e^{i phi}, Fhat = i sin(phi), and the
+    clover term is -(c_sw/2) sin(phi) sigma_{mu nu}: sigma_12 = diag(-1,1,-1,1),
+    sigma_03 = diag(1,-1,-1,1) in the chiral basis."""
+    dims = (4, 6, 4, 8)
+    su3, _ = syn.unit_gauge_field(dims)
+    theta, phi = syn.abelian_flux_theta(dims, 1, plane)
+    m0, csw = 0.1, 1.7
+    op = oracle.Operator(dims, su3, theta, m0, csw, -1)
+    want = (4 + m0) * np.eye(12) + 0.5 * csw * np.sin(phi) * np.kron(np.diag(diag), np.eye(3))
+    assert np.abs(op.A - want).max() < 1e-14
+
+
+# ----------------------------------------------------------------- dense 4^4
+
+def test_dense_structure(dense44):
+    """54 non-zeros per row (6 clover + 8 hops x 2 spin x 3 colour) of 3072, ~1.8 %
+    (the paper quotes about 2 % for its 4^4 operator)."""
+    nnz = (np.abs(dense44) > 0).sum(axis=1)
+    assert np.all(nnz == 54)
+    assert abs(nnz.sum() / dense44.size - 54 / 3072) < 1e-12
+
+
+def test_dense_adjoint(op44, dense44):
+    dag = oracle.dense_matrix(op44, "dag")
+    assert np.abs(dag - dense44.conj().T).max() < 1e-15
+
+
+def test_even_odd_structure(dense44):
+    """Even sites couple to odd sites only through hops: the even-even and odd-odd
+    blocks hold nothing but the (site-diagonal) clover term."""
+    x = np.indices(D44).reshape(4, -1)
+    par = np.repeat(x.sum(axis=0) % 2, 12)
+    for p in (0, 1):
+        blk = dense44[np.ix_(par == p, par == p)]
+        n = blk.shape[0] // 12
+        sites = blk.reshape(n, 12, n, 12)
+        off = sites.copy()
+        off[np.arange(n), :, np.arange(n), :] = 0
+        assert np.abs(off).max() == 0
+
+
+def test_spectrum_conjugate_pairs():
+    dims = (4, 2, 2, 2)
+    op = _op(dims, m0=-0.2, csw=1.5, eps=0.5, seed=9)
+    ev = np.linalg.eigvals(oracle.dense_matrix(op))
+    ev_c = np.conj(ev)
+    d = np.abs(ev[:, None] - ev_c[None, :]).min(axis=1)
+    assert d.max() < 1e-10
+
+
+# ----------------------------------------------------------------- CGNE
+
+def test_cgne_matches_dense_solve(op44, dense44):
+    eta = syn.gaussian_spinor(D44, 7388 + 1000)
+    x, status, hist = oracle.cgne(op44, eta, 1e-10, 1000, history=True)
+    assert status > 0
+    xd = np.linalg.solve(dense44.conj().T @ dense44, eta.reshape(-1))
+    # true residual of the normal equations and error against the dense solution
+    r = eta - op44.normal(x)
+    assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(eta)
+    assert np.linalg.norm(x.reshape(-1) - xd) <= 1e-7 * np.linalg.norm(xd)
+    # successive directions are A-orthogonal (Fig. 1, panel d)
+    a = np.abs(np.array(hist["a_orth"]))
+    assert a.max() < 1e-8 * np.linalg.norm(eta) ** 2
+    # the exact residual follows the recursive one closely in FP64 (no reset needed)
+    gap = np.abs(np.array(hist["exact"]) - np.array(hist["recursive"]))
+    assert gap.max() < 1e-11
+
+
+def test_cg_krylov_optimality(op44, dense44):
+    """After k steps CG minimises the A-norm of the error over K_k(A, eta), A = D^+ D."""
+    eta = syn.gaussian_spinor(D44, 5).reshape(-1)
+    A = dense44.conj().T @ dense44
+    xs = np.linalg.solve(A, eta)
+    Q = np.zeros((eta.size, 0), dtype=np.complex128)
+    v = eta / np.linalg.norm(eta)
+    for k in range(1, 13):
+        Q = np.column_stack([Q, v])
+        w = A @ v
+        w -= Q @ (Q.conj().T @ w)
+        w -= Q @ (Q.conj().T @ w)
+        v = w / np.linalg.norm(w)
+        xk, st = oracle.cgne(op44, eta, 1e-30, k)
+        assert st == -1
+        y = np.linalg.solve(Q.conj().T @ A @ Q, Q.conj().T @ eta)
+        xopt = Q @ y
+        e_cg = xk.reshape(-1) - xs
+        e_opt = xopt - xs
+        an = lambda e: np.sqrt(np.vdot(e, A @ e).real)
+        assert abs(an(e_cg) - an(e_opt)) <= 1e-9 * an(xs)
+        assert np.linalg.norm(xk.reshape(-1) - xopt) <= 1e-8 * np.linalg.norm(xs)
+
+
+# ----------------------------------------------------------------- FGCR
+
+def test_gcr_residuals_equal_gmres(op44, dense44):
+    """Unpreconditioned, unrestarted GCR minimises |eta - D y| over K_k(D, eta): its
+    residual norms equal GMRES's, obtained here by dense least squares."""
+    eta = syn.gaussian_spinor(D44, 21)
+    k_max = 12
+    _, st, hist = oracle.fgcr(op44, eta, 1e-30, k_max, 64, None, history=True)
+    assert st == -1
+    b = eta.reshape(-1)
+    K = [b]
+    for _ in range(k_max - 1):
+        K.append(dense44 @ K[-1])
+    for k in range(1, k_max + 1):
+        B = np.linalg.qr(np.column_stack(K[:k]))[0]
+        y = np.linalg.lstsq(dense44 @ B, b, rcond=None)[0]
+        gm = np.linalg.norm(b - dense44 @ (B @ y)) / np.linalg.norm(b)
+        assert abs(hist[k - 1] - gm) <= 1e-10 * max(gm, 1e-3)
+    assert np.all(np.diff(hist) <= 1e-15)
+
+
+def test_gcr_exact_preconditioner_one_step(op44, dense44):
+    eta = syn.gaussian_spinor(D44, 22)
+    Dinv = np.linalg.inv(dense44)
+    M = lambda v: (Dinv @ v.reshape(-1)).reshape(v.shape)
+    psi, st = oracle.fgcr(op44, eta, 1e-10, 5, 4, M)
+    assert st == 1
+    assert np.linalg.norm(eta - op44.dw(psi)) <= 1e-10 * np.linalg.norm(eta)
+
+
+def test_gcr_restarts_match_dense_solve(op44, dense44):
+    eta = syn.gaussian_spinor(D44, 23)
+    psi, st = oracle.fgcr(op44, eta, 1e-10, 500, 8)
+    assert st > 8  # needs several restarts
+    xd = np.linalg.solve(dense44, eta.reshape(-1))
+    assert np.linalg.norm(psi.reshape(-1) - xd) <= 1e-8 * np.linalg.norm(xd)
+
+
+# ----------------------------------------------------------------- SAP
+
+BS2 = (2, 2, 2, 2)
+
+
+def test_block_operator_is_masked_dense(op44, dense44):
+    """D_b (hops leaving the block dropped) equals P_b D P_b for every block."""
+    Db = oracle.dense_block_matrix(op44, BS2)
+    bid, col, nblk = oracle.block_ids(D44, BS2)
+    b12 = np.repeat(bid, 12)
+    same = b12[:, None] == b12[None, :]
+    assert np.array_equal(Db, np.where(same, dense44, 0))
+
+
+def test_mr_step_minimises_block_residual(op44):
+    r = syn.gaussian_spinor(D44, 31)
+    bid, col, nblk = oracle.block_ids(D44, BS2)
+    chi, rb = oracle.mr_blocks(op44, r, BS2, 0, 1)
+    for b in np.unique(bid[col == 0])[:6]:
+        m = bid == b
+        v = op44.dw_blocks(np.where(m[:, None, None], r, 0), BS2)[m].reshape(-1)
+        r0 = r[m].reshape(-1)
+        # closed form of one MR step: |r1|^2 = |r0|^2 - |v^+ r0|^2 / |v|^2
+        want = np.vdot(r0, r0).real - abs(np.vdot(v, r0)) ** 2 / np.vdot(v, v).real
+        assert abs(np.vdot(rb[m], rb[m]).real - want) < 1e-12 * np.vdot(r0, r0).real
+        # and the block residual is r0 - D_b chi
+        res = r0 - op44.dw_blocks(np.where(m[:, None, None], chi, 0), BS2)[m].reshape(-1)
+        assert np.abs(res - rb[m].reshape(-1)).max() < 1e-13
+    assert np.abs(chi[col == 1]).max() == 0
+
+
+def test_mr_norm_never_increases(op44):
+    r = syn.gaussian_spinor(D44, 32)
+    _, _, norms = oracle.mr_blocks(op44, r, BS2, 1, 8, history=True)
+    n = np.array(norms)
+    bid, col, _ = oracle.block_ids(D44, BS2)
+    used = np.unique(bid[col == 1])
+    assert np.all(np.diff(n[:, used], axis=0) <= 1e-14)
+
+
+def test_sap_cycle_is_block_gauss_seidel(op44, dense44):
+    """MR iterated to convergence makes one SAP cycle the block Gauss-Seidel sweep
+    psi_b = D_bb^-1 rho_b; psi_w = D_ww^-1 (rho - D psi_b)_w."""
+    rho = syn.gaussian_spinor(D44, 33)
+    bid, col, _ = oracle.block_ids(D44, BS2)
+    c12 = np.repeat(col, 12)
+    b, w = c12 == 0, c12 == 1
+    r = rho.reshape(-1)
+    psi = np.zeros_like(r)
+    psi[b] = np.linalg.solve(dense44[np.ix_(b, b)], r[b])
+    res = r - dense44 @ psi
+    psi[w] = np.linalg.solve(dense44[np.ix_(w, w)], res[w])
+    got = oracle.sap(op44, rho, BS2, 1, 150).reshape(-1)
+    assert np.linalg.norm(got - psi) <= 1e-9 * np.linalg.norm(psi)
+
+
+def test_sap_zero_cycles_is_identity(op44):
+    rho = syn.gaussian_spinor(D44, 34)
+    assert np.array_equal(oracle.sap(op44, rho, BS2, 0, 4), rho)
+
+
+def test_sap_gcr_converges_to_dense_solution(op44, dense44):
+    eta = syn.gaussian_spinor(D44, 35)
+    M = lambda v: oracle.sap(op44, v, BS2, 3, 4)
+    psi, st = oracle.fgcr(op44, eta, 1e-10, 200, 16, M)
+    _, st0 = oracle.fgcr(op44, eta, 1e-10, 500, 16, None)
+    assert 0 < st < st0
+    xd = np.linalg.solve(dense44, eta.reshape(-1))
+    assert np.linalg.norm(psi.reshape(-1) - xd) <= 1e-8 * np.linalg.norm(xd)
+
+
+def test_adaptive_sap_exit_rules(op44):
+    rho = syn.gaussian_spinor(D44, 36)
+    psi, cycles, steps = oracle.sap_adaptive(op44, rho, BS2, 20, 20, 0.9, 0.0)
+    assert 1 <= cycles <= 20
+    assert all(np.all((s >= 1) & (s <= 20)) for s in steps)
+    r = np.linalg.norm(rho - op44.dw(psi))
+    assert r < np.linalg.norm(rho)
+    # a huge tolerance makes every block exit at once (rule 3): nothing is done
+    psi0, c0, s0 = oracle.sap_adaptive(op44, rho, BS2, 20, 20, 0.9, 1e30)
+    assert c0 == 1 and np.abs(psi0).max() == 0 and all(np.all(s == 0) for s in s0)
+
+
+# ----------------------------------------------------------------- network
+
+DN = (4, 2, 2, 4)
+
+
+@pytest.fixture(scope="module")
+def opn():
+    return _op(DN, m0=-0.05, csw=1.7, seed=44)
+
+
+def _rand_weights(seed, scale=0.3):
+    return oracle.nn_identity_weights(seed=seed, scale=scale)
+
+
+def test_nn_identity_init(opn):
+    r = syn.gaussian_spinor(DN, 1)
+    out, _ = oracle.nn_forward(opn, oracle.nn_identity_weights(), r)
+    assert np.array_equal(out, r)
+
+
+def test_nn_transport_adjoint_pairs(opn):
+    a = syn.gaussian_spinor(DN, 2)
+    b = syn.gaussian_spinor(DN, 3)
+    for p in range(oracle.NPATH):
+        lhs = np.vdot(b, oracle.nn_transport(opn, a, p))
+        rhs = np.vdot(oracle.nn_transport_adj(opn, b, p), a)
+        assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def test_nn_transport_reproduces_hopping_term(opn):
+    """The hop part of D is -1/2 sum_mu [(1-gamma_mu) T_{+mu} + (1+gamma_mu) T_{-mu}]."""
+    psi = syn.gaussian_spinor(DN, 4)
+    g = oracle.gamma()
+    hop = np.zeros_like(psi)
+    for mu in range(4):
+        hop -= 0.5 * spin(np.eye(4) - g[mu], oracle.nn_transport(opn, psi, 1 + 2 * mu))
+        hop -= 0.5 * spin(np.eye(4) + g[mu], oracle.nn_transport(opn, psi, 2 + 2 * mu))
+    diag = np.einsum("xij,xj->xi", opn.A, psi.reshape(-1, 12)).reshape(psi.shape)
+    assert np.abs(opn.dw(psi) - (diag + hop)).max() < 1e-13
+
+
+def test_nn_linear_and_equivariant():
+    dims = (4, 2, 2, 4)
+    su3, th = syn.gauge_field(dims, 0.3, 0.1, 45)
+    op = oracle.Operator(dims, su3, th, -0.05, 1.7, -1)
+    W = _rand_weights(1)
+    a, b = syn.gaussian_spinor(dims, 5), syn.gaussian_spinor(dims, 6)
+    na, _ = oracle.nn_forward(op, W, a)
+    nb_, _ = oracle.nn_forward(op, W, b)
+    nab, _ = oracle.nn_forward(op, W, a + 2j * b)
+    assert np.abs(nab - (na + 2j * nb_)).max() < 1e-12 * np.abs(nab).max()
+    G = syn.random_gauge_transform(dims, 7)
+    nbm = oracle.neighbours(dims)
+    ug = np.einsum("xij,xmjk,xmlk->xmil", G, op.u, np.conj(G[nbm[:, 0::2]]))
+    thg = np.angle(np.linalg.det(ug)) / 3.0
+    opg = oracle.Operator(dims, ug * np.exp(-1j * thg)[..., None, None], thg, -0.05, 1.7, -1)
+    Ga = np.einsum("xij,xsj->xsi", G, a)
+    lhs, _ = oracle.nn_forward(opg, W, Ga)
+    rhs = np.einsum("xij,xsj->xsi", G, na)
+    assert np.abs(lhs - rhs).max() < 1e-12 * np.abs(rhs).max()
+
+
+def test_nn_gradients_finite_differences(opn):
+    W = _rand_weights(2, 0.2)
+    r = syn.gaussian_spinor(DN, 8)
+    e = syn.gaussian_spinor(DN, 9)
+    L, g, acts = oracle.nn_loss(opn, W, r, e)
+    grads, gin = oracle.nn_backward(opn, W, acts, g)
+    rng = np.random.default_rng(0)
+    h = 1e-6
+    for l in range(3):
+        for _ in range(6):
+            idx = tuple(rng.integers(0, s) for s in W[l].shape)
+            for unit, part in ((1.0, "re"), (1j, "im")):
+                Wp = [w.copy() for w in W]
+                Wm = [w.copy() for w in W]
+                Wp[l][idx] += unit * h
+                Wm[l][idx] -= unit * h
+                fd = (oracle.nn_loss(opn, Wp, r, e)[0] - oracle.nn_loss(opn, Wm, r, e)[0]) / (2 * h)
+                an = grads[l][idx].real if part == "re" else grads[l][idx].imag
+                assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (l, idx, part, fd, an)
+    # input gradient: dL/dRe r + i dL/dIm r = 2 gin
+    for _ in range(4):
+        j = tuple(rng.integers(0, s) for s in r.shape)
+        rp, rm = r.copy(), r.copy()
+        rp[j] += h
+        rm[j] -= h
+        fd = (oracle.nn_loss(opn, W, rp, e)[0] - oracle.nn_loss(opn, W, rm, e)[0]) / (2 * h)
+        assert abs(fd - 2 * gin[j].real) <= 1e-6 * max(1.0, abs(fd))
