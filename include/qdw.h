@@ -1,0 +1,109 @@
+/*
+ * qdw.h -- C ABI of libqdw: the O(a)-improved Wilson-clover Dirac operator and its
+ * solvers on one AMD Instinct MI355X (gfx950).
+ *
+ * The paper (introduction) names the application of the Dirac operator to a spinor
+ * field -- a bandwidth-bound variant of a sparse matrix-vector product -- as one of the
+ * most important kernels of lattice field theory, and analyses the two solvers that
+ * spend their time in it: the mixed-precision conjugate gradient on the normal
+ * equations (Sec. 2, cgne) and the Schwarz-alternating-procedure preconditioned flexible
+ * GCR (Sec. 3, fgcr with the settings of Table 2). This library provides exactly that
+ * path as hand-written HIP kernels.
+ *
+ * Operator (standard Wilson-Sheikholeslami-Wohlert form):
+ *   (D psi)(x) = A(x) psi(x) - 1/2 sum_mu [ s U_mu(x) (1 - g_mu) psi(x+mu)
+ *                                         + s U_mu(x-mu)^+ (1 + g_mu) psi(x-mu) ]
+ *   A(x) = (4 + m0) + c_sw (i/4) sum_{mu,nu} sigma_{mu nu} Fhat_{mu nu}(x)
+ * with U = exp(i theta) V, V in SU(3), theta the U(1) angle (QCD+QED, charge 1), s = bc_t
+ * on hops across the time boundary, chiral gamma basis with gamma_5 = diag(1,1,-1,-1).
+ *
+ * Conventions for every entry point:
+ *  - Pointers marked (device) are device memory of the current HIP device; (host) are
+ *    host memory. The caller owns every buffer it passes; the library never frees or
+ *    retains them beyond the call (except where stated).
+ *  - `stream` is a hipStream_t (NULL = default stream). All device work of a call is
+ *    enqueued on it. Calls that return solver information synchronise the stream.
+ *  - Return value: QDW_OK (0) on success, a negative QDW_E* code otherwise; the
+ *    message of the last failure on the calling thread is qdw_last_error(). No C++
+ *    exception crosses this boundary.
+ *  - A qdw_op may be used from one stream at a time (its reduction scratch is shared).
+ *
+ * Field layout ("eo-SoA", what dw_apply and the solvers read and write): sites split by
+ * parity (x0+x1+x2+x3) mod 2, even first (the paper's even-odd ordering, Fig. 3 left),
+ * each parity stored as [chunk][V/2] 16-byte chunks of the site's 24 reals (12 complex,
+ * index spin*3 + colour, interleaved re/im). Within a parity the site with lexicographic
+ * index lex = ((x0*L1 + x1)*L2 + x2)*L3 + x3 sits at position lex/2. Use qdw_pack /
+ * qdw_unpack to convert from and to the canonical layout [V][4][3] complex128.
+ */
+#ifndef QDW_H
+#define QDW_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* storage precision of a spinor field; arithmetic is FP64 for QDW_F64, FP32 otherwise */
+typedef enum {
+    QDW_F64 = 0,   /* binary64 storage and arithmetic                          */
+    QDW_F32 = 1,   /* binary32 storage and arithmetic                          */
+    QDW_F16S = 2,  /* binary16 storage, binary32 arithmetic                    */
+    QDW_BF16S = 3  /* bfloat16 storage, binary32 arithmetic                    */
+} qdw_prec;
+
+enum {
+    QDW_OK = 0,
+    QDW_EINVAL = -1,       /* invalid argument (null pointer, bad size or enum)       */
+    QDW_EDEVICE = -2,      /* a HIP call failed                                        */
+    QDW_ENOTUNITARY = -3,  /* a link is not in SU(3) to 1e-10 (qdw_create)             */
+    QDW_EBLOCK = -4,       /* SAP block size does not tile the lattice as required     */
+    QDW_ENOMEM = -5,       /* device allocation failed                                 */
+    QDW_EWORKSPACE = -6    /* workspace too small                                      */
+};
+
+typedef struct {
+    int T, L1, L2, L3; /* extents; all must be even, direction 0 is time            */
+    int bc_t;          /* -1 antiperiodic or +1 periodic in time; space is periodic  */
+} qdw_lattice;
+
+typedef struct qdw_op qdw_op; /* opaque: compressed links and clover, all precisions */
+
+/* Message of the last error on this thread ("" if none). */
+const char* qdw_last_error(void);
+
+/* Build an operator on the current device.
+ *  su3   (device) complex128 [V][4][3][3], canonical site order: SU(3) part of U_mu(x)
+ *  theta (device) float64 [V][4]: U(1) angle of U_mu(x)
+ *  m0, csw: bare mass and Sheikholeslami-Wohlert coefficient.
+ * Checks that every su3 matrix is unitary with unit determinant to 1e-10
+ * (QDW_ENOTUNITARY otherwise), then stores the two-row compressed links and builds the
+ * clover blocks A_+-(x) in FP64 (Sec. 1 names O(a)-improved Wilson fermions); FP32,
+ * FP16 and BF16 copies are derived by rounding to nearest even. The op owns its device
+ * memory (about 1.5 kB per site) until qdw_destroy. The input buffers may be freed
+ * once this call has returned (it synchronises `stream`). */
+int qdw_create(const qdw_lattice* lat, const double* su3, const double* theta, double m0,
+               double csw, void* stream, qdw_op** out);
+int qdw_destroy(qdw_op* op);
+
+/* Number of lattice sites, and bytes of one eo-SoA spinor field in precision `prec`. */
+long qdw_volume(const qdw_op* op);
+size_t qdw_field_bytes(const qdw_op* op, qdw_prec prec);
+
+/* Canonical complex128 [V][4][3] (device) <-> eo-SoA field in `prec` (device).
+ * Down-conversion rounds to nearest even. */
+int qdw_pack(const qdw_op* op, const double* canonical, void* eo, qdw_prec prec, void* stream);
+int qdw_unpack(const qdw_op* op, const void* eo, double* canonical, qdw_prec prec, void* stream);
+
+/* out = D in, and out = D^+ in = gamma_5 D gamma_5 in (the normal-equation solver of
+ * Sec. 2 applies both per step). `in` and `out` are distinct eo-SoA fields (device) of
+ * precision `prec`; the links and clover term are read in the same precision (FP16 and
+ * BF16 storage: binary32 arithmetic). Deterministic: no atomics. */
+int dw_apply(qdw_op* op, const void* in, void* out, qdw_prec prec, void* stream);
+int dw_dag_apply(qdw_op* op, const void* in, void* out, qdw_prec prec, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QDW_H */

@@ -59,6 +59,8 @@ def lib():
             f.argtypes = [P, ctypes.c_int, P, P, P, P]
         L.oracle_dw_blocks.argtypes = [P, P, ctypes.c_int, P, P, P, P]
         L.oracle_u3_links.argtypes = [ctypes.c_long, P, P, P]
+        L.oracle_dw_at.argtypes = [P, ctypes.c_int, P, ctypes.c_double, ctypes.c_double, P, P,
+                                   ctypes.c_long, P]
         _lib = L
     return _lib
 
@@ -130,6 +132,18 @@ class Operator:
 
     def normal(self, psi):
         return self.dw_dag(self.dw(psi))
+
+
+def dw_at_sites(dims, bc_t, u, m0, csw, psi, sites):
+    """(D psi)(x) for the listed lexicographic sites only ([n, 4, 3]); the clover term is
+    built at those sites from its definition. For sampling lattices too large for a full
+    oracle sweep."""
+    sites = np.ascontiguousarray(np.asarray(sites, dtype=np.int64))
+    psi = np.ascontiguousarray(psi, dtype=np.complex128)
+    out = np.zeros((len(sites), 4, 3), dtype=np.complex128)
+    lib().oracle_dw_at(_p(_dims(dims)), int(bc_t), _p(np.ascontiguousarray(u)), float(m0),
+                       float(csw), _p(psi), _p(sites), len(sites), _p(out))
+    return out
 
 
 def dense_matrix(op: Operator, which: str = "dw") -> np.ndarray:

@@ -335,3 +335,69 @@ void oracle_u3_links(long V, const double *su3_, const double *theta, double *u_
         for (int i = 0; i < 9; ++i) u[l * 9 + i] = ph * su3[l * 9 + i];
     }
 }
+
+/* (D psi)(x) at a list of sites only, with the clover term built at those sites: lets a
+ * test sample outputs of a lattice too large for a full oracle sweep. */
+void oracle_dw_at(const int d[4], int bc_t, const double *u_, double m0, double csw,
+                  const double *psi_, const long *sites, long n, double *out_ /* [n][12] */)
+{
+    init_gamma();
+    const cplx *u = (const cplx *)u_;
+    const cplx *psi = (const cplx *)psi_;
+    cplx *out = (cplx *)out_;
+    /* clover of one site: reuse oracle_clover on a one-site view is not possible (it
+     * needs neighbours), so rebuild A(x) here with the same definition */
+    static cplx sig[4][4][4][4];
+    for (int mu = 0; mu < 4; ++mu)
+        for (int nu = 0; nu < 4; ++nu)
+            for (int a = 0; a < 4; ++a)
+                for (int b = 0; b < 4; ++b) {
+                    cplx z = 0;
+                    for (int k = 0; k < 4; ++k)
+                        z += G[mu][a][k] * G[nu][k][b] - G[nu][a][k] * G[mu][k][b];
+                    sig[mu][nu][a][b] = 0.5 * I * z;
+                }
+    cplx Pm[4][4][4], Pp[4][4][4];
+    for (int mu = 0; mu < 4; ++mu)
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b) {
+                cplx one = (a == b) ? 1.0 : 0.0;
+                Pm[mu][a][b] = one - G[mu][a][b];
+                Pp[mu][a][b] = one + G[mu][a][b];
+            }
+    for (long k = 0; k < n; ++k) {
+        long x = sites[k];
+        cplx Ax[144];
+        for (int i = 0; i < 144; ++i) Ax[i] = 0;
+        for (int i = 0; i < 12; ++i) Ax[i * 12 + i] = 4.0 + m0;
+        for (int mu = 0; mu < 4; ++mu)
+            for (int nu = 0; nu < 4; ++nu) {
+                if (mu == nu) continue;
+                cplx q[9], F[9];
+                clover_leaves(d, u, x, mu, nu, q);
+                for (int i = 0; i < 3; ++i)
+                    for (int j = 0; j < 3; ++j)
+                        F[i * 3 + j] = (q[i * 3 + j] - conj(q[j * 3 + i])) / 8.0;
+                for (int a = 0; a < 4; ++a)
+                    for (int b = 0; b < 4; ++b) {
+                        cplx sab = sig[mu][nu][a][b];
+                        if (sab == 0) continue;
+                        for (int i = 0; i < 3; ++i)
+                            for (int j = 0; j < 3; ++j)
+                                Ax[(a * 3 + i) * 12 + (b * 3 + j)] +=
+                                    csw * 0.25 * I * sab * F[i * 3 + j];
+                    }
+            }
+        cplx *o = out + k * 12;
+        for (int i = 0; i < 12; ++i) {
+            cplx z = 0;
+            for (int j = 0; j < 12; ++j) z += Ax[i * 12 + j] * psi[x * 12 + j];
+            o[i] = z;
+        }
+        for (int mu = 0; mu < 4; ++mu) {
+            long xf = step(d, x, mu, +1), xb = step(d, x, mu, -1);
+            add_hop(o, -0.5 * bsign(d, bc_t, x, mu), link(u, x, mu), 0, Pm[mu], psi + xf * 12);
+            add_hop(o, -0.5 * bsign(d, bc_t, xb, mu), link(u, xb, mu), 1, Pp[mu], psi + xb * 12);
+        }
+    }
+}

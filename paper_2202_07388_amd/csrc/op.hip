@@ -1,0 +1,515 @@
+// op.hip -- operator set-up: link compression, clover term, precision copies, spinor
+// pack/unpack, and the error plumbing of the C ABI.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "qdw_host.h"
+
+using namespace qdw;
+
+namespace qdw {
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+}  // namespace qdw
+
+extern "C" const char* qdw_last_error(void) { return qdw::g_last_error.c_str(); }
+
+namespace {
+
+// ------------------------------------------------------------------ canonical links
+
+struct M3 { cx<double> a[9]; };
+
+__device__ inline M3 mat_mul(const M3& x, const M3& y)
+{
+    M3 z;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            cx<double> s = {0.0, 0.0};
+#pragma unroll
+            for (int k = 0; k < 3; ++k) s = s + x.a[i * 3 + k] * y.a[k * 3 + j];
+            z.a[i * 3 + j] = s;
+        }
+    return z;
+}
+
+// x * y^+
+__device__ inline M3 mat_mul_dag(const M3& x, const M3& y)
+{
+    M3 z;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            cx<double> s = {0.0, 0.0};
+#pragma unroll
+            for (int k = 0; k < 3; ++k) s = s + x.a[i * 3 + k] * conj_(y.a[j * 3 + k]);
+            z.a[i * 3 + j] = s;
+        }
+    return z;
+}
+
+__device__ inline M3 dag(const M3& x)
+{
+    M3 z;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) z.a[i * 3 + j] = conj_(x.a[j * 3 + i]);
+    return z;
+}
+
+// full U(3) link exp(i theta) V at lexicographic site `lex`, direction mu
+__device__ inline M3 link_u3(const double* su3, const double* theta, long lex, int mu)
+{
+    M3 m;
+    const double* p = su3 + ((lex * 4 + mu) * 9) * 2;
+    double s, c;
+    sincos(theta[lex * 4 + mu], &s, &c);
+    const cx<double> ph = {c, s};
+#pragma unroll
+    for (int k = 0; k < 9; ++k) m.a[k] = ph * cx<double>{p[2 * k], p[2 * k + 1]};
+    return m;
+}
+
+__device__ inline void lex_coords(const Geom& g, long lex, int x[4])
+{
+    long r = lex;
+    x[3] = (int)(r % g.L[3]); r /= g.L[3];
+    x[2] = (int)(r % g.L[2]); r /= g.L[2];
+    x[1] = (int)(r % g.L[1]); r /= g.L[1];
+    x[0] = (int)r;
+}
+
+__device__ inline long lex_of(const Geom& g, const int x[4])
+{
+    return ((long)(x[0] * g.L[1] + x[1]) * g.L[2] + x[2]) * g.L[3] + x[3];
+}
+
+__device__ inline long shifted(const Geom& g, const int x[4], int mu, int dmu, int nu, int dnu)
+{
+    int y[4] = {x[0], x[1], x[2], x[3]};
+    y[mu] = (y[mu] + dmu + g.L[mu]) % g.L[mu];
+    y[nu] = (y[nu] + dnu + g.L[nu]) % g.L[nu];
+    return lex_of(g, y);
+}
+
+// ------------------------------------------------------------------ unitarity check
+
+__global__ void unitarity_kernel(const double* su3, long nlinks, unsigned long long* worst)
+{
+    __shared__ double red[256];
+    const long l = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    double dev = 0.0;
+    if (l < nlinks) {
+        M3 m;
+        const double* p = su3 + l * 18;
+        bool finite = true;
+        for (int k = 0; k < 9; ++k) {
+            m.a[k] = {p[2 * k], p[2 * k + 1]};
+            finite = finite && isfinite(p[2 * k]) && isfinite(p[2 * k + 1]);
+        }
+        M3 e = mat_mul_dag(m, m);
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                cx<double> d = e.a[i * 3 + j];
+                if (i == j) d.re -= 1.0;
+                dev = fmax(dev, fmax(fabs(d.re), fabs(d.im)));
+            }
+        // det = row0 . (row1 x row2)
+        cx<double> c0 = m.a[4] * m.a[8] - m.a[5] * m.a[7];
+        cx<double> c1 = m.a[5] * m.a[6] - m.a[3] * m.a[8];
+        cx<double> c2 = m.a[3] * m.a[7] - m.a[4] * m.a[6];
+        cx<double> det = m.a[0] * c0 + m.a[1] * c1 + m.a[2] * c2;
+        dev = fmax(dev, fmax(fabs(det.re - 1.0), fabs(det.im)));
+        if (!finite) dev = 1e300;
+    }
+    red[threadIdx.x] = dev;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    // non-negative doubles order like their bit patterns
+    if (threadIdx.x == 0) atomicMax(worst, (unsigned long long)__double_as_longlong(red[0]));
+}
+
+// ------------------------------------------------------------------ link compression
+
+__global__ void pack_links_kernel(Geom g, const double* su3, const double* theta, void* l64,
+                                  void* t64, void* l32, void* t32, void* l16, void* lb16)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int par = blockIdx.y;
+    const int mu = blockIdx.z;
+    if (i >= g.Vh) return;
+    int x[4], lex;
+    eo_coords(g, par, i, x, lex);
+    const double* p = su3 + (((long)lex * 4 + mu) * 9) * 2;  // rows 0 and 1: 12 reals
+    const double th = theta[(long)lex * 4 + mu];
+    const long row = (long)(par * 4 + mu);
+    double r[12];
+    for (int k = 0; k < 12; ++k) r[k] = p[k];
+    // FP64: 6 chunks of one complex each
+    for (int k = 0; k < 6; ++k) {
+        double2 v = {r[2 * k], r[2 * k + 1]};
+        ((double2*)l64)[(row * 6 + k) * g.Vh + i] = v;
+    }
+    ((double*)t64)[row * g.Vh + i] = th;
+    // FP32: 3 chunks of two complex each
+    for (int k = 0; k < 3; ++k) {
+        float4 v = {(float)r[4 * k], (float)r[4 * k + 1], (float)r[4 * k + 2], (float)r[4 * k + 3]};
+        ((float4*)l32)[(row * 3 + k) * g.Vh + i] = v;
+    }
+    ((float*)t32)[row * g.Vh + i] = (float)th;
+    // FP16 / BF16: 12 reals, then cos and sin of the angle, then two zeros
+    double s, c;
+    sincos(th, &s, &c);
+    double e[16];
+    for (int k = 0; k < 12; ++k) e[k] = r[k];
+    e[12] = c; e[13] = s; e[14] = 0.0; e[15] = 0.0;
+    _Float16* h = (_Float16*)l16;
+    uint16_t* b = (uint16_t*)lb16;
+    for (int k = 0; k < 2; ++k)
+        for (int j = 0; j < 8; ++j) {
+            const long at = ((row * 2 + k) * g.Vh + i) * 8 + j;
+            h[at] = (_Float16)e[8 * k + j];
+            b[at] = float_to_bf16((float)e[8 * k + j]);
+        }
+}
+
+// ------------------------------------------------------------------ clover term
+
+// Fhat_{mu nu}(x) = (Q - Q^+)/8, Q = sum of the four counter-clockwise leaves at x.
+__device__ M3 field_strength(const Geom& g, const double* su3, const double* theta,
+                             const int x[4], long lex, int mu, int nu)
+{
+    const long xpm = shifted(g, x, mu, 1, nu, 0), xpn = shifted(g, x, mu, 0, nu, 1);
+    const long xmm = shifted(g, x, mu, -1, nu, 0), xmn = shifted(g, x, mu, 0, nu, -1);
+    const long xmm_pn = shifted(g, x, mu, -1, nu, 1), xmm_mn = shifted(g, x, mu, -1, nu, -1);
+    const long xmn_pm = shifted(g, x, mu, 1, nu, -1);
+    const M3 umu = link_u3(su3, theta, lex, mu), unu = link_u3(su3, theta, lex, nu);
+    const M3 umu_mm = link_u3(su3, theta, xmm, mu), unu_mm = link_u3(su3, theta, xmm, nu);
+    const M3 umu_mn = link_u3(su3, theta, xmn, mu), unu_mn = link_u3(su3, theta, xmn, nu);
+    // (x, x+mu, x+mu+nu, x+nu)
+    M3 q = mat_mul_dag(mat_mul_dag(mat_mul(umu, link_u3(su3, theta, xpm, nu)),
+                                   link_u3(su3, theta, xpn, mu)), unu);
+    // (x, x+nu, x-mu+nu, x-mu)
+    M3 t = mat_mul(mat_mul_dag(mat_mul_dag(unu, link_u3(su3, theta, xmm_pn, mu)), unu_mm), umu_mm);
+    for (int k = 0; k < 9; ++k) q.a[k] = q.a[k] + t.a[k];
+    // (x, x-mu, x-mu-nu, x-nu)
+    t = mat_mul(mat_mul(mat_mul_dag(dag(umu_mm), link_u3(su3, theta, xmm_mn, nu)),
+                        link_u3(su3, theta, xmm_mn, mu)), unu_mn);
+    for (int k = 0; k < 9; ++k) q.a[k] = q.a[k] + t.a[k];
+    // (x, x-nu, x-nu+mu, x+mu)
+    t = mat_mul_dag(mat_mul(mat_mul(dag(unu_mn), umu_mn), link_u3(su3, theta, xmn_pm, nu)), umu);
+    for (int k = 0; k < 9; ++k) q.a[k] = q.a[k] + t.a[k];
+    M3 f;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            cx<double> a = q.a[i * 3 + j], b = conj_(q.a[j * 3 + i]);
+            f.a[i * 3 + j] = scale(a - b, 0.125);
+        }
+    return f;
+}
+
+// A_+-(x) = (4 + m0) + (i csw/2) [[E3, E1 - i E2], [E1 + i E2, -E3]] with
+// E1 = +-F01 - F23, E2 = +-F02 + F13, E3 = +-F03 - F12 (chiral basis:
+// sigma_0k = diag(s_k, -s_k), sigma_12 = -s_3, sigma_13 = s_2, sigma_23 = -s_1).
+__global__ void clover_kernel(Geom g, const double* su3, const double* theta, double m0,
+                              double csw, double2* out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int par = blockIdx.y;
+    if (i >= g.Vh) return;
+    int x[4], lex;
+    eo_coords(g, par, i, x, lex);
+    const M3 f01 = field_strength(g, su3, theta, x, lex, 0, 1);
+    const M3 f02 = field_strength(g, su3, theta, x, lex, 0, 2);
+    const M3 f03 = field_strength(g, su3, theta, x, lex, 0, 3);
+    const M3 f12 = field_strength(g, su3, theta, x, lex, 1, 2);
+    const M3 f13 = field_strength(g, su3, theta, x, lex, 1, 3);
+    const M3 f23 = field_strength(g, su3, theta, x, lex, 2, 3);
+    double reals[72];
+    for (int blk = 0; blk < 2; ++blk) {
+        const double s = blk == 0 ? 1.0 : -1.0;
+        cx<double> S[2][2][9];
+        for (int k = 0; k < 9; ++k) {
+            cx<double> e1 = scale(f01.a[k], s) - f23.a[k];
+            cx<double> e2 = scale(f02.a[k], s) + f13.a[k];
+            cx<double> e3 = scale(f03.a[k], s) - f12.a[k];
+            S[0][0][k] = e3;
+            S[0][1][k] = e1 - times_i(e2);
+            S[1][0][k] = e1 + times_i(e2);
+            S[1][1][k] = scale(e3, -1.0);
+        }
+        // entry (r, c) of the 6x6 block, r = a*3 + i, c = b*3 + j
+        auto entry = [&](int r, int c) {
+            const int a = r / 3, ii = r % 3, b = c / 3, jj = c % 3;
+            cx<double> v = scale(times_i(S[a][b][ii * 3 + jj]), 0.5 * csw);
+            if (r == c) v.re += 4.0 + m0;
+            return v;
+        };
+        double* o = reals + 36 * blk;
+        for (int r = 0; r < 6; ++r) o[r] = entry(r, r).re;
+        int n = 0;
+        for (int r = 0; r < 6; ++r)
+            for (int c = r + 1; c < 6; ++c) {
+                cx<double> v = entry(r, c);
+                o[6 + 2 * n] = v.re;
+                o[6 + 2 * n + 1] = v.im;
+                ++n;
+            }
+    }
+    for (int k = 0; k < 36; ++k)
+        out[((long)par * 36 + k) * g.Vh + i] = double2{reals[2 * k], reals[2 * k + 1]};
+}
+
+// FP64 eo-SoA array of `nr` reals per site -> lower precision copies
+__global__ void convert_site_reals(Geom g, int nr, const double* src, float* f32, _Float16* f16,
+                                   uint16_t* b16)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int par = blockIdx.y;
+    if (i >= g.Vh) return;
+    for (int q = 0; q < nr; ++q) {
+        const double v = src[(((long)par * (nr / 2) + q / 2) * g.Vh + i) * 2 + q % 2];
+        f32[(((long)par * (nr / 4) + q / 4) * g.Vh + i) * 4 + q % 4] = (float)v;
+        const long a16 = (((long)par * (nr / 8) + q / 8) * g.Vh + i) * 8 + q % 8;
+        f16[a16] = (_Float16)v;
+        b16[a16] = float_to_bf16((float)v);
+    }
+}
+
+// ------------------------------------------------------------------ spinor pack
+
+template <int P>
+__global__ void pack_kernel(Geom g, const double* can, void* eo)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int par = blockIdx.y;
+    if (i >= g.Vh) return;
+    int x[4], lex;
+    eo_coords(g, par, i, x, lex);
+    using R = typename Traits<P>::real;
+    cx<R> s[12];
+    const double* p = can + (long)lex * 24;
+    for (int k = 0; k < 12; ++k) s[k] = {(R)p[2 * k], (R)p[2 * k + 1]};
+    store_spinor<P>(eo, g.Vh, par, i, s);
+}
+
+template <int P>
+__global__ void unpack_kernel(Geom g, const void* eo, double* can)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int par = blockIdx.y;
+    if (i >= g.Vh) return;
+    int x[4], lex;
+    eo_coords(g, par, i, x, lex);
+    using R = typename Traits<P>::real;
+    cx<R> s[12];
+    load_spinor<P>(eo, g.Vh, par, i, s);
+    double* p = can + (long)lex * 24;
+    for (int k = 0; k < 12; ++k) {
+        p[2 * k] = (double)s[k].re;
+        p[2 * k + 1] = (double)s[k].im;
+    }
+}
+
+// FP16 pack rounds each double once, straight to binary16 (no binary32 detour)
+template <>
+__global__ void pack_kernel<F16S>(Geom g, const double* can, void* eo)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int par = blockIdx.y;
+    if (i >= g.Vh) return;
+    int x[4], lex;
+    eo_coords(g, par, i, x, lex);
+    const double* p = can + (long)lex * 24;
+    _Float16* h = (_Float16*)eo;
+    for (int q = 0; q < 24; ++q)
+        h[(((long)par * 3 + q / 8) * g.Vh + i) * 8 + q % 8] = (_Float16)p[q];
+}
+
+// FP64 pack straight from canonical doubles (no float detour)
+template <>
+__global__ void pack_kernel<F64>(Geom g, const double* can, void* eo)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int par = blockIdx.y;
+    if (i >= g.Vh) return;
+    int x[4], lex;
+    eo_coords(g, par, i, x, lex);
+    const double* p = can + (long)lex * 24;
+    for (int k = 0; k < 12; ++k)
+        ((double2*)eo)[((long)par * 12 + k) * g.Vh + i] = double2{p[2 * k], p[2 * k + 1]};
+}
+
+void free_op(qdw_op* op)
+{
+    for (int p = 0; p < 4; ++p) {
+        if (op->links[p]) (void)hipFree(op->links[p]);
+        if (op->theta[p]) (void)hipFree(op->theta[p]);
+        if (op->clover[p]) (void)hipFree(op->clover[p]);
+    }
+    if (op->partials) (void)hipFree(op->partials);
+    if (op->scalars) (void)hipFree(op->scalars);
+    if (op->host_scalars) (void)hipHostFree(op->host_scalars);
+    delete op;
+}
+
+}  // namespace
+
+extern "C" int qdw_create(const qdw_lattice* lat, const double* su3, const double* theta,
+                          double m0, double csw, void* stream, qdw_op** out)
+{
+    QDW_CHECK(lat && su3 && theta && out, QDW_EINVAL, "qdw_create: null argument");
+    *out = nullptr;
+    const int L[4] = {lat->T, lat->L1, lat->L2, lat->L3};
+    for (int mu = 0; mu < 4; ++mu)
+        QDW_CHECK(L[mu] >= 2 && L[mu] % 2 == 0, QDW_EINVAL,
+                  "qdw_create: every lattice extent must be even and >= 2");
+    QDW_CHECK(lat->bc_t == 1 || lat->bc_t == -1, QDW_EINVAL, "qdw_create: bc_t must be +1 or -1");
+    const long V = (long)L[0] * L[1] * L[2] * L[3];
+    QDW_CHECK(V <= (1L << 30), QDW_EINVAL, "qdw_create: volume above 2^30 sites");
+    hipStream_t st = (hipStream_t)stream;
+
+    qdw_op* op = new qdw_op();
+    std::memset(op, 0, sizeof(*op));
+    Geom& g = op->g;
+    for (int mu = 0; mu < 4; ++mu) g.L[mu] = L[mu];
+    g.stride[3] = 1;
+    g.stride[2] = L[3];
+    g.stride[1] = L[3] * L[2];
+    g.stride[0] = L[3] * L[2] * L[1];
+    g.V = (int)V;
+    g.Vh = (int)(V / 2);
+    g.bc_t = lat->bc_t;
+    op->m0 = m0;
+    op->csw = csw;
+    (void)hipGetDevice(&op->device);
+
+    auto fail = [&](int code, const std::string& msg) {
+        set_error(msg);
+        free_op(op);
+        return code;
+    };
+#define CREATE_HIP(call)                                                               \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(e_ == hipErrorOutOfMemory ? QDW_ENOMEM : QDW_EDEVICE,          \
+                        std::string(#call) + ": " + hipGetErrorString(e_));            \
+    } while (0)
+
+    // 1. unitarity of the SU(3) parts
+    unsigned long long* worst = nullptr;
+    CREATE_HIP(hipMallocAsync((void**)&worst, sizeof(unsigned long long), st));
+    CREATE_HIP(hipMemsetAsync(worst, 0, sizeof(unsigned long long), st));
+    const long nlinks = V * 4;
+    unitarity_kernel<<<(unsigned)((nlinks + 255) / 256), 256, 0, st>>>(su3, nlinks, worst);
+    CREATE_HIP(hipGetLastError());
+    unsigned long long wbits = 0;
+    CREATE_HIP(hipMemcpyAsync(&wbits, worst, sizeof(wbits), hipMemcpyDeviceToHost, st));
+    CREATE_HIP(hipStreamSynchronize(st));
+    CREATE_HIP(hipFreeAsync(worst, st));
+    double wdev;
+    std::memcpy(&wdev, &wbits, sizeof(wdev));
+    if (!(wdev <= 1e-10))
+        return fail(QDW_ENOTUNITARY, "qdw_create: a link deviates from SU(3) by " +
+                                         std::to_string(wdev));
+
+    // 2. compressed links in every precision
+    const size_t nl = (size_t)g.Vh * 2 * 4;  // links per array (both parities, 4 dirs)
+    CREATE_HIP(hipMalloc(&op->links[F64], nl * 6 * 16));
+    CREATE_HIP(hipMalloc(&op->theta[F64], nl * 8));
+    CREATE_HIP(hipMalloc(&op->links[F32], nl * 3 * 16));
+    CREATE_HIP(hipMalloc(&op->theta[F32], nl * 4));
+    CREATE_HIP(hipMalloc(&op->links[F16S], nl * 2 * 16));
+    CREATE_HIP(hipMalloc(&op->links[BF16S], nl * 2 * 16));
+    dim3 gl((g.Vh + 255) / 256, 2, 4);
+    pack_links_kernel<<<gl, 256, 0, st>>>(g, su3, theta, op->links[F64], op->theta[F64],
+                                          op->links[F32], op->theta[F32], op->links[F16S],
+                                          op->links[BF16S]);
+    CREATE_HIP(hipGetLastError());
+
+    // 3. clover blocks (FP64) and their lower-precision copies
+    const size_t ns = (size_t)V;
+    CREATE_HIP(hipMalloc(&op->clover[F64], ns * 72 * 8));
+    CREATE_HIP(hipMalloc(&op->clover[F32], ns * 72 * 4));
+    CREATE_HIP(hipMalloc(&op->clover[F16S], ns * 72 * 2));
+    CREATE_HIP(hipMalloc(&op->clover[BF16S], ns * 72 * 2));
+    dim3 gs((g.Vh + 127) / 128, 2);
+    clover_kernel<<<gs, 128, 0, st>>>(g, su3, theta, m0, csw, (double2*)op->clover[F64]);
+    CREATE_HIP(hipGetLastError());
+    convert_site_reals<<<gs, 128, 0, st>>>(g, 72, (const double*)op->clover[F64],
+                                           (float*)op->clover[F32], (_Float16*)op->clover[F16S],
+                                           (uint16_t*)op->clover[BF16S]);
+    CREATE_HIP(hipGetLastError());
+
+    // 4. reduction scratch
+    CREATE_HIP(hipMalloc((void**)&op->partials, sizeof(double) * kMaxPartials * kMaxScalars));
+    CREATE_HIP(hipMalloc((void**)&op->scalars, sizeof(double) * kMaxScalars));
+    CREATE_HIP(hipHostMalloc((void**)&op->host_scalars, sizeof(double) * kMaxScalars));
+    CREATE_HIP(hipStreamSynchronize(st));
+#undef CREATE_HIP
+    *out = op;
+    return QDW_OK;
+}
+
+extern "C" int qdw_destroy(qdw_op* op)
+{
+    if (!op) return QDW_OK;
+    (void)hipDeviceSynchronize();
+    free_op(op);
+    return QDW_OK;
+}
+
+extern "C" long qdw_volume(const qdw_op* op) { return op ? (long)op->g.V : 0; }
+
+extern "C" size_t qdw_field_bytes(const qdw_op* op, qdw_prec prec)
+{
+    if (!op || prec < QDW_F64 || prec > QDW_BF16S) return 0;
+    return spinor_bytes(op->g, prec);
+}
+
+extern "C" int qdw_pack(const qdw_op* op, const double* canonical, void* eo, qdw_prec prec,
+                        void* stream)
+{
+    QDW_CHECK(op && canonical && eo, QDW_EINVAL, "qdw_pack: null argument");
+    const Geom& g = op->g;
+    dim3 gr((g.Vh + 255) / 256, 2);
+    hipStream_t st = (hipStream_t)stream;
+    switch (prec) {
+    case QDW_F64: pack_kernel<F64><<<gr, 256, 0, st>>>(g, canonical, eo); break;
+    case QDW_F32: pack_kernel<F32><<<gr, 256, 0, st>>>(g, canonical, eo); break;
+    case QDW_F16S: pack_kernel<F16S><<<gr, 256, 0, st>>>(g, canonical, eo); break;
+    case QDW_BF16S: pack_kernel<BF16S><<<gr, 256, 0, st>>>(g, canonical, eo); break;
+    default: QDW_CHECK(false, QDW_EINVAL, "qdw_pack: bad precision");
+    }
+    QDW_LAUNCH_CHECK();
+    return QDW_OK;
+}
+
+extern "C" int qdw_unpack(const qdw_op* op, const void* eo, double* canonical, qdw_prec prec,
+                          void* stream)
+{
+    QDW_CHECK(op && canonical && eo, QDW_EINVAL, "qdw_unpack: null argument");
+    const Geom& g = op->g;
+    dim3 gr((g.Vh + 255) / 256, 2);
+    hipStream_t st = (hipStream_t)stream;
+    switch (prec) {
+    case QDW_F64: unpack_kernel<F64><<<gr, 256, 0, st>>>(g, eo, canonical); break;
+    case QDW_F32: unpack_kernel<F32><<<gr, 256, 0, st>>>(g, eo, canonical); break;
+    case QDW_F16S: unpack_kernel<F16S><<<gr, 256, 0, st>>>(g, eo, canonical); break;
+    case QDW_BF16S: unpack_kernel<BF16S><<<gr, 256, 0, st>>>(g, eo, canonical); break;
+    default: QDW_CHECK(false, QDW_EINVAL, "qdw_unpack: bad precision");
+    }
+    QDW_LAUNCH_CHECK();
+    return QDW_OK;
+}

@@ -1,0 +1,58 @@
+// qdw_host.h -- host-side state of an operator and error plumbing of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/qdw.h"
+#include "qdw_internal.h"
+
+struct qdw_op {
+    qdw::Geom g;
+    double m0, csw;
+    int device;
+    // per precision (index = qdw::Prec): compressed links, U(1) angles (F64/F32 only),
+    // clover blocks
+    void* links[4];
+    void* theta[4];
+    void* clover[4];
+    // reduction scratch: per-workgroup partial sums and the final scalars
+    double* partials;      // device, kMaxPartials * kMaxScalars doubles
+    double* scalars;       // device, kMaxScalars doubles
+    double* host_scalars;  // pinned host, kMaxScalars doubles
+};
+
+namespace qdw {
+
+constexpr int kMaxPartials = 2048;  // workgroups of a reduction launch
+constexpr int kMaxScalars = 64;     // doubles produced by one fused reduction
+
+void set_error(const std::string& msg);
+
+inline size_t spinor_bytes(const Geom& g, int prec)
+{
+    const size_t r = prec == F64 ? 8 : prec == F32 ? 4 : 2;
+    return (size_t)g.V * 24 * r;
+}
+
+}  // namespace qdw
+
+#define QDW_HIP(call)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            qdw::set_error(std::string(#call) + ": " + hipGetErrorString(e_));         \
+            return QDW_EDEVICE;                                                        \
+        }                                                                              \
+    } while (0)
+
+#define QDW_CHECK(cond, code, msg)                                                     \
+    do {                                                                               \
+        if (!(cond)) {                                                                 \
+            qdw::set_error(msg);                                                       \
+            return (code);                                                             \
+        }                                                                              \
+    } while (0)
+
+#define QDW_LAUNCH_CHECK() QDW_HIP(hipGetLastError())

@@ -1,0 +1,220 @@
+// qdw_internal.h -- device-side building blocks shared by the HIP kernels of libqdw.
+//
+// Layout ("eo-SoA"): every per-site field is split by site parity (even sites first,
+// as in the paper's even-odd ordered operator, Sec. 3 / Fig. 3 left) and stored as
+// [parity][chunk][Vh] where a chunk is 16 bytes of one site's data. Consecutive lanes of
+// a wavefront therefore read consecutive 16-byte chunks: one fully coalesced 1 KiB
+// transaction per wave per chunk.
+//
+//   spinor  24 reals/site  (12 complex, index spin*3 + colour)
+//           F64: 12 chunks (1 complex each), F32: 6 (2 complex), F16/BF16: 3 (4 complex)
+//   link    rows 0 and 1 of the SU(3) part (6 complex) + U(1) phase, per direction mu
+//           F64: 6 chunks + angle array, F32: 3 chunks + angle array,
+//           F16/BF16: 2 chunks = 6 complex + (cos, sin) of the angle
+//           The third row is rebuilt in registers as conj(row0 x row1).
+//   clover  2 chirality blocks x 36 reals (6 real diagonal, 15 complex upper triangle,
+//           row-major), (4 + m0) included. F64: 36 chunks, F32: 18, F16/BF16: 9.
+//
+// The even-odd index of a site is lex/2 with lex = ((x0*L1 + x1)*L2 + x2)*L3 + x3;
+// this is a bijection per parity because L3 is even.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+namespace qdw {
+
+enum Prec { F64 = 0, F32 = 1, F16S = 2, BF16S = 3 };
+
+struct Geom {
+    int L[4];      // T, L1, L2, L3 (direction 0 is time)
+    int stride[4]; // lexicographic strides
+    int V, Vh;
+    int bc_t;      // -1 antiperiodic, +1 periodic in time
+};
+
+// ---------------------------------------------------------------- scalar types
+
+struct bf16_t { uint16_t bits; };
+
+__host__ __device__ inline float bf16_to_float(uint16_t b)
+{
+    union { uint32_t u; float f; } v;
+    v.u = ((uint32_t)b) << 16;
+    return v.f;
+}
+
+// round to nearest even; NaN stays NaN
+__host__ __device__ inline uint16_t float_to_bf16(float f)
+{
+    union { uint32_t u; float f; } v;
+    v.f = f;
+    if ((v.u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((v.u >> 16) | 0x40);
+    uint32_t lsb = (v.u >> 16) & 1u;
+    v.u += 0x7fffu + lsb;
+    return (uint16_t)(v.u >> 16);
+}
+
+template <int P> struct Traits;
+template <> struct Traits<F64> {
+    using real = double;     // arithmetic type
+    using store = double;    // storage scalar
+    static constexpr int SPIN_CHUNKS = 12, LINK_CHUNKS = 6, CLOVER_CHUNKS = 36;
+    static constexpr int PER_CHUNK = 2;   // reals per 16-byte chunk
+};
+template <> struct Traits<F32> {
+    using real = float;
+    using store = float;
+    static constexpr int SPIN_CHUNKS = 6, LINK_CHUNKS = 3, CLOVER_CHUNKS = 18;
+    static constexpr int PER_CHUNK = 4;
+};
+template <> struct Traits<F16S> {
+    using real = float;
+    using store = _Float16;
+    static constexpr int SPIN_CHUNKS = 3, LINK_CHUNKS = 2, CLOVER_CHUNKS = 9;
+    static constexpr int PER_CHUNK = 8;
+};
+template <> struct Traits<BF16S> {
+    using real = float;
+    using store = uint16_t;
+    static constexpr int SPIN_CHUNKS = 3, LINK_CHUNKS = 2, CLOVER_CHUNKS = 9;
+    static constexpr int PER_CHUNK = 8;
+};
+
+template <int P> __device__ __forceinline__ typename Traits<P>::real to_real(typename Traits<P>::store s);
+template <> __device__ __forceinline__ double to_real<F64>(double s) { return s; }
+template <> __device__ __forceinline__ float to_real<F32>(float s) { return s; }
+template <> __device__ __forceinline__ float to_real<F16S>(_Float16 s) { return (float)s; }
+template <> __device__ __forceinline__ float to_real<BF16S>(uint16_t s) { return bf16_to_float(s); }
+
+template <int P> __device__ __forceinline__ typename Traits<P>::store to_store(typename Traits<P>::real r);
+template <> __device__ __forceinline__ double to_store<F64>(double r) { return r; }
+template <> __device__ __forceinline__ float to_store<F32>(float r) { return r; }
+template <> __device__ __forceinline__ _Float16 to_store<F16S>(float r) { return (_Float16)r; }
+template <> __device__ __forceinline__ uint16_t to_store<BF16S>(float r) { return float_to_bf16(r); }
+
+// One 16-byte chunk, viewed as PER_CHUNK storage scalars.
+template <int P> struct Chunk {
+    typename Traits<P>::store v[Traits<P>::PER_CHUNK];
+};
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <int P>
+__device__ __forceinline__ Chunk<P> load_chunk(const void* base, long idx)
+{
+    const u32x4 raw = __builtin_nontemporal_load((const u32x4*)base + idx);
+    Chunk<P> c;
+    __builtin_memcpy(&c, &raw, 16);
+    return c;
+}
+
+template <int P>
+__device__ __forceinline__ Chunk<P> load_chunk_cached(const void* base, long idx)
+{
+    const u32x4 raw = ((const u32x4*)base)[idx];
+    Chunk<P> c;
+    __builtin_memcpy(&c, &raw, 16);
+    return c;
+}
+
+template <int P>
+__device__ __forceinline__ void store_chunk(void* base, long idx, const Chunk<P>& c)
+{
+    u32x4 raw;
+    __builtin_memcpy(&raw, &c, 16);
+    __builtin_nontemporal_store(raw, (u32x4*)base + idx);
+}
+
+// ---------------------------------------------------------------- complex helpers
+
+template <typename R> struct cx { R re, im; };
+
+template <typename R> __device__ __forceinline__ cx<R> mk(R a, R b) { return {a, b}; }
+template <typename R> __device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename R> __device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename R> __device__ __forceinline__ cx<R> operator*(cx<R> a, cx<R> b)
+{
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename R> __device__ __forceinline__ cx<R> cmul_conj(cx<R> a, cx<R> b)   // conj(a) * b
+{
+    return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+template <typename R> __device__ __forceinline__ cx<R> conj_(cx<R> a) { return {a.re, -a.im}; }
+template <typename R> __device__ __forceinline__ cx<R> times_i(cx<R> a) { return {-a.im, a.re}; }
+template <typename R> __device__ __forceinline__ cx<R> scale(cx<R> a, R s) { return {a.re * s, a.im * s}; }
+
+// ---------------------------------------------------------------- field access
+
+// spinor of one site (12 complex) from an eo-SoA field
+template <int P>
+__device__ __forceinline__ void load_spinor(const void* f, int Vh, int par, int i,
+                                            cx<typename Traits<P>::real> s[12])
+{
+    using T = Traits<P>;
+    const long base = (long)par * T::SPIN_CHUNKS * Vh + i;
+#pragma unroll
+    for (int k = 0; k < T::SPIN_CHUNKS; ++k) {
+        Chunk<P> c = load_chunk_cached<P>(f, base + (long)k * Vh);
+#pragma unroll
+        for (int j = 0; j < T::PER_CHUNK / 2; ++j)
+            s[k * (T::PER_CHUNK / 2) + j] = {to_real<P>(c.v[2 * j]), to_real<P>(c.v[2 * j + 1])};
+    }
+}
+
+template <int P>
+__device__ __forceinline__ void store_spinor(void* f, int Vh, int par, int i,
+                                             const cx<typename Traits<P>::real> s[12])
+{
+    using T = Traits<P>;
+    const long base = (long)par * T::SPIN_CHUNKS * Vh + i;
+#pragma unroll
+    for (int k = 0; k < T::SPIN_CHUNKS; ++k) {
+        Chunk<P> c;
+#pragma unroll
+        for (int j = 0; j < T::PER_CHUNK / 2; ++j) {
+            c.v[2 * j] = to_store<P>(s[k * (T::PER_CHUNK / 2) + j].re);
+            c.v[2 * j + 1] = to_store<P>(s[k * (T::PER_CHUNK / 2) + j].im);
+        }
+        store_chunk<P>(f, base + (long)k * Vh, c);
+    }
+}
+
+// site coordinates of (parity, eo index)
+__device__ __forceinline__ void eo_coords(const Geom& g, int par, int i, int x[4], int& lex)
+{
+    int l = 2 * i;
+    int r = l / g.L[3];
+    x[3] = l - r * g.L[3];
+    int r2 = r / g.L[2];
+    x[2] = r - r2 * g.L[2];
+    int r3 = r2 / g.L[1];
+    x[1] = r2 - r3 * g.L[1];
+    x[0] = r3;
+    if (((x[0] + x[1] + x[2] + x[3]) & 1) != par) { x[3] += 1; l += 1; }
+    lex = l;
+}
+
+// lexicographic index of the neighbour x +- mu, given x's coordinates and lex index
+__device__ __forceinline__ int lex_fwd(const Geom& g, const int x[4], int lex, int mu)
+{
+    return (x[mu] == g.L[mu] - 1) ? lex - (g.L[mu] - 1) * g.stride[mu] : lex + g.stride[mu];
+}
+__device__ __forceinline__ int lex_bwd(const Geom& g, const int x[4], int lex, int mu)
+{
+    return (x[mu] == 0) ? lex + (g.L[mu] - 1) * g.stride[mu] : lex - g.stride[mu];
+}
+
+// XCD-aware block mapping: hardware hands out workgroups round-robin over the 8 XCDs;
+// remap so that each XCD walks one contiguous range of tiles and neighbouring tiles
+// share that XCD's L2.
+__device__ __forceinline__ int xcd_tile(int bid, int nblk)
+{
+    const int q = nblk >> 3, r = nblk & 7;
+    const int x = bid & 7, k = bid >> 3;
+    return x * q + (x < r ? x : r) + k;
+}
+
+}  // namespace qdw

@@ -1,0 +1,180 @@
+"""Python binding of libqdw (ctypes). Argument marshalling only: every step of the
+operator and the solvers runs in the HIP kernels of ``libqdw.so``.
+
+PyTorch supplies device memory and the current stream; fields are plain byte tensors
+holding the library's eo-SoA layout. The binding fails loudly when the library is
+missing or when no GPU is present: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqdw.so")
+
+PREC = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
+REAL_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
+
+# machine epsilon 2^-m of the storage formats (paper Table 1)
+EPS = {"f64": 2.0 ** -52, "f32": 2.0 ** -23, "f16": 2.0 ** -10, "bf16": 2.0 ** -7}
+
+
+class QdwError(RuntimeError):
+    pass
+
+
+class Lattice(ctypes.Structure):
+    _fields_ = [("T", ctypes.c_int), ("L1", ctypes.c_int), ("L2", ctypes.c_int),
+                ("L3", ctypes.c_int), ("bc_t", ctypes.c_int)]
+
+
+_lib = None
+_P = ctypes.c_void_p
+
+
+def load():
+    """Load libqdw.so and declare argument types of every exported entry point."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise QdwError("libqdw.so is not built (run __graft_entry__.build() or "
+                       "python -m paper_2202_07388_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    L.qdw_last_error.restype = ctypes.c_char_p
+    L.qdw_create.argtypes = [ctypes.POINTER(Lattice), _P, _P, ctypes.c_double,
+                             ctypes.c_double, _P, ctypes.POINTER(_P)]
+    L.qdw_destroy.argtypes = [_P]
+    L.qdw_volume.argtypes = [_P]
+    L.qdw_volume.restype = ctypes.c_long
+    L.qdw_field_bytes.argtypes = [_P, ctypes.c_int]
+    L.qdw_field_bytes.restype = ctypes.c_size_t
+    for f in (L.qdw_pack, L.qdw_unpack):
+        f.argtypes = [_P, _P, _P, ctypes.c_int, _P]
+    for f in (L.dw_apply, L.dw_dag_apply):
+        f.argtypes = [_P, _P, _P, ctypes.c_int, _P]
+    _declare_solvers(L)
+    _lib = L
+    return L
+
+
+def _declare_solvers(L):
+    """Solver entry points are declared when the library exports them."""
+    for name, args, res in _OPTIONAL:
+        if hasattr(L, name):
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+
+
+_OPTIONAL: list = []
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        msg = load().qdw_last_error().decode(errors="replace")
+        raise QdwError("%s failed (code %d): %s" % (what, rc, msg))
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise QdwError("libqdw needs a HIP GPU; none is visible")
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    if not t.is_cuda:
+        raise QdwError("expected a device tensor")
+    if not t.is_contiguous():
+        raise QdwError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Op:
+    """A Wilson-clover operator resident on the current GPU (qdw_create)."""
+
+    def __init__(self, dims, su3, theta, m0: float, csw: float, bc_t: int = -1):
+        torch = _torch()
+        L = load()
+        self.dims = tuple(int(v) for v in dims)
+        self.V = int(np.prod(self.dims))
+        self.m0, self.csw, self.bc_t = float(m0), float(csw), int(bc_t)
+        dev = torch.device("cuda", torch.cuda.current_device())
+        su3_t = torch.as_tensor(np.ascontiguousarray(su3, dtype=np.complex128)
+                                if isinstance(su3, np.ndarray) else su3)
+        th_t = torch.as_tensor(np.ascontiguousarray(theta, dtype=np.float64)
+                               if isinstance(theta, np.ndarray) else theta)
+        su3_d = torch.view_as_real(su3_t.to(dev).contiguous()).contiguous()
+        th_d = th_t.to(dev, dtype=torch.float64).contiguous()
+        if su3_d.numel() != self.V * 4 * 9 * 2 or th_d.numel() != self.V * 4:
+            raise QdwError("gauge field shape does not match the lattice")
+        lat = Lattice(*self.dims, self.bc_t)
+        h = _P()
+        _check(L.qdw_create(ctypes.byref(lat), _ptr(su3_d), _ptr(th_d), self.m0, self.csw,
+                            _stream(), ctypes.byref(h)), "qdw_create")
+        self._h = h
+        self.device = dev
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().qdw_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def field_bytes(self, prec: str = "f64") -> int:
+        return int(load().qdw_field_bytes(self._h, PREC[prec]))
+
+    def new_field(self, prec: str = "f64", zero: bool = True):
+        torch = _torch()
+        n = self.field_bytes(prec)
+        t = torch.zeros(n, dtype=torch.uint8, device=self.device) if zero else \
+            torch.empty(n, dtype=torch.uint8, device=self.device)
+        return t
+
+    def pack(self, canonical, prec: str = "f64", out=None):
+        """canonical complex128 [V, 4, 3] (numpy or tensor) -> eo-SoA byte tensor."""
+        torch = _torch()
+        c = torch.as_tensor(canonical).to(self.device, dtype=torch.complex128).contiguous()
+        if c.numel() != self.V * 12:
+            raise QdwError("spinor shape does not match the lattice")
+        out = self.new_field(prec, zero=False) if out is None else out
+        _check(load().qdw_pack(self._h, _ptr(torch.view_as_real(c)), _ptr(out), PREC[prec],
+                               _stream()), "qdw_pack")
+        return out
+
+    def unpack(self, eo, prec: str = "f64"):
+        """eo-SoA byte tensor -> canonical complex128 [V, 4, 3] device tensor."""
+        torch = _torch()
+        out = torch.empty((self.V, 4, 3, 2), dtype=torch.float64, device=self.device)
+        _check(load().qdw_unpack(self._h, _ptr(eo), _ptr(out), PREC[prec], _stream()),
+               "qdw_unpack")
+        return torch.view_as_complex(out)
+
+
+def dw_apply(op: Op, x, out, prec: str = "f64"):
+    _check(load().dw_apply(op.handle, _ptr(x), _ptr(out), PREC[prec], _stream()), "dw_apply")
+    return out
+
+
+def dw_dag_apply(op: Op, x, out, prec: str = "f64"):
+    _check(load().dw_dag_apply(op.handle, _ptr(x), _ptr(out), PREC[prec], _stream()),
+           "dw_dag_apply")
+    return out

@@ -1,0 +1,63 @@
+"""Host-side checks of the C ABI: the library builds, loads without a GPU, and exports
+every entry point that include/qdw.h declares."""
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2202_07388_amd import qdw
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qdw.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z_0-9]*\s*\*?\s*([A-Za-z_][A-Za-z_0-9]*)\s*\(",
+                       src, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "while", "return")))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(qdw.LIB_PATH):
+        from paper_2202_07388_amd import build
+        build.build(verbose=False)
+    return qdw.load()
+
+
+def test_header_declares_the_four_named_calls():
+    names = declared_functions()
+    for n in ("dw_apply", "dw_dag_apply"):
+        assert n in names, n
+
+
+def test_every_declared_symbol_is_exported(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", qdw.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(l.split()[-1] for l in out.splitlines() if l.strip())
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+    for n in declared_functions():
+        assert hasattr(lib, n)
+
+
+def test_errors_are_reported_without_gpu(lib):
+    import ctypes
+    rc = lib.dw_apply(None, None, None, 0, None)
+    assert rc == -1
+    assert b"null" in lib.qdw_last_error()
+    assert lib.qdw_field_bytes(None, 0) == 0
+
+
+def test_format_eps_match_paper_table():
+    """Machine epsilons used for the reset threshold are the paper's Table 1 values."""
+    rows = [l.split() for l in open(os.path.join(ROOT, "tests", "golden",
+                                                 "table1_format_limits.txt"))
+            if l.strip() and not l.startswith("#")]
+    table = {r[0]: float(r[-1]) for r in rows}
+    for name, key in (("binary64", "f64"), ("binary32", "f32"), ("binary16", "f16"),
+                      ("bfloat16", "bf16")):
+        assert abs(qdw.EPS[key] - table[name]) <= 0.05 * table[name]
