@@ -102,6 +102,100 @@ int qdw_unpack(const qdw_op* op, const void* eo, double* canonical, qdw_prec pre
 int dw_apply(qdw_op* op, const void* in, void* out, qdw_prec prec, void* stream);
 int dw_dag_apply(qdw_op* op, const void* in, void* out, qdw_prec prec, void* stream);
 
+/* Result of a solve. */
+typedef struct {
+    int status;          /* >= 0: converged, number of regular steps (the paper's `status`,
+                            Fig. 1); -1: nmx steps did not suffice; -2: stagnation (no
+                            progress, Sec. 2: the residual stalls once the working type is
+                            exhausted); -3: a non-finite value appeared                    */
+    int nreset;          /* reset steps (CGNE) / restarts (GCR) performed                  */
+    int n_dw_hi;         /* applications of D or D^+ in FP64                               */
+    int n_dw_lo;         /* applications of D or D^+ in a lower precision (incl. SAP blocks
+                            counted as one full-lattice application per colour sweep)     */
+    int n_steps;         /* regular steps executed (equals status when converged)         */
+    double rel_res_true; /* |eta - M psi| / |eta| recomputed in FP64 at exit, M = D^+D
+                            (cgne_solve) or D (GCR solvers)                                */
+    double t_sec;        /* wall time of the call, host clock                              */
+} qdw_info;
+
+/* Settings of the normal-equation solver (Sec. 2, openQ*D's cgne). */
+typedef struct {
+    double res;      /* target |eta - D^+ D psi| / |eta|                                   */
+    int nmx;         /* maximal number of regular CG steps                                  */
+    qdw_prec inner;  /* QDW_F64: plain FP64 CG. QDW_F32 / QDW_F16S / QDW_BF16S: regular
+                        steps in that storage precision (binary32 arithmetic, binary64
+                        reductions), reset steps in FP64                                    */
+    double delta;    /* reset when the recursive residual fell by this factor since the last
+                        reset. < 0: default, 10 eps of `inner` when keep_p = 0 (the paper's
+                        reset, Fig. 1: about the working type's epsilon) and 0.1 when
+                        keep_p = 1; 0: only when the target is reached or progress stalls  */
+    int keep_p;      /* 1: a reset keeps the search direction (reliable update) as long as
+                        the recursive residual stayed within 30 % of the true one, else
+                        restarts; 0: every reset restarts CG from the new residual          */
+} qdw_cgne_params;
+
+/* Device workspace (bytes) cgne_solve needs for these settings. 0 on bad arguments. */
+size_t qdw_cgne_workspace_bytes(const qdw_op* op, const qdw_cgne_params* prm);
+
+/* Solve D^+ D psi = eta from psi = 0 (Sec. 2). eta and psi are distinct FP64 eo-SoA
+ * fields (device); work is device memory of at least qdw_cgne_workspace_bytes bytes
+ * (caller-owned scratch, clobbered). Regular steps keep their scalars in device memory;
+ * the host reads |r|^2 one step late to decide on resets and termination. On return
+ * psi holds the solution (also when status < 0: the best iterate), *info (host) the
+ * outcome; the stream is synchronised. Non-convergence is reported in info->status,
+ * not as an error code. */
+int cgne_solve(qdw_op* op, const void* eta, void* psi, const qdw_cgne_params* prm, void* work,
+               size_t work_bytes, qdw_info* info, void* stream);
+
+/* Preconditioners of the flexible GCR solver. */
+enum {
+    QDW_PRECOND_NONE = 0,  /* identity: plain GCR, the paper's (ncy, nmr) = (0, 0)          */
+    QDW_PRECOND_SAP = 1,   /* Schwarz alternating procedure (Sec. 3)                          */
+    QDW_PRECOND_NN = 2,    /* learned gauge-covariant network (not from the paper)            */
+    QDW_PRECOND_NN_SAP = 3 /* network while it reduces the GCR residual, then SAP             */
+};
+
+/* Settings of the SAP-preconditioned flexible GCR (Sec. 3.1, Table 2). The large and the
+ * reduction data type (ldtype, rdtype) are binary64; sdtype is the small type of the
+ * SAP block solves. */
+typedef struct {
+    double res;          /* desired relative residual |eta - D psi| / |eta|               */
+    int nmx;             /* maximal number of GCR steps                                    */
+    int nkv;             /* Krylov vectors generated before a restart (1..16)              */
+    int ncy;             /* SAP cycles per preconditioner application                      */
+    int nmr;             /* MR steps per block per cycle                                   */
+    int bs[4];           /* block extents (T, L1, L2, L3 order). Each divides the lattice
+                            extent with an even number (>= 2) of blocks per direction; the
+                            block holds 64, 128, 192 or 256 sites (QDW_EBLOCK otherwise)     */
+    qdw_prec sdtype;     /* QDW_F32, QDW_F16S or QDW_BF16S storage for the SAP fields      */
+    int precond;         /* QDW_PRECOND_*                                                  */
+    const void* nn_weights; /* (device) network weights for QDW_PRECOND_NN / _NN_SAP        */
+} qdw_sap_gcr_params;
+
+/* Device workspace (bytes) sap_gcr_solve needs (2 nkv + 2 FP64 fields plus the
+ * preconditioner's). 0 on bad arguments. */
+size_t qdw_sap_gcr_workspace_bytes(const qdw_op* op, const qdw_sap_gcr_params* prm);
+
+/* Solve D psi = eta from psi = 0 with flexible GCR restarted every nkv steps (Sec. 3.1).
+ * eta, psi: distinct FP64 eo-SoA fields (device); work: device scratch of at least
+ * qdw_sap_gcr_workspace_bytes. On return psi holds the solution and *info (host) the
+ * outcome (status = GCR steps, nreset = restart steps, rel_res_true = |eta - D psi|/|eta|
+ * of the final FP64 restart step); n_dw_lo counts SAP work as ncy*nmr block-operator
+ * sweeps of the full lattice per preconditioner application. Synchronises the stream. */
+int sap_gcr_solve(qdw_op* op, const void* eta, void* psi, const qdw_sap_gcr_params* prm,
+                  void* work, size_t work_bytes, qdw_info* info, void* stream);
+
+/* Device workspace (bytes) of sap_apply for storage precision sdtype. */
+size_t qdw_sap_workspace_bytes(const qdw_op* op, qdw_prec sdtype);
+
+/* phi = M_SAP rho: ncy Schwarz cycles (Sec. 3, Fig. 2), each solving every colour-0
+ * block then every colour-1 block by nmr minimal-residual steps on the block operator
+ * (hops leaving the block dropped, Fig. 3), from phi = 0. rho, phi: distinct FP64
+ * eo-SoA fields (device); internally stored in sdtype, scaled to unit component size.
+ * ncy = 0 copies rho. Errors: QDW_EBLOCK for an unsupported block size. */
+int sap_apply(qdw_op* op, const void* rho, void* phi, int ncy, int nmr, const int bs[4],
+              qdw_prec sdtype, void* work, size_t work_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

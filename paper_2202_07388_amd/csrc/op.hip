@@ -455,7 +455,7 @@ extern "C" int qdw_create(const qdw_lattice* lat, const double* su3, const doubl
     // 4. reduction scratch
     CREATE_HIP(hipMalloc((void**)&op->partials, sizeof(double) * kMaxPartials * kMaxScalars));
     CREATE_HIP(hipMalloc((void**)&op->scalars, sizeof(double) * kMaxScalars));
-    CREATE_HIP(hipHostMalloc((void**)&op->host_scalars, sizeof(double) * kMaxScalars));
+    CREATE_HIP(hipHostMalloc((void**)&op->host_scalars, sizeof(double) * kHostScalars));
     CREATE_HIP(hipStreamSynchronize(st));
 #undef CREATE_HIP
     *out = op;

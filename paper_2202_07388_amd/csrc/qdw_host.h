@@ -20,13 +20,14 @@ struct qdw_op {
     // reduction scratch: per-workgroup partial sums and the final scalars
     double* partials;      // device, kMaxPartials * kMaxScalars doubles
     double* scalars;       // device, kMaxScalars doubles
-    double* host_scalars;  // pinned host, kMaxScalars doubles
+    double* host_scalars;  // pinned host, kHostScalars doubles
 };
 
 namespace qdw {
 
 constexpr int kMaxPartials = 2048;  // workgroups of a reduction launch
 constexpr int kMaxScalars = 64;     // doubles produced by one fused reduction
+constexpr int kHostScalars = 1024;  // doubles the host can read back in one copy
 
 void set_error(const std::string& msg);
 

@@ -1,0 +1,354 @@
+// sap.hip -- Schwarz alternating procedure as a preconditioner (paper Sec. 3, Fig. 2
+// and 3): the lattice is cut into blocks coloured like a chessboard; one cycle solves
+// every block of colour 0, then every block of colour 1, each approximately by nmr
+// minimal-residual steps on the block-restricted operator D_b (hops leaving the block
+// dropped), with the residual brought up to date between the two colours.
+//
+// GPU mapping: one workgroup per block, one lane per site (block volume 64..256 sites).
+// A block's residual lives in LDS for all nmr steps; every lane keeps its own clover
+// blocks and its four forward links in registers. The backward hop into a site is
+// computed by the lane that owns the link (the site below it) and handed over through
+// LDS as a transported half spinor, so each link is read from HBM once per sweep.
+// Storage precision SP (FP32, FP16 or BF16) for every field in HBM; FP32 arithmetic;
+// block reductions accumulate per lane in FP32 and combine across lanes in FP64.
+//
+// After a colour's block solves, the block residuals r_b are exactly the new residual
+// on that colour; the other colour's residual loses the hops from the block corrections
+// that cross into it (D_partial chi, Fig. 3 right), applied by a second kernel.
+#include "sap.h"
+
+#include "dirac_core.h"
+
+namespace qdw {
+
+int make_block_geom(const Geom& g, const int bs[4], BlockGeom* B)
+{
+    int vol = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+        QDW_CHECK(bs[mu] >= 1 && g.L[mu] % bs[mu] == 0, QDW_EBLOCK,
+                  "SAP: block extents must divide the lattice extents");
+        const int nb = g.L[mu] / bs[mu];
+        QDW_CHECK(nb >= 2 && nb % 2 == 0, QDW_EBLOCK,
+                  "SAP: need an even number (>= 2) of blocks in every direction");
+        B->bs[mu] = bs[mu];
+        B->nb[mu] = nb;
+        vol *= bs[mu];
+    }
+    QDW_CHECK(vol >= 64 && vol <= 256 && vol % 64 == 0, QDW_EBLOCK,
+              "SAP: block volume must be 64, 128, 192 or 256 sites");
+    B->bvol = vol;
+    B->lstride[3] = 1;
+    B->lstride[2] = bs[3];
+    B->lstride[1] = bs[3] * bs[2];
+    B->lstride[0] = bs[3] * bs[2] * bs[1];
+    B->nblk = B->nb[0] * B->nb[1] * B->nb[2] * B->nb[3];
+    return QDW_OK;
+}
+
+namespace {
+
+constexpr int kBMax = 256;
+
+template <int SP, int MU>
+__device__ __forceinline__ void push_backward(float (*hb)[12][kBMax], const BlockGeom& B,
+                                              const int l[4], int t, const cx<float> r[12],
+                                              const cx<float> u[6], cx<float> ph)
+{
+    if (l[MU] < B.bs[MU] - 1) {
+        cx<float> h[6], w[6];
+        project<float, MU, +1>(r, h);
+        su3_apply<float, true>(u, scale(conj_(ph), -0.5f), h, w);
+        const int dst = t + B.lstride[MU];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            hb[MU][2 * c][dst] = w[c].re;
+            hb[MU][2 * c + 1][dst] = w[c].im;
+        }
+    }
+}
+
+template <int SP, int MU>
+__device__ __forceinline__ void hop_forward(float (*rl)[kBMax], const BlockGeom& B, const int l[4],
+                                            int t, const cx<float> u[6], cx<float> ph,
+                                            cx<float> v[12])
+{
+    if (l[MU] < B.bs[MU] - 1) {
+        const int src = t + B.lstride[MU];
+        cx<float> s[12], h[6], w[6];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) s[c] = {rl[2 * c][src], rl[2 * c + 1][src]};
+        project<float, MU, -1>(s, h);
+        su3_apply<float, false>(u, scale(ph, -0.5f), h, w);
+        expand_add<float, MU, -1>(w, v);
+    }
+}
+
+template <int MU>
+__device__ __forceinline__ void hop_backward(float (*hb)[12][kBMax], const int l[4], int t,
+                                             cx<float> v[12])
+{
+    if (l[MU] > 0) {
+        cx<float> w[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) w[c] = {hb[MU][2 * c][t], hb[MU][2 * c + 1][t]};
+        expand_add<float, MU, +1>(w, v);
+    }
+}
+
+template <int SP>
+__global__ __launch_bounds__(256) void sap_mr_kernel(Geom g, BlockGeom B, int colour, int nmr,
+                                                     void* __restrict__ rs, void* __restrict__ psis,
+                                                     void* __restrict__ delta,
+                                                     const void* __restrict__ links,
+                                                     const void* __restrict__ theta,
+                                                     const void* __restrict__ clover)
+{
+    __shared__ float rl[24][kBMax];
+    __shared__ float hb[4][12][kBMax];
+    __shared__ double red[4][3];
+    const int t = threadIdx.x;
+    const int nw = B.bvol >> 6;
+    // the blockIdx-th block of this colour (blocks per x3 row is even, so colours alternate)
+    int b[4];
+    {
+        int r = 2 * blockIdx.x;
+        b[3] = r % B.nb[3]; r /= B.nb[3];
+        b[2] = r % B.nb[2]; r /= B.nb[2];
+        b[1] = r % B.nb[1];
+        b[0] = r / B.nb[1];
+        if (((b[0] + b[1] + b[2] + b[3]) & 1) != colour) b[3] += 1;
+    }
+    int l[4];
+    {
+        int r = t;
+        l[3] = r % B.bs[3]; r /= B.bs[3];
+        l[2] = r % B.bs[2]; r /= B.bs[2];
+        l[1] = r % B.bs[1];
+        l[0] = r / B.bs[1];
+    }
+    int x[4];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) x[mu] = b[mu] * B.bs[mu] + l[mu];
+    const int lex = ((x[0] * g.L[1] + x[1]) * g.L[2] + x[2]) * g.L[3] + x[3];
+    const int par = (x[0] + x[1] + x[2] + x[3]) & 1;
+    const int i = lex >> 1;
+
+    cx<float> r[12], chi[12];
+    load_spinor<SP>(rs, g.Vh, par, i, r);
+    float cl[72];
+    load_clover<SP>(clover, g.Vh, par, i, cl);
+    cx<float> u[4][6], ph[4];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) load_link<SP>(links, theta, g.Vh, par, i, mu, u[mu], ph[mu]);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        chi[c] = {0.f, 0.f};
+        rl[2 * c][t] = r[c].re;
+        rl[2 * c + 1][t] = r[c].im;
+    }
+    for (int k = 0; k < nmr; ++k) {
+        __syncthreads();  // rl holds the current block residual
+        push_backward<SP, 0>(hb, B, l, t, r, u[0], ph[0]);
+        push_backward<SP, 1>(hb, B, l, t, r, u[1], ph[1]);
+        push_backward<SP, 2>(hb, B, l, t, r, u[2], ph[2]);
+        push_backward<SP, 3>(hb, B, l, t, r, u[3], ph[3]);
+        cx<float> v[12];
+        herm6_apply<float>(cl, r, v);
+        herm6_apply<float>(cl + 36, r + 6, v + 6);
+        hop_forward<SP, 0>(rl, B, l, t, u[0], ph[0], v);
+        hop_forward<SP, 1>(rl, B, l, t, u[1], ph[1], v);
+        hop_forward<SP, 2>(rl, B, l, t, u[2], ph[2], v);
+        hop_forward<SP, 3>(rl, B, l, t, u[3], ph[3], v);
+        __syncthreads();  // every pushed half spinor is in hb
+        hop_backward<0>(hb, l, t, v);
+        hop_backward<1>(hb, l, t, v);
+        hop_backward<2>(hb, l, t, v);
+        hop_backward<3>(hb, l, t, v);
+        // omega = (v, r) / (v, v) over the block
+        float nre = 0.f, nim = 0.f, den = 0.f;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            const cx<float> z = cmul_conj(v[c], r[c]);
+            nre += z.re;
+            nim += z.im;
+            den += v[c].re * v[c].re + v[c].im * v[c].im;
+        }
+        double a0 = nre, a1 = nim, a2 = den;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            a0 += __shfl_xor(a0, o, 64);
+            a1 += __shfl_xor(a1, o, 64);
+            a2 += __shfl_xor(a2, o, 64);
+        }
+        if ((t & 63) == 0) {
+            red[t >> 6][0] = a0;
+            red[t >> 6][1] = a1;
+            red[t >> 6][2] = a2;
+        }
+        __syncthreads();
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        for (int w = 0; w < nw; ++w) {
+            s0 += red[w][0];
+            s1 += red[w][1];
+            s2 += red[w][2];
+        }
+        const cx<float> om = s2 > 0.0 ? cx<float>{(float)(s0 / s2), (float)(s1 / s2)}
+                                      : cx<float>{0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            chi[c] = chi[c] + om * r[c];
+            r[c] = r[c] - om * v[c];
+        }
+        __syncthreads();  // all lanes have read red and rl of this step
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            rl[2 * c][t] = r[c].re;
+            rl[2 * c + 1][t] = r[c].im;
+        }
+    }
+    cx<float> p[12];
+    load_spinor<SP>(psis, g.Vh, par, i, p);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) p[c] = p[c] + chi[c];
+    store_spinor<SP>(psis, g.Vh, par, i, p);
+    store_spinor<SP>(delta, g.Vh, par, i, chi);
+    store_spinor<SP>(rs, g.Vh, par, i, r);
+}
+
+// r(x) -= (D delta)(x) restricted to the hops that enter x's block from outside, for
+// every site x of a block of colour 1 - `colour` (delta lives on the colour blocks)
+template <int SP, int MU>
+__device__ __forceinline__ void cross_hops(const Geom& g, const BlockGeom& B, const void* delta,
+                                           const void* links, const void* theta, int par, int i,
+                                           const int x[4], int lex, cx<float> acc[12], bool& any)
+{
+    cx<float> s[12], h[6], w[6], u[6], ph;
+    if (x[MU] % B.bs[MU] == B.bs[MU] - 1) {
+        const int j = lex_fwd(g, x, lex, MU) >> 1;
+        load_spinor<SP>(delta, g.Vh, 1 - par, j, s);
+        project<float, MU, -1>(s, h);
+        load_link<SP>(links, theta, g.Vh, par, i, MU, u, ph);
+        const float sg = (MU == 0 && x[0] == g.L[0] - 1) ? -0.5f * g.bc_t : -0.5f;
+        su3_apply<float, false>(u, scale(ph, sg), h, w);
+        expand_add<float, MU, -1>(w, acc);
+        any = true;
+    }
+    if (x[MU] % B.bs[MU] == 0) {
+        const int j = lex_bwd(g, x, lex, MU) >> 1;
+        load_spinor<SP>(delta, g.Vh, 1 - par, j, s);
+        project<float, MU, +1>(s, h);
+        load_link<SP>(links, theta, g.Vh, 1 - par, j, MU, u, ph);
+        const float sg = (MU == 0 && x[0] == 0) ? -0.5f * g.bc_t : -0.5f;
+        su3_apply<float, true>(u, scale(conj_(ph), sg), h, w);
+        expand_add<float, MU, +1>(w, acc);
+        any = true;
+    }
+}
+
+template <int SP>
+__global__ __launch_bounds__(256) void sap_boundary_kernel(Geom g, BlockGeom B, int colour,
+                                                           void* __restrict__ rs,
+                                                           const void* __restrict__ delta,
+                                                           const void* __restrict__ links,
+                                                           const void* __restrict__ theta)
+{
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int par = threadIdx.x >> 7;
+    const int i = tile * 128 + (threadIdx.x & 127);
+    if (i >= g.Vh) return;
+    int x[4], lex;
+    eo_coords(g, par, i, x, lex);
+    const int bc = (x[0] / B.bs[0] + x[1] / B.bs[1] + x[2] / B.bs[2] + x[3] / B.bs[3]) & 1;
+    if (bc == colour) return;
+    cx<float> acc[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[c] = {0.f, 0.f};
+    bool any = false;
+    cross_hops<SP, 0>(g, B, delta, links, theta, par, i, x, lex, acc, any);
+    cross_hops<SP, 1>(g, B, delta, links, theta, par, i, x, lex, acc, any);
+    cross_hops<SP, 2>(g, B, delta, links, theta, par, i, x, lex, acc, any);
+    cross_hops<SP, 3>(g, B, delta, links, theta, par, i, x, lex, acc, any);
+    if (!any) return;
+    cx<float> r[12];
+    load_spinor<SP>(rs, g.Vh, par, i, r);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) r[c] = r[c] - acc[c];
+    store_spinor<SP>(rs, g.Vh, par, i, r);
+}
+
+template <int SP>
+int sap_impl(qdw_op* op, const void* rho, void* phi, double rho_norm, int ncy, int nmr,
+             const BlockGeom& B, char* work, hipStream_t st)
+{
+    const Geom& g = op->g;
+    const size_t fb = spinor_bytes(g, SP);
+    void* rs = work;
+    void* psis = work + fb;
+    void* delta = work + 2 * fb;
+    int rc;
+    if (ncy == 0 || !(rho_norm > 0.0)) {
+        // no preconditioning (the (0, 0) setting), or nothing to precondition
+        return run_map(op, Axpby<F64, F64>{rho, phi, ncy == 0 ? 1.0 : 0.0, 0.0, g.Vh}, st);
+    }
+    const double s = std::sqrt(24.0 * g.V) / rho_norm;
+    if ((rc = run_map(op, ScaleNorm<F64, SP>{rho, rs, s, g.Vh}, st, op->scalars + S_SAP))) return rc;
+    if ((rc = run_map(op, Zero<SP>{psis, g.Vh}, st))) return rc;
+    const int nbdw = (g.Vh + 127) / 128;
+    for (int cy = 0; cy < ncy; ++cy)
+        for (int c = 0; c < 2; ++c) {
+            sap_mr_kernel<SP><<<B.nblk / 2, B.bvol, 0, st>>>(g, B, c, nmr, rs, psis, delta,
+                                                             op->links[SP], op->theta[SP],
+                                                             op->clover[SP]);
+            QDW_LAUNCH_CHECK();
+            sap_boundary_kernel<SP><<<nbdw, 256, 0, st>>>(g, B, c, rs, delta, op->links[SP],
+                                                          op->theta[SP]);
+            QDW_LAUNCH_CHECK();
+        }
+    return run_map(op, Axpby<SP, F64>{psis, phi, 1.0 / s, 0.0, g.Vh}, st);
+}
+
+}  // namespace
+
+size_t sap_workspace(const qdw_op* op, int sdtype) { return 3 * spinor_bytes(op->g, sdtype) + 256; }
+
+int sap_run(qdw_op* op, const void* rho, void* phi, double rho_norm, int ncy, int nmr,
+            const BlockGeom& B, int sdtype, char* work, hipStream_t st)
+{
+    switch (sdtype) {
+    case F32: return sap_impl<F32>(op, rho, phi, rho_norm, ncy, nmr, B, work, st);
+    case F16S: return sap_impl<F16S>(op, rho, phi, rho_norm, ncy, nmr, B, work, st);
+    case BF16S: return sap_impl<BF16S>(op, rho, phi, rho_norm, ncy, nmr, B, work, st);
+    default: QDW_CHECK(false, QDW_EINVAL, "SAP: sdtype must be QDW_F32, QDW_F16S or QDW_BF16S");
+    }
+}
+
+}  // namespace qdw
+
+using namespace qdw;
+
+extern "C" size_t qdw_sap_workspace_bytes(const qdw_op* op, qdw_prec sdtype)
+{
+    if (!op || sdtype < QDW_F32 || sdtype > QDW_BF16S) return 0;
+    return sap_workspace(op, sdtype);
+}
+
+extern "C" int sap_apply(qdw_op* op, const void* rho, void* phi, int ncy, int nmr, const int bs[4],
+                         qdw_prec sdtype, void* work, size_t work_bytes, void* stream)
+{
+    QDW_CHECK(op && rho && phi && bs && work, QDW_EINVAL, "sap_apply: null argument");
+    QDW_CHECK(rho != phi, QDW_EINVAL, "sap_apply: rho and phi must be distinct");
+    QDW_CHECK(ncy >= 0 && nmr >= 0, QDW_EINVAL, "sap_apply: ncy and nmr must be >= 0");
+    QDW_CHECK(sdtype >= QDW_F32 && sdtype <= QDW_BF16S, QDW_EINVAL,
+              "sap_apply: sdtype must be QDW_F32, QDW_F16S or QDW_BF16S");
+    QDW_CHECK(work_bytes >= sap_workspace(op, sdtype), QDW_EWORKSPACE,
+              "sap_apply: workspace smaller than qdw_sap_workspace_bytes()");
+    BlockGeom B;
+    int rc = make_block_geom(op->g, bs, &B);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = run_map(op, Norm2<F64>{rho, op->g.Vh}, st, op->scalars + S_TMP))) return rc;
+    double n2;
+    if ((rc = read_scalars(op, S_TMP, 1, &n2, st))) return rc;
+    char* wk = (char*)(((uintptr_t)work + 255) & ~(uintptr_t)255);
+    return sap_run(op, rho, phi, std::sqrt(n2), ncy, nmr, B, sdtype, wk, st);
+}

@@ -70,7 +70,40 @@ def _declare_solvers(L):
             fn.restype = res
 
 
-_OPTIONAL: list = []
+class Info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("nreset", ctypes.c_int), ("n_dw_hi", ctypes.c_int),
+                ("n_dw_lo", ctypes.c_int), ("n_steps", ctypes.c_int),
+                ("rel_res_true", ctypes.c_double), ("t_sec", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class CgneParams(ctypes.Structure):
+    _fields_ = [("res", ctypes.c_double), ("nmx", ctypes.c_int), ("inner", ctypes.c_int),
+                ("delta", ctypes.c_double), ("keep_p", ctypes.c_int)]
+
+
+class SapGcrParams(ctypes.Structure):
+    _fields_ = [("res", ctypes.c_double), ("nmx", ctypes.c_int), ("nkv", ctypes.c_int),
+                ("ncy", ctypes.c_int), ("nmr", ctypes.c_int), ("bs", ctypes.c_int * 4),
+                ("sdtype", ctypes.c_int), ("precond", ctypes.c_int),
+                ("nn_weights", ctypes.c_void_p)]
+
+
+PRECOND = {"none": 0, "sap": 1, "nn": 2, "nn_sap": 3}
+
+_OPTIONAL: list = [
+    ("qdw_sap_gcr_workspace_bytes", [_P, ctypes.POINTER(SapGcrParams)], ctypes.c_size_t),
+    ("sap_gcr_solve", [_P, _P, _P, ctypes.POINTER(SapGcrParams), _P, ctypes.c_size_t,
+                       ctypes.POINTER(Info), _P], ctypes.c_int),
+    ("qdw_sap_workspace_bytes", [_P, ctypes.c_int], ctypes.c_size_t),
+    ("sap_apply", [_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int * 4),
+                   ctypes.c_int, _P, ctypes.c_size_t, _P], ctypes.c_int),
+    ("qdw_cgne_workspace_bytes", [_P, ctypes.POINTER(CgneParams)], ctypes.c_size_t),
+    ("cgne_solve", [_P, _P, _P, ctypes.POINTER(CgneParams), _P, ctypes.c_size_t,
+                    ctypes.POINTER(Info), _P], ctypes.c_int),
+]
 
 
 def _check(rc: int, what: str):
@@ -178,3 +211,58 @@ def dw_dag_apply(op: Op, x, out, prec: str = "f64"):
     _check(load().dw_dag_apply(op.handle, _ptr(x), _ptr(out), PREC[prec], _stream()),
            "dw_dag_apply")
     return out
+
+
+def _workspace(op: Op, nbytes: int):
+    """Device workspace owned by the Python Op (grown on demand, reused across calls)."""
+    torch = _torch()
+    ws = getattr(op, "_ws", None)
+    if ws is None or ws.numel() < nbytes:
+        op._ws = None
+        op._ws = torch.empty(nbytes, dtype=torch.uint8, device=op.device)
+    return op._ws
+
+
+def cgne_solve(op: Op, eta, psi, res: float = 1e-10, nmx: int = 20000, inner: str = "f64",
+               delta: float = -1.0, keep_p: bool = True) -> dict:
+    """Solve D^+ D psi = eta (FP64 eo-SoA fields) with the normal-equation CG."""
+    L = load()
+    prm = CgneParams(res, nmx, PREC[inner], delta, 1 if keep_p else 0)
+    nb = int(L.qdw_cgne_workspace_bytes(op.handle, ctypes.byref(prm)))
+    ws = _workspace(op, nb)
+    info = Info()
+    _check(L.cgne_solve(op.handle, _ptr(eta), _ptr(psi), ctypes.byref(prm), _ptr(ws),
+                        ws.numel(), ctypes.byref(info), _stream()), "cgne_solve")
+    return info.as_dict()
+
+
+def sap_gcr_solve(op: Op, eta, psi, res: float = 1e-10, nmx: int = 2000, nkv: int = 16,
+                  ncy: int = 5, nmr: int = 4, bs=(4, 4, 4, 4), sdtype: str = "f16",
+                  precond: str = "sap", nn_weights=None) -> dict:
+    """Solve D psi = eta (FP64 eo-SoA fields) with (SAP-preconditioned) flexible GCR."""
+    L = load()
+    w = ctypes.c_void_p(nn_weights.data_ptr()) if nn_weights is not None else None
+    prm = SapGcrParams(res, nmx, nkv, ncy, nmr, (ctypes.c_int * 4)(*bs), PREC[sdtype],
+                       PRECOND[precond], w)
+    nb = int(L.qdw_sap_gcr_workspace_bytes(op.handle, ctypes.byref(prm)))
+    if nb == 0:
+        raise QdwError("bad SAP-GCR settings")
+    ws = _workspace(op, nb)
+    info = Info()
+    _check(L.sap_gcr_solve(op.handle, _ptr(eta), _ptr(psi), ctypes.byref(prm), _ptr(ws),
+                           ws.numel(), ctypes.byref(info), _stream()), "sap_gcr_solve")
+    return info.as_dict()
+
+
+def sap_apply(op: Op, rho, phi, ncy: int = 5, nmr: int = 4, bs=(4, 4, 4, 4),
+              sdtype: str = "f16"):
+    """phi = M_SAP rho (FP64 eo-SoA fields)."""
+    L = load()
+    nb = int(L.qdw_sap_workspace_bytes(op.handle, PREC[sdtype]))
+    if nb == 0:
+        raise QdwError("bad SAP storage precision")
+    ws = _workspace(op, nb)
+    b = (ctypes.c_int * 4)(*bs)
+    _check(L.sap_apply(op.handle, _ptr(rho), _ptr(phi), ncy, nmr, ctypes.byref(b),
+                       PREC[sdtype], _ptr(ws), ws.numel(), _stream()), "sap_apply")
+    return phi

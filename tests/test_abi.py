@@ -30,7 +30,7 @@ def lib():
 
 def test_header_declares_the_four_named_calls():
     names = declared_functions()
-    for n in ("dw_apply", "dw_dag_apply"):
+    for n in ("dw_apply", "dw_dag_apply", "cgne_solve", "sap_gcr_solve"):
         assert n in names, n
 
 
