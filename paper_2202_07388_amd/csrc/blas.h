@@ -25,7 +25,7 @@ __device__ __forceinline__ void ld4(const void* f, int Vh, int par, int g, int i
     constexpr int NCH = 4 / CPC;                 // chunks per unit
 #pragma unroll
     for (int k = 0; k < NCH; ++k) {
-        Chunk<P> c = load_chunk_cached<P>(f, ((long)par * T::SPIN_CHUNKS + g * NCH + k) * Vh + i);
+        Chunk<P> c = load_chunk_cached<P>(f, chunk_at(Vh, T::SPIN_CHUNKS, par, g * NCH + k, i));
 #pragma unroll
         for (int j = 0; j < CPC; ++j)
             v[k * CPC + j] = {(R)to_real<P>(c.v[2 * j]), (R)to_real<P>(c.v[2 * j + 1])};
@@ -47,7 +47,7 @@ __device__ __forceinline__ void st4(void* f, int Vh, int par, int g, int i, cons
             c.v[2 * j] = to_store<P>((RT)v[k * CPC + j].re);
             c.v[2 * j + 1] = to_store<P>((RT)v[k * CPC + j].im);
         }
-        const long at = ((long)par * T::SPIN_CHUNKS + g * NCH + k) * Vh + i;
+        const long at = chunk_at(Vh, T::SPIN_CHUNKS, par, g * NCH + k, i);
         uint4 raw;
         __builtin_memcpy(&raw, &c, 16);
         ((uint4*)f)[at] = raw;

@@ -56,11 +56,11 @@ __device__ __forceinline__ void expand_add(const cx<R> w[6], cx<R> acc[12])
     }
 }
 
-// link rows 0, 1 (6 complex) and the phase exp(i theta) of link (par, i, mu)
+// link (par, i, mu): rows 0, 1 of the U(3) matrix U (6 complex) and d = det U
 template <int P>
-__device__ __forceinline__ void load_link(const void* links, const void* theta, int Vh, int par,
+__device__ __forceinline__ void load_link(const void* links, const void* dets, int Vh, int par,
                                           int i, int mu, cx<typename Traits<P>::real> u[6],
-                                          cx<typename Traits<P>::real>& ph)
+                                          cx<typename Traits<P>::real>& d)
 {
     using T = Traits<P>;
     using R = typename T::real;
@@ -68,46 +68,42 @@ __device__ __forceinline__ void load_link(const void* links, const void* theta, 
     if constexpr (P == F64 || P == F32) {
 #pragma unroll
         for (int k = 0; k < T::LINK_CHUNKS; ++k) {
-            Chunk<P> c = load_chunk_cached<P>(links, (row * T::LINK_CHUNKS + k) * Vh + i);
+            Chunk<P> c = load_chunk_cached<P>(links, chunk_at(Vh, T::LINK_CHUNKS, row, k, i));
 #pragma unroll
             for (int j = 0; j < T::PER_CHUNK / 2; ++j)
                 u[k * (T::PER_CHUNK / 2) + j] = {c.v[2 * j], c.v[2 * j + 1]};
         }
-        const R th = ((const typename T::store*)theta)[row * Vh + i];
-        R s, co;
-        if constexpr (P == F64) sincos(th, &s, &co);
-        else sincosf(th, &s, &co);
-        ph = {co, s};
+        const R* dp = (const R*)dets + 2 * (row * Vh + i);
+        d = {dp[0], dp[1]};
     } else {
-        Chunk<P> c0 = load_chunk_cached<P>(links, (row * 2 + 0) * Vh + i);
-        Chunk<P> c1 = load_chunk_cached<P>(links, (row * 2 + 1) * Vh + i);
+        Chunk<P> c0 = load_chunk_cached<P>(links, chunk_at(Vh, 2, row, 0, i));
+        Chunk<P> c1 = load_chunk_cached<P>(links, chunk_at(Vh, 2, row, 1, i));
 #pragma unroll
         for (int j = 0; j < 4; ++j) u[j] = {to_real<P>(c0.v[2 * j]), to_real<P>(c0.v[2 * j + 1])};
         u[4] = {to_real<P>(c1.v[0]), to_real<P>(c1.v[1])};
         u[5] = {to_real<P>(c1.v[2]), to_real<P>(c1.v[3])};
-        ph = {to_real<P>(c1.v[4]), to_real<P>(c1.v[5])};
+        d = {to_real<P>(c1.v[4]), to_real<P>(c1.v[5])};
     }
 }
 
-// w = c * V h (DAGGER: c * V^+ h) for the two spin components of h; V rebuilt from rows
+// w = U h (DAGGER: U^+ h) for both spin components of the half spinor h; row 2 of U is
+// rebuilt as d * conj(row0 x row1)
 template <typename R, bool DAGGER>
-__device__ __forceinline__ void su3_apply(const cx<R> u[6], cx<R> c, const cx<R> h[6], cx<R> w[6])
+__device__ __forceinline__ void su3_mul(const cx<R> u[6], cx<R> d, const cx<R> h[6], cx<R> w[6])
 {
-    cx<R> r2[3];
-    r2[0] = conj_(u[1] * u[5] - u[2] * u[4]);
-    r2[1] = conj_(u[2] * u[3] - u[0] * u[5]);
-    r2[2] = conj_(u[0] * u[4] - u[1] * u[3]);
+    const cx<R> r2[3] = {d * conj_(u[1] * u[5] - u[2] * u[4]),
+                         d * conj_(u[2] * u[3] - u[0] * u[5]),
+                         d * conj_(u[0] * u[4] - u[1] * u[3])};
     const cx<R> m[9] = {u[0], u[1], u[2], u[3], u[4], u[5], r2[0], r2[1], r2[2]};
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
-        const cx<R> h0 = c * h[3 * a], h1 = c * h[3 * a + 1], h2 = c * h[3 * a + 2];
+        const cx<R> h0 = h[3 * a], h1 = h[3 * a + 1], h2 = h[3 * a + 2];
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
-            if (!DAGGER) {
+            if (!DAGGER)
                 w[3 * a + r] = m[3 * r] * h0 + m[3 * r + 1] * h1 + m[3 * r + 2] * h2;
-            } else {
+            else
                 w[3 * a + r] = cmul_conj(m[r], h0) + cmul_conj(m[3 + r], h1) + cmul_conj(m[6 + r], h2);
-            }
         }
     }
 }
@@ -139,13 +135,13 @@ __device__ __forceinline__ void clover_apply(const void* clover, int Vh, int par
 {
     using T = Traits<P>;
     using R = typename T::real;
-    const long base = (long)par * T::CLOVER_CHUNKS * Vh + i;
+    const long base = chunk_at(Vh, T::CLOVER_CHUNKS, par, 0, i);
     if constexpr (T::PER_CHUNK == 8) {
         // 16-bit storage: the 72 reals are 9 chunks; block 0 ends inside chunk 4
         R a[72];
 #pragma unroll
         for (int k = 0; k < T::CLOVER_CHUNKS; ++k) {
-            Chunk<P> c = load_chunk<P>(clover, base + (long)k * Vh);
+            Chunk<P> c = load_chunk<P>(clover, base + (long)k * kSB);
 #pragma unroll
             for (int j = 0; j < 8; ++j) a[8 * k + j] = to_real<P>(c.v[j]);
         }
@@ -158,7 +154,7 @@ __device__ __forceinline__ void clover_apply(const void* clover, int Vh, int par
             R a[36];
 #pragma unroll
             for (int k = 0; k < CPB; ++k) {
-                Chunk<P> c = load_chunk<P>(clover, base + (long)(b * CPB + k) * Vh);
+                Chunk<P> c = load_chunk<P>(clover, base + (long)(b * CPB + k) * kSB);
 #pragma unroll
                 for (int j = 0; j < T::PER_CHUNK; ++j) a[k * T::PER_CHUNK + j] = to_real<P>(c.v[j]);
             }
@@ -173,10 +169,10 @@ __device__ __forceinline__ void load_clover(const void* clover, int Vh, int par,
                                             typename Traits<P>::real a[72])
 {
     using T = Traits<P>;
-    const long base = (long)par * T::CLOVER_CHUNKS * Vh + i;
+    const long base = chunk_at(Vh, T::CLOVER_CHUNKS, par, 0, i);
 #pragma unroll
     for (int k = 0; k < T::CLOVER_CHUNKS; ++k) {
-        Chunk<P> c = load_chunk<P>(clover, base + (long)k * Vh);
+        Chunk<P> c = load_chunk<P>(clover, base + (long)k * kSB);
 #pragma unroll
         for (int j = 0; j < T::PER_CHUNK; ++j) a[k * T::PER_CHUNK + j] = to_real<P>(c.v[j]);
     }

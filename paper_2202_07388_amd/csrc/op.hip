@@ -141,8 +141,11 @@ __global__ void unitarity_kernel(const double* su3, long nlinks, unsigned long l
 
 // ------------------------------------------------------------------ link compression
 
+// A stored link is rows 0 and 1 of the full U(3) matrix U = exp(i theta) V and the phase
+// d = det U = exp(3 i theta): row 2 of U is d * conj(row0 x row1), since row 2 of V is
+// conj(v0 x v1) and u0 x u1 = exp(2 i theta) v0 x v1. No trigonometry at apply time.
 __global__ void pack_links_kernel(Geom g, const double* su3, const double* theta, void* l64,
-                                  void* t64, void* l32, void* t32, void* l16, void* lb16)
+                                  void* d64, void* l32, void* d32, void* l16, void* lb16)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int par = blockIdx.y;
@@ -153,31 +156,36 @@ __global__ void pack_links_kernel(Geom g, const double* su3, const double* theta
     const double* p = su3 + (((long)lex * 4 + mu) * 9) * 2;  // rows 0 and 1: 12 reals
     const double th = theta[(long)lex * 4 + mu];
     const long row = (long)(par * 4 + mu);
+    double s1, c1, s3, c3;
+    sincos(th, &s1, &c1);
+    sincos(3.0 * th, &s3, &c3);
     double r[12];
-    for (int k = 0; k < 12; ++k) r[k] = p[k];
-    // FP64: 6 chunks of one complex each
+    for (int k = 0; k < 6; ++k) {  // r = exp(i theta) * (rows 0, 1 of V)
+        const double a = p[2 * k], b = p[2 * k + 1];
+        r[2 * k] = c1 * a - s1 * b;
+        r[2 * k + 1] = c1 * b + s1 * a;
+    }
+    // FP64: 6 chunks of one complex each, d as a double2 array
     for (int k = 0; k < 6; ++k) {
         double2 v = {r[2 * k], r[2 * k + 1]};
-        ((double2*)l64)[(row * 6 + k) * g.Vh + i] = v;
+        ((double2*)l64)[chunk_at(g.Vh, 6, (int)row, k, i)] = v;
     }
-    ((double*)t64)[row * g.Vh + i] = th;
-    // FP32: 3 chunks of two complex each
+    ((double2*)d64)[row * g.Vh + i] = double2{c3, s3};
+    // FP32: 3 chunks of two complex each, d as a float2 array
     for (int k = 0; k < 3; ++k) {
         float4 v = {(float)r[4 * k], (float)r[4 * k + 1], (float)r[4 * k + 2], (float)r[4 * k + 3]};
-        ((float4*)l32)[(row * 3 + k) * g.Vh + i] = v;
+        ((float4*)l32)[chunk_at(g.Vh, 3, (int)row, k, i)] = v;
     }
-    ((float*)t32)[row * g.Vh + i] = (float)th;
-    // FP16 / BF16: 12 reals, then cos and sin of the angle, then two zeros
-    double s, c;
-    sincos(th, &s, &c);
+    ((float2*)d32)[row * g.Vh + i] = float2{(float)c3, (float)s3};
+    // FP16 / BF16: 12 reals, then d, then two zeros
     double e[16];
     for (int k = 0; k < 12; ++k) e[k] = r[k];
-    e[12] = c; e[13] = s; e[14] = 0.0; e[15] = 0.0;
+    e[12] = c3; e[13] = s3; e[14] = 0.0; e[15] = 0.0;
     _Float16* h = (_Float16*)l16;
     uint16_t* b = (uint16_t*)lb16;
     for (int k = 0; k < 2; ++k)
         for (int j = 0; j < 8; ++j) {
-            const long at = ((row * 2 + k) * g.Vh + i) * 8 + j;
+            const long at = chunk_at(g.Vh, 2, (int)row, k, i) * 8 + j;
             h[at] = (_Float16)e[8 * k + j];
             b[at] = float_to_bf16((float)e[8 * k + j]);
         }
@@ -267,7 +275,7 @@ __global__ void clover_kernel(Geom g, const double* su3, const double* theta, do
             }
     }
     for (int k = 0; k < 36; ++k)
-        out[((long)par * 36 + k) * g.Vh + i] = double2{reals[2 * k], reals[2 * k + 1]};
+        out[chunk_at(g.Vh, 36, par, k, i)] = double2{reals[2 * k], reals[2 * k + 1]};
 }
 
 // FP64 eo-SoA array of `nr` reals per site -> lower precision copies
@@ -278,9 +286,9 @@ __global__ void convert_site_reals(Geom g, int nr, const double* src, float* f32
     const int par = blockIdx.y;
     if (i >= g.Vh) return;
     for (int q = 0; q < nr; ++q) {
-        const double v = src[(((long)par * (nr / 2) + q / 2) * g.Vh + i) * 2 + q % 2];
-        f32[(((long)par * (nr / 4) + q / 4) * g.Vh + i) * 4 + q % 4] = (float)v;
-        const long a16 = (((long)par * (nr / 8) + q / 8) * g.Vh + i) * 8 + q % 8;
+        const double v = src[chunk_at(g.Vh, nr / 2, par, q / 2, i) * 2 + q % 2];
+        f32[chunk_at(g.Vh, nr / 4, par, q / 4, i) * 4 + q % 4] = (float)v;
+        const long a16 = chunk_at(g.Vh, nr / 8, par, q / 8, i) * 8 + q % 8;
         f16[a16] = (_Float16)v;
         b16[a16] = float_to_bf16((float)v);
     }
@@ -333,7 +341,7 @@ __global__ void pack_kernel<F16S>(Geom g, const double* can, void* eo)
     const double* p = can + (long)lex * 24;
     _Float16* h = (_Float16*)eo;
     for (int q = 0; q < 24; ++q)
-        h[(((long)par * 3 + q / 8) * g.Vh + i) * 8 + q % 8] = (_Float16)p[q];
+        h[chunk_at(g.Vh, 3, par, q / 8, i) * 8 + q % 8] = (_Float16)p[q];
 }
 
 // FP64 pack straight from canonical doubles (no float detour)
@@ -347,14 +355,14 @@ __global__ void pack_kernel<F64>(Geom g, const double* can, void* eo)
     eo_coords(g, par, i, x, lex);
     const double* p = can + (long)lex * 24;
     for (int k = 0; k < 12; ++k)
-        ((double2*)eo)[((long)par * 12 + k) * g.Vh + i] = double2{p[2 * k], p[2 * k + 1]};
+        ((double2*)eo)[chunk_at(g.Vh, 12, par, k, i)] = double2{p[2 * k], p[2 * k + 1]};
 }
 
 void free_op(qdw_op* op)
 {
     for (int p = 0; p < 4; ++p) {
         if (op->links[p]) (void)hipFree(op->links[p]);
-        if (op->theta[p]) (void)hipFree(op->theta[p]);
+        if (op->det[p]) (void)hipFree(op->det[p]);
         if (op->clover[p]) (void)hipFree(op->clover[p]);
     }
     if (op->partials) (void)hipFree(op->partials);
@@ -390,6 +398,11 @@ extern "C" int qdw_create(const qdw_lattice* lat, const double* su3, const doubl
     g.V = (int)V;
     g.Vh = (int)(V / 2);
     g.bc_t = lat->bc_t;
+    g.S = L[1] * L[2] * L[3] / 2;
+    g.ntile = (g.S + 127) / 128;
+    g.nt = 1;
+    for (int d = 1; d <= 8; ++d)
+        if (L[0] % d == 0) g.nt = d;
     op->m0 = m0;
     op->csw = csw;
     (void)hipGetDevice(&op->device);
@@ -425,21 +438,21 @@ extern "C" int qdw_create(const qdw_lattice* lat, const double* su3, const doubl
                                          std::to_string(wdev));
 
     // 2. compressed links in every precision
-    const size_t nl = (size_t)g.Vh * 2 * 4;  // links per array (both parities, 4 dirs)
+    const size_t nl = (size_t)padded(g.Vh) * 8;  // link slots per array (2 parities x 4 dirs)
     CREATE_HIP(hipMalloc(&op->links[F64], nl * 6 * 16));
-    CREATE_HIP(hipMalloc(&op->theta[F64], nl * 8));
+    CREATE_HIP(hipMalloc(&op->det[F64], nl * 16));
     CREATE_HIP(hipMalloc(&op->links[F32], nl * 3 * 16));
-    CREATE_HIP(hipMalloc(&op->theta[F32], nl * 4));
+    CREATE_HIP(hipMalloc(&op->det[F32], nl * 8));
     CREATE_HIP(hipMalloc(&op->links[F16S], nl * 2 * 16));
     CREATE_HIP(hipMalloc(&op->links[BF16S], nl * 2 * 16));
     dim3 gl((g.Vh + 255) / 256, 2, 4);
-    pack_links_kernel<<<gl, 256, 0, st>>>(g, su3, theta, op->links[F64], op->theta[F64],
-                                          op->links[F32], op->theta[F32], op->links[F16S],
+    pack_links_kernel<<<gl, 256, 0, st>>>(g, su3, theta, op->links[F64], op->det[F64],
+                                          op->links[F32], op->det[F32], op->links[F16S],
                                           op->links[BF16S]);
     CREATE_HIP(hipGetLastError());
 
     // 3. clover blocks (FP64) and their lower-precision copies
-    const size_t ns = (size_t)V;
+    const size_t ns = (size_t)padded(g.Vh) * 2;  // site slots of both parities
     CREATE_HIP(hipMalloc(&op->clover[F64], ns * 72 * 8));
     CREATE_HIP(hipMalloc(&op->clover[F32], ns * 72 * 4));
     CREATE_HIP(hipMalloc(&op->clover[F16S], ns * 72 * 2));

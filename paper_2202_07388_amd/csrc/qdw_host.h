@@ -12,10 +12,11 @@ struct qdw_op {
     qdw::Geom g;
     double m0, csw;
     int device;
-    // per precision (index = qdw::Prec): compressed links, U(1) angles (F64/F32 only),
-    // clover blocks
+    // per precision (index = qdw::Prec): compressed links (rows 0, 1 of the U(3) link),
+    // link phases exp(3 i theta) (F64: double2, F32: float2 arrays; the 16-bit formats
+    // keep them inside the link chunks), clover blocks
     void* links[4];
-    void* theta[4];
+    void* det[4];
     void* clover[4];
     // reduction scratch: per-workgroup partial sums and the final scalars
     double* partials;      // device, kMaxPartials * kMaxScalars doubles
@@ -34,7 +35,7 @@ void set_error(const std::string& msg);
 inline size_t spinor_bytes(const Geom& g, int prec)
 {
     const size_t r = prec == F64 ? 8 : prec == F32 ? 4 : 2;
-    return (size_t)g.V * 24 * r;
+    return (size_t)2 * padded(g.Vh) * 24 * r;
 }
 
 }  // namespace qdw

@@ -2,9 +2,9 @@
 //
 // Layout ("eo-SoA"): every per-site field is split by site parity (even sites first,
 // as in the paper's even-odd ordered operator, Sec. 3 / Fig. 3 left) and stored as
-// [parity][chunk][Vh] where a chunk is 16 bytes of one site's data. Consecutive lanes of
-// a wavefront therefore read consecutive 16-byte chunks: one fully coalesced 1 KiB
-// transaction per wave per chunk.
+// [parity][site/64][chunk][site%64] where a chunk is 16 bytes of one site's data (see
+// chunk_at). Consecutive lanes of a wavefront read consecutive 16-byte chunks: one
+// fully coalesced 1 KiB transaction per wave per chunk.
 //
 //   spinor  24 reals/site  (12 complex, index spin*3 + colour)
 //           F64: 12 chunks (1 complex each), F32: 6 (2 complex), F16/BF16: 3 (4 complex)
@@ -32,6 +32,9 @@ struct Geom {
     int stride[4]; // lexicographic strides
     int V, Vh;
     int bc_t;      // -1 antiperiodic, +1 periodic in time
+    int S;         // even-odd sites per time slice and parity (L1*L2*L3/2)
+    int ntile;     // 128-site tiles per time slice (ceil(S/128))
+    int nt;        // time slices per chunk of the workgroup walk (a divisor of T, <= 8)
 };
 
 // ---------------------------------------------------------------- scalar types
@@ -119,6 +122,23 @@ __device__ __forceinline__ Chunk<P> load_chunk_cached(const void* base, long idx
     return c;
 }
 
+// ---------------------------------------------------------------- AoSoA addressing
+//
+// A per-site field is stored in rows (a parity, or parity*4 + mu for links); a row holds
+// its sites in blocks of kSB = 64 consecutive even-odd indices, and a block stores chunk 0
+// of its 64 sites, then chunk 1, ...: [row][site/64][chunk][site%64]. A wavefront's 64
+// lanes read one contiguous 1 KiB run per chunk, and all chunks of one site lie within
+// one block of NC KiB (a few pages at most), which keeps address translation cheap.
+constexpr int kSB = 64;
+
+__host__ __device__ __forceinline__ int padded(int Vh) { return (Vh + kSB - 1) & ~(kSB - 1); }
+
+__host__ __device__ __forceinline__ long chunk_at(int Vh, int NC, int row, int k, int i)
+{
+    const unsigned u = (unsigned)i;
+    return (((long)row * (padded(Vh) / kSB) + (u / kSB)) * NC + k) * kSB + (u % kSB);
+}
+
 template <int P>
 __device__ __forceinline__ void store_chunk(void* base, long idx, const Chunk<P>& c)
 {
@@ -154,10 +174,10 @@ __device__ __forceinline__ void load_spinor(const void* f, int Vh, int par, int 
                                             cx<typename Traits<P>::real> s[12])
 {
     using T = Traits<P>;
-    const long base = (long)par * T::SPIN_CHUNKS * Vh + i;
+    const long base = chunk_at(Vh, T::SPIN_CHUNKS, par, 0, i);
 #pragma unroll
     for (int k = 0; k < T::SPIN_CHUNKS; ++k) {
-        Chunk<P> c = load_chunk_cached<P>(f, base + (long)k * Vh);
+        Chunk<P> c = load_chunk_cached<P>(f, base + (long)k * kSB);
 #pragma unroll
         for (int j = 0; j < T::PER_CHUNK / 2; ++j)
             s[k * (T::PER_CHUNK / 2) + j] = {to_real<P>(c.v[2 * j]), to_real<P>(c.v[2 * j + 1])};
@@ -169,7 +189,7 @@ __device__ __forceinline__ void store_spinor(void* f, int Vh, int par, int i,
                                              const cx<typename Traits<P>::real> s[12])
 {
     using T = Traits<P>;
-    const long base = (long)par * T::SPIN_CHUNKS * Vh + i;
+    const long base = chunk_at(Vh, T::SPIN_CHUNKS, par, 0, i);
 #pragma unroll
     for (int k = 0; k < T::SPIN_CHUNKS; ++k) {
         Chunk<P> c;
@@ -178,7 +198,7 @@ __device__ __forceinline__ void store_spinor(void* f, int Vh, int par, int i,
             c.v[2 * j] = to_store<P>(s[k * (T::PER_CHUNK / 2) + j].re);
             c.v[2 * j + 1] = to_store<P>(s[k * (T::PER_CHUNK / 2) + j].im);
         }
-        store_chunk<P>(f, base + (long)k * Vh, c);
+        store_chunk<P>(f, base + (long)k * kSB, c);
     }
 }
 
@@ -216,5 +236,26 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblk)
     const int x = bid & 7, k = bid >> 3;
     return x * q + (x < r ? x : r) + k;
 }
+
+// Workgroup walk of the site kernels: a workgroup handles one 128-site tile of one time
+// slice (T * ntile workgroups). Consecutive logical workgroups step through the nt time
+// slices of a chunk for one spatial tile before moving to the next tile, so the sites'
+// t +- 1 neighbours are loaded by workgroups running at the same time, and the x1 +- 1
+// neighbours (4 tiles away at 32^3) by workgroups a few dozen positions away -- on the
+// same XCD, whose L2 then serves the halo instead of HBM. Returns false for the lanes
+// of the last, ragged tile of a slice.
+__device__ __forceinline__ bool walk_site(const Geom& g, int logical, int lane, int& i)
+{
+    const int per_chunk = g.nt * g.ntile;
+    const int c = logical / per_chunk;
+    const int r = logical - c * per_chunk;
+    const int s = r / g.nt;
+    const int t = c * g.nt + (r - s * g.nt);
+    const int k = s * 128 + lane;
+    i = t * g.S + k;
+    return k < g.S;
+}
+
+inline int walk_blocks(const Geom& g) { return g.L[0] * g.ntile; }
 
 }  // namespace qdw

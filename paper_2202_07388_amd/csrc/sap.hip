@@ -52,12 +52,12 @@ constexpr int kBMax = 256;
 template <int SP, int MU>
 __device__ __forceinline__ void push_backward(float (*hb)[12][kBMax], const BlockGeom& B,
                                               const int l[4], int t, const cx<float> r[12],
-                                              const cx<float> u[6], cx<float> ph)
+                                              const cx<float> u[6], cx<float> d)
 {
     if (l[MU] < B.bs[MU] - 1) {
         cx<float> h[6], w[6];
         project<float, MU, +1>(r, h);
-        su3_apply<float, true>(u, scale(conj_(ph), -0.5f), h, w);
+        su3_mul<float, true>(u, d, h, w);
         const int dst = t + B.lstride[MU];
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
@@ -69,7 +69,7 @@ __device__ __forceinline__ void push_backward(float (*hb)[12][kBMax], const Bloc
 
 template <int SP, int MU>
 __device__ __forceinline__ void hop_forward(float (*rl)[kBMax], const BlockGeom& B, const int l[4],
-                                            int t, const cx<float> u[6], cx<float> ph,
+                                            int t, const cx<float> u[6], cx<float> d,
                                             cx<float> v[12])
 {
     if (l[MU] < B.bs[MU] - 1) {
@@ -78,7 +78,7 @@ __device__ __forceinline__ void hop_forward(float (*rl)[kBMax], const BlockGeom&
 #pragma unroll
         for (int c = 0; c < 12; ++c) s[c] = {rl[2 * c][src], rl[2 * c + 1][src]};
         project<float, MU, -1>(s, h);
-        su3_apply<float, false>(u, scale(ph, -0.5f), h, w);
+        su3_mul<float, false>(u, d, h, w);
         expand_add<float, MU, -1>(w, v);
     }
 }
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(256) void sap_mr_kernel(Geom g, BlockGeom B, int co
                                                      void* __restrict__ rs, void* __restrict__ psis,
                                                      void* __restrict__ delta,
                                                      const void* __restrict__ links,
-                                                     const void* __restrict__ theta,
+                                                     const void* __restrict__ dets,
                                                      const void* __restrict__ clover)
 {
     __shared__ float rl[24][kBMax];
@@ -137,9 +137,9 @@ __global__ __launch_bounds__(256) void sap_mr_kernel(Geom g, BlockGeom B, int co
     load_spinor<SP>(rs, g.Vh, par, i, r);
     float cl[72];
     load_clover<SP>(clover, g.Vh, par, i, cl);
-    cx<float> u[4][6], ph[4];
+    cx<float> u[4][6], d[4];
 #pragma unroll
-    for (int mu = 0; mu < 4; ++mu) load_link<SP>(links, theta, g.Vh, par, i, mu, u[mu], ph[mu]);
+    for (int mu = 0; mu < 4; ++mu) load_link<SP>(links, dets, g.Vh, par, i, mu, u[mu], d[mu]);
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
         chi[c] = {0.f, 0.f};
@@ -148,22 +148,27 @@ __global__ __launch_bounds__(256) void sap_mr_kernel(Geom g, BlockGeom B, int co
     }
     for (int k = 0; k < nmr; ++k) {
         __syncthreads();  // rl holds the current block residual
-        push_backward<SP, 0>(hb, B, l, t, r, u[0], ph[0]);
-        push_backward<SP, 1>(hb, B, l, t, r, u[1], ph[1]);
-        push_backward<SP, 2>(hb, B, l, t, r, u[2], ph[2]);
-        push_backward<SP, 3>(hb, B, l, t, r, u[3], ph[3]);
-        cx<float> v[12];
+        push_backward<SP, 0>(hb, B, l, t, r, u[0], d[0]);
+        push_backward<SP, 1>(hb, B, l, t, r, u[1], d[1]);
+        push_backward<SP, 2>(hb, B, l, t, r, u[2], d[2]);
+        push_backward<SP, 3>(hb, B, l, t, r, u[3], d[3]);
+        cx<float> v[12], vh[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) vh[c] = {0.f, 0.f};
+        hop_forward<SP, 0>(rl, B, l, t, u[0], d[0], vh);
+        hop_forward<SP, 1>(rl, B, l, t, u[1], d[1], vh);
+        hop_forward<SP, 2>(rl, B, l, t, u[2], d[2], vh);
+        hop_forward<SP, 3>(rl, B, l, t, u[3], d[3], vh);
+        __syncthreads();  // every pushed half spinor is in hb
+        hop_backward<0>(hb, l, t, vh);
+        hop_backward<1>(hb, l, t, vh);
+        hop_backward<2>(hb, l, t, vh);
+        hop_backward<3>(hb, l, t, vh);
+        // v = D_b r = A r - 1/2 (hops inside the block)
         herm6_apply<float>(cl, r, v);
         herm6_apply<float>(cl + 36, r + 6, v + 6);
-        hop_forward<SP, 0>(rl, B, l, t, u[0], ph[0], v);
-        hop_forward<SP, 1>(rl, B, l, t, u[1], ph[1], v);
-        hop_forward<SP, 2>(rl, B, l, t, u[2], ph[2], v);
-        hop_forward<SP, 3>(rl, B, l, t, u[3], ph[3], v);
-        __syncthreads();  // every pushed half spinor is in hb
-        hop_backward<0>(hb, l, t, v);
-        hop_backward<1>(hb, l, t, v);
-        hop_backward<2>(hb, l, t, v);
-        hop_backward<3>(hb, l, t, v);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) v[c] = v[c] - scale(vh[c], 0.5f);
         // omega = (v, r) / (v, v) over the block
         float nre = 0.f, nim = 0.f, den = 0.f;
 #pragma unroll
@@ -215,21 +220,22 @@ __global__ __launch_bounds__(256) void sap_mr_kernel(Geom g, BlockGeom B, int co
     store_spinor<SP>(rs, g.Vh, par, i, r);
 }
 
-// r(x) -= (D delta)(x) restricted to the hops that enter x's block from outside, for
-// every site x of a block of colour 1 - `colour` (delta lives on the colour blocks)
+// acc += the hops of D delta that enter x's block from outside (without the -1/2), for
+// a site x of a block of colour 1 - `colour` (delta lives on the colour blocks)
 template <int SP, int MU>
 __device__ __forceinline__ void cross_hops(const Geom& g, const BlockGeom& B, const void* delta,
-                                           const void* links, const void* theta, int par, int i,
+                                           const void* links, const void* dets, int par, int i,
                                            const int x[4], int lex, cx<float> acc[12], bool& any)
 {
-    cx<float> s[12], h[6], w[6], u[6], ph;
+    cx<float> s[12], h[6], w[6], u[6], d;
     if (x[MU] % B.bs[MU] == B.bs[MU] - 1) {
         const int j = lex_fwd(g, x, lex, MU) >> 1;
         load_spinor<SP>(delta, g.Vh, 1 - par, j, s);
         project<float, MU, -1>(s, h);
-        load_link<SP>(links, theta, g.Vh, par, i, MU, u, ph);
-        const float sg = (MU == 0 && x[0] == g.L[0] - 1) ? -0.5f * g.bc_t : -0.5f;
-        su3_apply<float, false>(u, scale(ph, sg), h, w);
+        if (MU == 0 && g.bc_t < 0 && x[0] == g.L[0] - 1)
+            for (int c = 0; c < 6; ++c) h[c] = {-h[c].re, -h[c].im};
+        load_link<SP>(links, dets, g.Vh, par, i, MU, u, d);
+        su3_mul<float, false>(u, d, h, w);
         expand_add<float, MU, -1>(w, acc);
         any = true;
     }
@@ -237,25 +243,26 @@ __device__ __forceinline__ void cross_hops(const Geom& g, const BlockGeom& B, co
         const int j = lex_bwd(g, x, lex, MU) >> 1;
         load_spinor<SP>(delta, g.Vh, 1 - par, j, s);
         project<float, MU, +1>(s, h);
-        load_link<SP>(links, theta, g.Vh, 1 - par, j, MU, u, ph);
-        const float sg = (MU == 0 && x[0] == 0) ? -0.5f * g.bc_t : -0.5f;
-        su3_apply<float, true>(u, scale(conj_(ph), sg), h, w);
+        if (MU == 0 && g.bc_t < 0 && x[0] == 0)
+            for (int c = 0; c < 6; ++c) h[c] = {-h[c].re, -h[c].im};
+        load_link<SP>(links, dets, g.Vh, 1 - par, j, MU, u, d);
+        su3_mul<float, true>(u, d, h, w);
         expand_add<float, MU, +1>(w, acc);
         any = true;
     }
 }
 
+// r(x) -= (D delta)(x) over the hops that enter x's block from outside
 template <int SP>
 __global__ __launch_bounds__(256) void sap_boundary_kernel(Geom g, BlockGeom B, int colour,
                                                            void* __restrict__ rs,
                                                            const void* __restrict__ delta,
                                                            const void* __restrict__ links,
-                                                           const void* __restrict__ theta)
+                                                           const void* __restrict__ dets)
 {
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int par = threadIdx.x >> 7;
-    const int i = tile * 128 + (threadIdx.x & 127);
-    if (i >= g.Vh) return;
+    int i;
+    if (!walk_site(g, xcd_tile(blockIdx.x, gridDim.x), threadIdx.x & 127, i)) return;
     int x[4], lex;
     eo_coords(g, par, i, x, lex);
     const int bc = (x[0] / B.bs[0] + x[1] / B.bs[1] + x[2] / B.bs[2] + x[3] / B.bs[3]) & 1;
@@ -264,15 +271,15 @@ __global__ __launch_bounds__(256) void sap_boundary_kernel(Geom g, BlockGeom B, 
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc[c] = {0.f, 0.f};
     bool any = false;
-    cross_hops<SP, 0>(g, B, delta, links, theta, par, i, x, lex, acc, any);
-    cross_hops<SP, 1>(g, B, delta, links, theta, par, i, x, lex, acc, any);
-    cross_hops<SP, 2>(g, B, delta, links, theta, par, i, x, lex, acc, any);
-    cross_hops<SP, 3>(g, B, delta, links, theta, par, i, x, lex, acc, any);
+    cross_hops<SP, 0>(g, B, delta, links, dets, par, i, x, lex, acc, any);
+    cross_hops<SP, 1>(g, B, delta, links, dets, par, i, x, lex, acc, any);
+    cross_hops<SP, 2>(g, B, delta, links, dets, par, i, x, lex, acc, any);
+    cross_hops<SP, 3>(g, B, delta, links, dets, par, i, x, lex, acc, any);
     if (!any) return;
     cx<float> r[12];
     load_spinor<SP>(rs, g.Vh, par, i, r);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) r[c] = r[c] - acc[c];
+    for (int c = 0; c < 12; ++c) r[c] = r[c] + scale(acc[c], 0.5f);  // hops carry -1/2
     store_spinor<SP>(rs, g.Vh, par, i, r);
 }
 
@@ -293,15 +300,15 @@ int sap_impl(qdw_op* op, const void* rho, void* phi, double rho_norm, int ncy, i
     const double s = std::sqrt(24.0 * g.V) / rho_norm;
     if ((rc = run_map(op, ScaleNorm<F64, SP>{rho, rs, s, g.Vh}, st, op->scalars + S_SAP))) return rc;
     if ((rc = run_map(op, Zero<SP>{psis, g.Vh}, st))) return rc;
-    const int nbdw = (g.Vh + 127) / 128;
+    const int nbdw = walk_blocks(g);
     for (int cy = 0; cy < ncy; ++cy)
         for (int c = 0; c < 2; ++c) {
             sap_mr_kernel<SP><<<B.nblk / 2, B.bvol, 0, st>>>(g, B, c, nmr, rs, psis, delta,
-                                                             op->links[SP], op->theta[SP],
+                                                             op->links[SP], op->det[SP],
                                                              op->clover[SP]);
             QDW_LAUNCH_CHECK();
             sap_boundary_kernel<SP><<<nbdw, 256, 0, st>>>(g, B, c, rs, delta, op->links[SP],
-                                                          op->theta[SP]);
+                                                          op->det[SP]);
             QDW_LAUNCH_CHECK();
         }
     return run_map(op, Axpby<SP, F64>{psis, phi, 1.0 / s, 0.0, g.Vh}, st);

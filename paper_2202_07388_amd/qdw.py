@@ -188,7 +188,7 @@ class Op:
         c = torch.as_tensor(canonical).to(self.device, dtype=torch.complex128).contiguous()
         if c.numel() != self.V * 12:
             raise QdwError("spinor shape does not match the lattice")
-        out = self.new_field(prec, zero=False) if out is None else out
+        out = self.new_field(prec) if out is None else out
         _check(load().qdw_pack(self._h, _ptr(torch.view_as_real(c)), _ptr(out), PREC[prec],
                                _stream()), "qdw_pack")
         return out
