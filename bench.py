@@ -1,20 +1,25 @@
-"""Benchmark of the Wilson-clover operator on one MI355X.
+"""Benchmark of the Wilson-clover operator and its solvers on one MI355X.
 
-Workload: 32^3 x 64 lattice (V = 2,097,152 sites), near-identity SU(3) x U(1) links
-(eps = 0.3, U(1) eps = 0.1), m0 = -0.05, c_sw = 1.7, antiperiodic time, Gaussian source.
-A timed step is one application of D in FP64 with 12-real compressed links (+ U(1)
-angle); ``value`` is its throughput in GB/s of algorithmic HBM bytes (1376 B per site:
-spinor in and out, 4 links of 13 reals, 72 clover reals, each read once).
+Timed steps (the `value`): one application of D in FP64 at 32^3 x 64 (V = 2,097,152
+sites), near-identity SU(3) x U(1) links (eps = 0.3, U(1) eps = 0.1), m0 = -0.05,
+c_sw = 1.7, antiperiodic time, Gaussian source; throughput in GB/s of algorithmic HBM
+bytes (1376 B per site: spinor in and out, 4 links of 12 + 1 reals, 72 clover reals,
+each read once), inputs resident in HBM.
 
-Also reported (timed separately, outside the K steps): D in FP32 and FP16 storage, the
-solves to FP64 true residual 1e-10 (plain FP64 against the mixed-precision / SAP
-forms), and the FP64 oracle timed on the host's cores on a bounded sample.
+Also reported, each timed on its own outside the K steps:
+  * D in FP32 and FP16 storage, D^+ in FP64;
+  * the 32^3 x 64 normal-equation solve to FP64 true residual 1e-10: plain FP64 CG
+    against FP32 and FP16 regular steps with FP64 reset steps;
+  * the 24^3 x 48 solve of D psi = eta to 1e-10 (eps = 0.35, m0 = -0.08): plain FP64 GCR
+    against SAP-preconditioned GCR (4^4 blocks, 5 cycles, 4 MR steps, FP16 and FP32);
+  * the FP64 oracle timed on the host on a bounded sample (cpu_baseline).
 
-Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-solves]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -29,19 +34,41 @@ HBM_PEAK_GBS = 8000.0
 DIMS = (64, 32, 32, 32)
 M0, CSW, EPS, EPS_U1 = -0.05, 1.7, 0.3, 0.1
 SEED = 7388 + 10
+SAP_DIMS = (48, 24, 24, 24)
+SAP_M0, SAP_EPS, SAP_SEED = -0.08, 0.35, 7388 + 20
 # algorithmic bytes per site of one application of D (each datum read once)
 BYTES_PER_SITE = {"f64": 1376, "f32": 688, "f16": 344}
+# HBM traffic measured with rocprofv3 counters for the FP64 kernel (profiles/); reported
+# only while the kernel sources are the ones it was measured on
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dw_f64_32c64_traffic.json")
+KERNEL_SOURCES = ["paper_2202_07388_amd/csrc/dirac.hip", "paper_2202_07388_amd/csrc/dirac_core.h",
+                  "paper_2202_07388_amd/csrc/qdw_internal.h"]
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def time_launches(fn, n, stream=None):
-    """Average duration of n launches of fn, bracketed by HIP events on the stream the
-    library launches on (torch's current stream)."""
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    return t.get("bytes_per_launch") if t.get("kernel_hash") == kernel_hash() else None
+
+
+def time_launches(fn, n):
+    """Average duration of n launches of fn, bracketed by HIP events recorded on the stream
+    the library launches on (torch's current stream)."""
     import torch
-    s = torch.cuda.current_stream() if stream is None else stream
+    s = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(s)
     for _ in range(n):
@@ -51,12 +78,12 @@ def time_launches(fn, n, stream=None):
     return e0.elapsed_time(e1) / 1e3 / n
 
 
-def cpu_baseline(su3_small_dims=(8, 32, 32, 32)):
+def cpu_baseline():
     """The FP64 oracle's D on a bounded sample: an 8 x 32^3 slab (1/8 of the volume) of
     the same field recipe, 3 applications, clover build excluded."""
     import oracle
     from paper_2202_07388_amd import synthetic as syn
-    dims = su3_small_dims
+    dims = (8, 32, 32, 32)
     su3, th = syn.gauge_field(dims, EPS, EPS_U1, SEED)
     op = oracle.Operator(dims, su3, th, M0, CSW, -1)
     psi = syn.gaussian_spinor(dims, SEED + 1000)
@@ -69,9 +96,45 @@ def cpu_baseline(su3_small_dims=(8, 32, 32, 32)):
     V = int(np.prod(dims))
     return {"value": round(BYTES_PER_SITE["f64"] * V / dt / 1e9, 3), "unit": "GB/s",
             "cores": 1, "kind": "oracle",
-            "sample": "oracle D (FP64, single thread) on an 8x32^3 slab of the same "
-                      "recipe, mean of 3 applies, clover build excluded; %.3f s per apply"
-                      % dt}
+            "sample": "oracle D (FP64, one thread) on an 8x32^3 slab of the same recipe, "
+                      "mean of 3 applications, clover build excluded; %.3f s each" % dt}
+
+
+def solve_record(info):
+    return {"s": round(info["t_sec"], 4), "steps": info["n_steps"], "status": info["status"],
+            "resets_or_restarts": info["nreset"], "rel_res_true": info["rel_res_true"],
+            "dw_fp64": info["n_dw_hi"], "dw_low": info["n_dw_lo"]}
+
+
+def cgne_solves(op, qdw, psi):
+    """Plain FP64 CG against mixed precision, D^+ D psi = eta to 1e-10 (32^3 x 64)."""
+    eta = op.pack(psi, "f64")
+    out = {}
+    for inner in ("f64", "f32", "f16"):
+        x = op.new_field("f64")
+        info = qdw.cgne_solve(op, eta, x, res=1e-10, nmx=20000, inner=inner)
+        out[inner] = solve_record(info)
+        log("  cgne %s: %s" % (inner, out[inner]))
+    return out
+
+
+def gcr_solves(qdw, syn):
+    """Plain FP64 GCR against SAP-GCR, D psi = eta to 1e-10 (24^3 x 48)."""
+    su3, th = syn.gauge_field(SAP_DIMS, SAP_EPS, EPS_U1, SAP_SEED)
+    op = qdw.Op(SAP_DIMS, su3, th, SAP_M0, CSW, -1)
+    del su3, th
+    eta = op.pack(syn.gaussian_spinor(SAP_DIMS, SAP_SEED + 1000), "f64")
+    out = {}
+    for name, kw in (("plain_fp64", dict(precond="none")),
+                     ("sap_fp16", dict(precond="sap", sdtype="f16")),
+                     ("sap_fp32", dict(precond="sap", sdtype="f32"))):
+        x = op.new_field("f64")
+        info = qdw.sap_gcr_solve(op, eta, x, res=1e-10, nmx=5000, nkv=16, ncy=5, nmr=4,
+                                 bs=(4, 4, 4, 4), **kw)
+        out[name] = solve_record(info)
+        log("  gcr %s: %s" % (name, out[name]))
+    op.close()
+    return out
 
 
 def main():
@@ -81,6 +144,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solves", action="store_true")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="also run a plain elementwise kernel that reads and writes 1 GiB "
+                         "(3 launches), to scale hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -95,19 +161,17 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     qdw.load()
-    log("generating 32^3x64 gauge field ...")
+    log("generating the 32^3x64 gauge field ...")
     t0 = time.time()
     su3, th = syn.gauge_field(DIMS, EPS, EPS_U1, SEED)
     psi = syn.gaussian_spinor(DIMS, SEED + 1000)
-    log("  %.1f s; creating operator" % (time.time() - t0))
+    log("  %.1f s; creating the operator" % (time.time() - t0))
     op = qdw.Op(DIMS, su3, th, M0, CSW, -1)
     del su3, th
     V = op.V
     fields = {}
     for prec in ("f64", "f32", "f16"):
-        x = op.pack(psi, prec)
-        y = op.new_field(prec)
-        fields[prec] = (x, y)
+        fields[prec] = (op.pack(psi, prec), op.new_field(prec))
     torch.cuda.synchronize()
 
     x64, y64 = fields["f64"]
@@ -124,21 +188,30 @@ def main():
     wall = time.perf_counter() - t_wall0
     gbs = BYTES_PER_SITE["f64"] * V / dt / 1e9
 
-    extra = {}
+    other = {}
     for prec in ("f32", "f16"):
         x, y = fields[prec]
         f = lambda: qdw.dw_apply(op, x, y, prec)
         for _ in range(10):
             f()
         d = time_launches(f, 100)
-        extra[prec] = {"ms": round(d * 1e3, 4),
+        other[prec] = {"ms": round(d * 1e3, 4),
                        "GB_s": round(BYTES_PER_SITE[prec] * V / d / 1e9, 1),
                        "frac_hbm_peak": round(BYTES_PER_SITE[prec] * V / d / 1e9 / HBM_PEAK_GBS, 4)}
-    dag = lambda: qdw.dw_dag_apply(op, x64, y64, "f64")
-    d_dag = time_launches(dag, 50)
-    extra["f64_dag"] = {"ms": round(d_dag * 1e3, 4),
+    d_dag = time_launches(lambda: qdw.dw_dag_apply(op, x64, y64, "f64"), 50)
+    other["f64_dag"] = {"ms": round(d_dag * 1e3, 4),
                         "GB_s": round(BYTES_PER_SITE["f64"] * V / d_dag / 1e9, 1)}
+    del fields
 
+    if args.calibrate:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.mul(a, 2.0, out=b)
+        torch.cuda.synchronize()
+        del a, b
+
+    traffic = measured_traffic()
     out = {
         "metric": "Dw GB/s (% HBM peak) at 32^3x64; solve s to rel res 1e-10, plain vs chosen",
         "value": round(gbs, 2),
@@ -152,14 +225,20 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "Wilson-clover D, 32^3x64, FP64, 12+1-real links",
+        "config": {"workload": "Wilson-clover D, 32^3x64, FP64, two-row compressed links",
                    "lattice": "32^3x64", "m0": M0, "c_sw": CSW, "eps": EPS,
                    "eps_u1": EPS_U1, "bc_t": "antiperiodic"},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None},
-        "dw_other_precisions": extra,
+                     "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "traffic": traffic},
+        "dw_other_precisions": other,
         "wall_s_timed_region": round(wall, 4),
     }
+    if not args.no_solves:
+        log("solves ...")
+        out["cgne_32c64"] = cgne_solves(op, qdw, psi)
+        op.close()
+        out["sap_gcr_24c48"] = gcr_solves(qdw, syn)
     if not args.no_cpu_baseline:
         log("timing the oracle on the host (bounded sample) ...")
         out["cpu_baseline"] = cpu_baseline()
