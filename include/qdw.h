@@ -102,6 +102,21 @@ int qdw_unpack(const qdw_op* op, const void* eo, double* canonical, qdw_prec pre
 int dw_apply(qdw_op* op, const void* in, void* out, qdw_prec prec, void* stream);
 int dw_dag_apply(qdw_op* op, const void* in, void* out, qdw_prec prec, void* stream);
 
+/* Fused BLAS-1 on eo-SoA fields of one precision (device), every reduction accumulated in
+ * binary64 (Sec. 2.1: reduction variables in binary64 whatever the working type) in a
+ * fixed order, so results are bitwise reproducible. qdw_norm2 and qdw_cdot write their
+ * result to host memory and synchronise the stream.
+ *   qdw_axpby: y = a x + b y (real a, b)
+ *   qdw_norm2: *out = |x|^2
+ *   qdw_cdot:  out[0] + i out[1] = x^+ y */
+int qdw_axpby(qdw_op* op, double a, const void* x, double b, void* y, qdw_prec prec,
+              void* stream);
+int qdw_norm2(qdw_op* op, const void* x, qdw_prec prec, double* out, void* stream);
+int qdw_cdot(qdw_op* op, const void* x, const void* y, qdw_prec prec, double* out, void* stream);
+/* y = s x between precisions (distinct fields; down-conversion rounds to nearest even) */
+int qdw_convert(qdw_op* op, const void* x, qdw_prec px, void* y, qdw_prec py, double s,
+                void* stream);
+
 /* Result of a solve. */
 typedef struct {
     int status;          /* >= 0: converged, number of regular steps (the paper's `status`,
@@ -184,6 +199,41 @@ size_t qdw_sap_gcr_workspace_bytes(const qdw_op* op, const qdw_sap_gcr_params* p
  * sweeps of the full lattice per preconditioner application. Synchronises the stream. */
 int sap_gcr_solve(qdw_op* op, const void* eta, void* psi, const qdw_sap_gcr_params* prm,
                   void* work, size_t work_bytes, qdw_info* info, void* stream);
+
+/* ---- learned gauge-covariant preconditioner (not from the paper) ----------------------
+ * Three linear parallel-transport layers, 1 -> 8 -> 8 -> 1 spinor channels:
+ *   out_a(x) = sum_{p=0..8} sum_b W_p[a][b] (T_p in_b)(x),
+ *   T_0 = 1, T_{+mu} v(x) = s U_mu(x) v(x+mu), T_{-mu} v(x) = s U_mu(x-mu)^+ v(x-mu),
+ * path order p = 0, +t, -t, +x1, -x1, +x2, -x2, +x3, -x3; W_p[a][b] a complex 4x4 spin
+ * matrix, so the network commutes with gauge transformations. Weights (device, FP32
+ * complex, interleaved re/im): layer after layer, each [9][Cout][Cin][4][4] (spin row,
+ * spin column), qdw_nn_weight_count() complex numbers in all. Channel mixing runs on the
+ * matrix cores: bf16 operands with FP32 accumulation, or FP32 operands when
+ * f32_mixing != 0 (for gradient checks). Gradients are real gradients:
+ * dL/dRe z + i dL/dIm z. Used by sap_gcr_solve with QDW_PRECOND_NN / QDW_PRECOND_NN_SAP. */
+int qdw_nn_weight_count(void);
+/* device workspace of nn_forward (training = 0) or nn_backward (training = 1) */
+size_t qdw_nn_workspace_bytes(const qdw_op* op, int training);
+/* out = N(in); in, out FP64 eo-SoA fields (device) */
+int nn_forward(qdw_op* op, const float* weights, const void* in, void* out, int f32_mixing,
+               void* work, size_t work_bytes, void* stream);
+/* For L with real gradient gout = dL/dRe N(in) + i dL/dIm N(in) (FP64 field): dW (device,
+ * 2 * qdw_nn_weight_count() floats, overwritten) and gin = dL/dRe in + i dL/dIm in. */
+int nn_backward(qdw_op* op, const float* weights, const void* in, const void* gout, float* dW,
+                void* gin, int f32_mixing, void* work, size_t work_bytes, void* stream);
+/* One Adam step (beta 0.9, 0.999, eps 1e-8, step >= 1, lr) on the batch mean of the loss
+ * over nbatch (residual rho_k, error err_k = D^-1 rho_k) pairs of eo-SoA fields of
+ * precision pair_prec (QDW_F64, QDW_F32 or QDW_BF16S; host arrays of device pointers):
+ *   loss_kind 0: |N(rho) - err|^2 / |err|^2            (error space)
+ *   loss_kind 1: |D (N(rho) - err)|^2 / |D err|^2      (the same error in the D-norm, i.e.
+ *                the residual |D N(rho) - rho| a GCR step would leave; gradient through
+ *                D^+ D with the library's FP32 operator)
+ * Weights updated in place; adam: 4 * qdw_nn_weight_count() floats of state (zero before
+ * step 1); *loss (host) = the batch loss before the update. work: at least
+ * qdw_nn_workspace_bytes(op, 1) + 8 * qdw_nn_weight_count() + 512 bytes. */
+int nn_train_step(qdw_op* op, float* weights, float* adam, int step, double lr,
+                  const void* const* rho, const void* const* err, int nbatch, qdw_prec pair_prec,
+                  int loss_kind, double* loss, void* work, size_t work_bytes, void* stream);
 
 /* Device workspace (bytes) of sap_apply for storage precision sdtype. */
 size_t qdw_sap_workspace_bytes(const qdw_op* op, qdw_prec sdtype);

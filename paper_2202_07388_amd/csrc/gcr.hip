@@ -276,7 +276,9 @@ int gcr_impl(qdw_op* op, const void* eta, void* psi, const qdw_sap_gcr_params& p
                                                    hs[G_A + 2 * (kMaxKv * j + i) + 1]);
                     s -= rij * al[j];
                 }
-                al[i] = s / hs[G_B + i];
+                // a preconditioner output with D phi_i in the span of the previous chi
+                // (b_i = 0, then also c_i = 0) contributes nothing
+                al[i] = hs[G_B + i] > 0.0 ? s / hs[G_B + i] : std::complex<double>(0.0, 0.0);
             }
             TRY(dispatch_k<MultiAxpy>(k, op, st, [&](auto& f) {
                 f.psi = psi;

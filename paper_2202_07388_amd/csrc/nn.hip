@@ -1,13 +1,727 @@
-// nn.hip -- learned gauge-covariant preconditioner (parallel-transport layers).
+// nn.hip -- a learned gauge-covariant preconditioner for flexible GCR (not from the paper;
+// the paper's solvers tolerate any preconditioner that changes from step to step).
+//
+// Network: three linear parallel-transport layers with 1 -> 8 -> 8 -> 1 spinor channels.
+// A layer maps channels in_b to
+//     out_a(x) = sum_{p=0..8} sum_b W_p[a][b] (T_p in_b)(x)
+// with T_0 = 1, T_{+mu} v(x) = s U_mu(x) v(x+mu), T_{-mu} v(x) = s U_mu(x-mu)^+ v(x-mu)
+// (s the fermion boundary sign) and W_p[a][b] a complex 4x4 matrix acting on spin only,
+// so the network commutes with gauge transformations.
+//
+// GPU mapping of a layer: (1) a transport kernel writes, for every site x and colour c,
+// one row of the matrix A[(x, c)][(p, b, t, re/im)] (t a spin index); (2) the channel
+// mixing is the real GEMM out[(x, c)][(a, s, re/im)] = A B with B the real embedding of the
+// complex weights, run on the matrix cores: bf16 operands and FP32 accumulation
+// (v_mfma_f32_16x16x16_bf16), or FP32 operands (v_mfma_f32_16x16x4_f32) for gradient
+// checks. Backward: dA = G B^T (matrix cores), then the adjoint transport gathers dA back
+// to the input channels; dB = A^T G (matrix cores, split over rows, fixed-order reduction)
+// gives the weight gradient. Adam updates FP32 master weights.
+#include <cmath>
+#include <vector>
+
 #include "blas.h"
+#include "dirac_core.h"
 
 namespace qdw {
 
-size_t nn_precond_workspace(const qdw_op*) { return 0; }
+namespace {
 
-int nn_precondition(qdw_op*, const void*, const void*, void*, double, char*, hipStream_t)
+constexpr int kPaths = 9;
+constexpr int kLayers = 3;
+constexpr int kCh[kLayers + 1] = {1, 8, 8, 1};
+constexpr int kMaxK = 72 * 8;   // 9 paths x 8 channels x 4 spins x 2
+constexpr int kMaxN = 64;       // 8 channels x 4 spins x 2
+
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+inline int layer_K(int l) { return (kPaths * kCh[l] * 8 + 15) & ~15; }
+inline int layer_N(int l) { return std::max(16, kCh[l + 1] * 8); }
+inline int layer_w_offset(int l)  // in complex numbers
 {
-    QDW_CHECK(false, QDW_EINVAL, "the learned preconditioner is not available in this build");
+    int o = 0;
+    for (int j = 0; j < l; ++j) o += kPaths * kCh[j] * kCh[j + 1] * 16;
+    return o;
+}
+inline int total_weights() { return layer_w_offset(kLayers); }
+
+inline long rows_of(const Geom& g) { return (long)2 * padded(g.Vh) * 3; }
+inline long rows_padded(const Geom& g) { return (rows_of(g) + 63) & ~63L; }
+
+__device__ __forceinline__ uint16_t bf16_bits(float f) { return float_to_bf16(f); }
+
+template <bool F32M>
+__device__ __forceinline__ void put_el(void* A, long at, float v)
+{
+    if (F32M) ((float*)A)[at] = v;
+    else ((uint16_t*)A)[at] = bf16_bits(v);
+}
+
+// one complex component (spin s, colour c) of an FP32 eo-SoA field at site (par, i)
+__device__ __forceinline__ long f32_addr(int Vh, int par, int i, int s, int c)
+{
+    const int k12 = s * 3 + c;
+    return chunk_at(Vh, 6, par, k12 >> 1, i) * 4 + (k12 & 1) * 2;
+}
+
+// ------------------------------------------------------------------ transport
+//
+// A[(q, c)][((p*Cin + b)*4 + t)*2 + re/im] = (T_p in_b)(q)[t][c], q = par*Vp + i.
+template <bool F32M>
+__global__ __launch_bounds__(256) void nn_transport_kernel(Geom g, int Cin, int Kpad,
+                                                           const float* const* in, void* A,
+                                                           const void* links, const void* dets)
+{
+    const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int Vp = padded(g.Vh);
+    const long nq = 2L * Vp;
+    if (tid >= nq * Cin) return;
+    const int b = (int)(tid / nq);
+    const long q = tid - (long)b * nq;
+    const int par = (int)(q / Vp), i = (int)(q - (long)par * Vp);
+    if (i >= g.Vh) return;  // padded sites keep their zero rows
+    int x[4], lex;
+    eo_coords(g, par, i, x, lex);
+    const float* v = in[b];
+    for (int p = 0; p < kPaths; ++p) {
+        cx<float> s[12], w[12];
+        if (p == 0) {
+            load_spinor<F32>(v, g.Vh, par, i, s);
+            for (int k = 0; k < 12; ++k) w[k] = s[k];
+        } else {
+            const int mu = (p - 1) >> 1;
+            const bool fwd = ((p - 1) & 1) == 0;
+            const int j = (fwd ? lex_fwd(g, x, lex, mu) : lex_bwd(g, x, lex, mu)) >> 1;
+            load_spinor<F32>(v, g.Vh, 1 - par, j, s);
+            cx<float> u[6], d;
+            float sg = 1.f;
+            if (fwd) {
+                load_link<F32>(links, dets, g.Vh, par, i, mu, u, d);
+                if (mu == 0 && x[0] == g.L[0] - 1) sg = (float)g.bc_t;
+            } else {
+                load_link<F32>(links, dets, g.Vh, 1 - par, j, mu, u, d);
+                if (mu == 0 && x[0] == 0) sg = (float)g.bc_t;
+            }
+            // the SU(3) multiply of dirac_core acts on two spin components at a time
+            cx<float> h[6], o[6];
+            for (int half = 0; half < 2; ++half) {
+                for (int k = 0; k < 6; ++k) h[k] = scale(s[6 * half + k], sg);
+                if (fwd) su3_mul<float, false>(u, d, h, o);
+                else su3_mul<float, true>(u, d, h, o);
+                for (int k = 0; k < 6; ++k) w[6 * half + k] = o[k];
+            }
+        }
+        // rows (q, c): 8 consecutive entries (t, re/im) for this (p, b)
+        const int k0 = ((p * Cin + b) * 4) * 2;
+        for (int c = 0; c < 3; ++c) {
+            const long row = (q * 3 + c) * (long)Kpad + k0;
+            for (int t = 0; t < 4; ++t) {
+                put_el<F32M>(A, row + 2 * t, w[t * 3 + c].re);
+                put_el<F32M>(A, row + 2 * t + 1, w[t * 3 + c].im);
+            }
+        }
+    }
+}
+
+// g_b(x) = sum_p T_p^+ dA[p][b](x): T_{+mu}^+ = T_{-mu}, T_{-mu}^+ = T_{+mu}
+__global__ __launch_bounds__(256) void nn_transport_adj_kernel(Geom g, int Cin, int Kpad,
+                                                               const float* dA, float* const* gout,
+                                                               const void* links, const void* dets)
+{
+    const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int Vp = padded(g.Vh);
+    const long nq = 2L * Vp;
+    if (tid >= nq * Cin) return;
+    const int b = (int)(tid / nq);
+    const long q = tid - (long)b * nq;
+    const int par = (int)(q / Vp), i = (int)(q - (long)par * Vp);
+    if (i >= g.Vh) return;
+    int x[4], lex;
+    eo_coords(g, par, i, x, lex);
+    cx<float> acc[12];
+    auto rows = [&](long qq, int p, cx<float> w[12]) {
+        const int k0 = ((p * Cin + b) * 4) * 2;
+        for (int c = 0; c < 3; ++c) {
+            const float* r = dA + (qq * 3 + c) * (long)Kpad + k0;
+            for (int t = 0; t < 4; ++t) w[t * 3 + c] = {r[2 * t], r[2 * t + 1]};
+        }
+    };
+    rows(q, 0, acc);
+    for (int mu = 0; mu < 4; ++mu) {
+        for (int dir = 0; dir < 2; ++dir) {
+            // dir 0: the +mu path of site y = x - mu lands here through U_mu(y)^+
+            // dir 1: the -mu path of site y = x + mu lands here through U_mu(x)
+            const bool from_below = dir == 0;
+            const int ylex = from_below ? lex_bwd(g, x, lex, mu) : lex_fwd(g, x, lex, mu);
+            const long yq = (long)(1 - par) * Vp + (ylex >> 1);
+            cx<float> w[12], u[6], d, h[6], o[6];
+            rows(yq, from_below ? 1 + 2 * mu : 2 + 2 * mu, w);
+            float sg = 1.f;
+            if (from_below) {
+                load_link<F32>(links, dets, g.Vh, 1 - par, ylex >> 1, mu, u, d);
+                if (mu == 0 && x[0] == 0) sg = (float)g.bc_t;
+            } else {
+                load_link<F32>(links, dets, g.Vh, par, i, mu, u, d);
+                if (mu == 0 && x[0] == g.L[0] - 1) sg = (float)g.bc_t;
+            }
+            for (int half = 0; half < 2; ++half) {
+                for (int k = 0; k < 6; ++k) h[k] = scale(w[6 * half + k], sg);
+                if (from_below) su3_mul<float, true>(u, d, h, o);
+                else su3_mul<float, false>(u, d, h, o);
+                for (int k = 0; k < 6; ++k) acc[6 * half + k] = acc[6 * half + k] + o[k];
+            }
+        }
+    }
+    store_spinor<F32>(gout[b], g.Vh, par, i, acc);
+}
+
+// ------------------------------------------------------------------ weights as matrices
+//
+// Real embedding of the complex weights, B[k][n] with k = ((p*Cin + b)*4 + t)*2 + ri,
+// n = (a*4 + s)*2 + ro: B[(.., re)][(.., re)] = Re W, B[(.., im)][(.., re)] = -Im W,
+// B[(.., re)][(.., im)] = Im W, B[(.., im)][(.., im)] = Re W, W = W_p[a][b][s][t].
+// Stored transposed, Bt[n][k], for the forward GEMM, and as Bk[k][n] for dA = G B^T.
+__device__ __forceinline__ float embed(const float* W, int Cin, int Cout, int k, int n)
+{
+    const int ri = k & 1, kk = k >> 1, t = kk & 3, pb = kk >> 2, b = pb % Cin, p = pb / Cin;
+    const int ro = n & 1, nn = n >> 1, s = nn & 3, a = nn >> 2;
+    if (a >= Cout || p >= kPaths) return 0.f;
+    const long w = ((((long)p * Cout + a) * Cin + b) * 4 + s) * 4 + t;
+    const float re = W[2 * w], im = W[2 * w + 1];
+    if (ro == 0) return ri == 0 ? re : -im;
+    return ri == 0 ? im : re;
+}
+
+template <bool F32M>
+__global__ void nn_embed_kernel(const float* W, int Cin, int Cout, int Kpad, int Npad, void* Bt,
+                                void* Bk)
+{
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= Kpad * Npad) return;
+    const int n = tid / Kpad, k = tid - n * Kpad;
+    const float v = (k < kPaths * Cin * 8) ? embed(W, Cin, Cout, k, n) : 0.f;
+    put_el<F32M>(Bt, (long)n * Kpad + k, v);
+    put_el<F32M>(Bk, (long)k * Npad + n, v);
+}
+
+// dW (complex, dL/dRe W + i dL/dIm W) += the real-embedding gradient dB[k][n]
+__global__ void nn_dw_kernel(const float* dB, int Cin, int Cout, int Npad, float* dW)
+{
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nw = kPaths * Cout * Cin * 16;
+    if (tid >= nw) return;
+    const int t = tid & 3, s = (tid >> 2) & 3, rest = tid >> 4;
+    const int b = rest % Cin, a = (rest / Cin) % Cout, p = rest / (Cin * Cout);
+    const int kr = (((p * Cin + b) * 4 + t) * 2), nr = ((a * 4 + s) * 2);
+    const float d_rr = dB[(long)kr * Npad + nr], d_ii = dB[(long)(kr + 1) * Npad + nr + 1];
+    const float d_ir = dB[(long)(kr + 1) * Npad + nr], d_ri = dB[(long)kr * Npad + nr + 1];
+    dW[2 * tid] += d_rr + d_ii;
+    dW[2 * tid + 1] += d_ri - d_ir;
+}
+
+// ------------------------------------------------------------------ GEMMs on matrix cores
+
+// acc[j] += A[m0 : m0+16][k0 : k0+KS] * B[k0 : k0+KS][16 j : 16 j + 16] for one wave
+template <bool F32M>
+__device__ __forceinline__ void mfma_step(const void* A, long arow, const void* Bt, long brow0,
+                                          long bstride, int kofs, int nt, f4 acc[4])
+{
+    if constexpr (!F32M) {
+        const s4 a = *(const s4*)((const uint16_t*)A + arow + kofs);
+        for (int j = 0; j < nt; ++j) {
+            const s4 b = *(const s4*)((const uint16_t*)Bt + brow0 + j * 16 * bstride + kofs);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[j], 0, 0, 0);
+        }
+    } else {
+        const float a = ((const float*)A)[arow + kofs];
+        for (int j = 0; j < nt; ++j) {
+            const float b = ((const float*)Bt)[brow0 + j * 16 * bstride + kofs];
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[j], 0, 0, 0);
+        }
+    }
+}
+
+// out channels (FP32 fields) = A Bt^T; a workgroup computes 64 rows, a wave 16 rows x Npad
+template <bool F32M>
+__global__ __launch_bounds__(256) void nn_gemm_out_kernel(Geom g, int Kpad, int Npad, int Cout,
+                                                          const void* A, const void* Bt,
+                                                          float* const* out)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const long m0 = (long)blockIdx.x * 64 + wave * 16;
+    const int nt = Npad / 16;
+    f4 acc[4];
+    for (int j = 0; j < 4; ++j) acc[j] = f4{0.f, 0.f, 0.f, 0.f};
+    const int KS = F32M ? 4 : 16;
+    const long arow = (m0 + (lane & 15)) * Kpad;
+    const long brow0 = (long)(lane & 15) * Kpad;
+    const int kl = F32M ? (lane >> 4) : 4 * (lane >> 4);
+    for (int k0 = 0; k0 < Kpad; k0 += KS)
+        mfma_step<F32M>(A, arow, Bt, brow0, Kpad, k0 + kl, nt, acc);
+    const int Vp = padded(g.Vh);
+    for (int j = 0; j < nt; ++j)
+        for (int r = 0; r < 4; ++r) {
+            const long m = m0 + 4 * (lane >> 4) + r;
+            const int n = j * 16 + (lane & 15);
+            const long q = m / 3;
+            const int c = (int)(m - q * 3);
+            const int a = n >> 3, s = (n >> 1) & 3, ri = n & 1;
+            if (q >= 2L * Vp || a >= Cout) continue;
+            const int par = (int)(q / Vp), i = (int)(q - (long)par * Vp);
+            if (i >= g.Vh) continue;
+            out[a][f32_addr(g.Vh, par, i, s, c) + ri] = acc[j][r];
+        }
+}
+
+// dA[m][k] = sum_n G[m][n] Bk[k][n]  (G = gradient of the layer output, FP32 rows)
+template <bool F32M>
+__global__ __launch_bounds__(256) void nn_gemm_da_kernel(int Kpad, int Npad, const void* G,
+                                                         const void* Bk, float* dA)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const long m0 = (long)blockIdx.x * 64 + wave * 16;
+    const int KS = F32M ? 4 : 16;
+    const long arow = (m0 + (lane & 15)) * Npad;
+    const int kl = F32M ? (lane >> 4) : 4 * (lane >> 4);
+    for (int kt = 0; kt < Kpad / 16; kt += 4) {
+        const int nt = std::min(4, Kpad / 16 - kt);
+        f4 acc[4];
+        for (int j = 0; j < 4; ++j) acc[j] = f4{0.f, 0.f, 0.f, 0.f};
+        const long brow0 = (long)(kt * 16 + (lane & 15)) * Npad;
+        for (int n0 = 0; n0 < Npad; n0 += KS)
+            mfma_step<F32M>(G, arow, Bk, brow0, Npad, n0 + kl, nt, acc);
+        for (int j = 0; j < nt; ++j)
+            for (int r = 0; r < 4; ++r)
+                dA[(m0 + 4 * (lane >> 4) + r) * Kpad + (kt + j) * 16 + (lane & 15)] = acc[j][r];
+    }
+}
+
+// partial dB[k][n] over a slice of rows: D[k][n] += sum_m A[m][k] G[m][n]
+template <bool F32M>
+__global__ __launch_bounds__(256) void nn_gemm_db_kernel(long M, int Kpad, int Npad, int rows_per,
+                                                         const void* A, const void* G,
+                                                         float* part)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int kt = blockIdx.x;     // 16 columns k of A
+    const int split = blockIdx.y;  // slice of rows
+    const int nt = Npad / 16;
+    if (wave >= nt) return;
+    const long mbeg = (long)split * rows_per;
+    const long mend = std::min(M, mbeg + rows_per);
+    f4 acc = f4{0.f, 0.f, 0.f, 0.f};
+    const int kcol = kt * 16 + (lane & 15);
+    const int ncol = wave * 16 + (lane & 15);
+    if constexpr (!F32M) {
+        const uint16_t* Au = (const uint16_t*)A;
+        const uint16_t* Gu = (const uint16_t*)G;
+        for (long m = mbeg; m < mend; m += 16) {
+            s4 a, b;
+            for (int j = 0; j < 4; ++j) {
+                const long mm = m + 4 * (lane >> 4) + j;
+                a[j] = (short)Au[mm * Kpad + kcol];
+                b[j] = (short)Gu[mm * Npad + ncol];
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+        }
+    } else {
+        const float* Af = (const float*)A;
+        const float* Gf = (const float*)G;
+        for (long m = mbeg; m < mend; m += 4) {
+            const long mm = m + (lane >> 4);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(Af[mm * Kpad + kcol], Gf[mm * Npad + ncol],
+                                                        acc, 0, 0, 0);
+        }
+    }
+    for (int r = 0; r < 4; ++r) {
+        const int k = kt * 16 + 4 * (lane >> 4) + r;
+        part[((long)split * Kpad + k) * Npad + ncol] = acc[r];
+    }
+}
+
+__global__ void nn_reduce_db_kernel(const float* part, int nsplit, int KN, float* dB)
+{
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= KN) return;
+    float s = 0.f;
+    for (int p = 0; p < nsplit; ++p) s += part[(long)p * KN + tid];
+    dB[tid] = s;
+}
+
+// G rows from a channel gradient (FP32 fields), times `scale`
+template <bool F32M>
+__global__ __launch_bounds__(256) void nn_pack_g_kernel(Geom g, int Cout, int Npad,
+                                                        const float* const* gf, float scale, void* G)
+{
+    const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int Vp = padded(g.Vh);
+    const long nq = 2L * Vp;
+    if (tid >= nq) return;
+    const int par = (int)(tid / Vp), i = (int)(tid - (long)par * Vp);
+    for (int c = 0; c < 3; ++c)
+        for (int n = 0; n < Npad; ++n) {
+            const int a = n >> 3, s = (n >> 1) & 3, ri = n & 1;
+            float v = 0.f;
+            if (a < Cout && i < g.Vh) v = scale * gf[a][f32_addr(g.Vh, par, i, s, c) + ri];
+            put_el<F32M>(G, (tid * 3 + c) * Npad + n, v);
+        }
+}
+
+__global__ void fill_kernel(uint32_t* p, long n)
+{
+    for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x)
+        p[k] = 0u;
+}
+
+__global__ void adam_kernel(float* w, float* m, float* v, const float* g, int n, float lr,
+                            float b1, float b2, float c1, float c2, float eps, float gscale)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const float gr = g[k] * gscale;
+    m[k] = b1 * m[k] + (1.f - b1) * gr;
+    v[k] = b2 * v[k] + (1.f - b2) * gr * gr;
+    w[k] -= lr * (m[k] / c1) / (sqrtf(v[k] / c2) + eps);
+}
+
+// loss terms: d = out - e (stored in `d`), sum |d|^2
+struct LossDiff {
+    static constexpr int NS = 1;
+    const void* out;
+    const void* e;
+    void* d;
+    int Vh;
+    __device__ void operator()(const Unit& u, double* acc) const
+    {
+        cx<float> o[4], t[4];
+        ld4<F32, float>(out, Vh, u.par, u.g, u.i, o);
+        ld4<F32, float>(e, Vh, u.par, u.g, u.i, t);
+        for (int k = 0; k < 4; ++k) {
+            o[k] = o[k] - t[k];
+            acc[0] += (double)o[k].re * o[k].re + (double)o[k].im * o[k].im;
+        }
+        st4<F32, float>(d, Vh, u.par, u.g, u.i, o);
+    }
+};
+
+// ------------------------------------------------------------------ host side
+
+struct NnWork {
+    float* act[kLayers + 1][8];  // channel fields per layer boundary (FP32)
+    float* grad[2][8];           // gradient channel fields (ping-pong)
+    float* efield;               // target (FP32)
+    void* A;                     // transported rows, [Mpad][Kmax]
+    float* dA;                   // [Mpad][Kmax] (training only)
+    void* G;                     // [Mpad][Nmax]
+    void* Bt;                    // [Nmax][Kmax]
+    void* Bk;                    // [Kmax][Nmax]
+    float* part;                 // [nsplit][Kmax][Nmax]
+    float* dB;                   // [Kmax][Nmax]
+    float** ptrs;                // device pointer tables (16 slots)
+    char* end;
+};
+
+constexpr int kSplit = 64;
+
+size_t nn_layout(const qdw_op* op, bool training, char* base, NnWork* W)
+{
+    const Geom& g = op->g;
+    const size_t fb = spinor_bytes(g, F32);
+    const long Mp = rows_padded(g);
+    size_t off = 0;
+    auto take = [&](size_t n) {
+        char* at = base ? base + off : nullptr;
+        off += (n + 255) & ~(size_t)255;
+        return at;
+    };
+    for (int l = 0; l <= kLayers; ++l)
+        for (int c = 0; c < 8; ++c) W->act[l][c] = c < kCh[l] ? (float*)take(fb) : nullptr;
+    for (int h = 0; h < 2; ++h)
+        for (int c = 0; c < 8; ++c) W->grad[h][c] = training ? (float*)take(fb) : nullptr;
+    W->efield = training ? (float*)take(fb) : nullptr;
+    W->A = take((size_t)Mp * kMaxK * 4);
+    W->dA = training ? (float*)take((size_t)Mp * kMaxK * 4) : nullptr;
+    W->G = training ? take((size_t)Mp * kMaxN * 4) : nullptr;
+    W->Bt = take((size_t)kMaxN * kMaxK * 4);
+    W->Bk = take((size_t)kMaxN * kMaxK * 4);
+    W->part = training ? (float*)take((size_t)kSplit * kMaxN * kMaxK * 4) : nullptr;
+    W->dB = training ? (float*)take((size_t)kMaxN * kMaxK * 4) : nullptr;
+    W->ptrs = (float**)take(64 * sizeof(float*));
+    return off + 256;
+}
+
+int set_ptrs(float** dev, float* const* host, int n, int slot, hipStream_t st)
+{
+    QDW_HIP(hipMemcpyAsync(dev + 8 * slot, host, sizeof(float*) * n, hipMemcpyHostToDevice, st));
+    return QDW_OK;
+}
+
+int zero_dev(void* p, size_t bytes, hipStream_t st)
+{
+    const long n = (long)(bytes / 4);
+    fill_kernel<<<1024, 256, 0, st>>>((uint32_t*)p, n);
+    QDW_LAUNCH_CHECK();
+    return QDW_OK;
+}
+
+// forward through all layers, input already in act[0][0]; keeps every layer's input
+template <bool F32M>
+int forward(qdw_op* op, const float* weights, NnWork& W, hipStream_t st)
+{
+    const Geom& g = op->g;
+    const long Mp = rows_padded(g);
+    const long nq = 2L * padded(g.Vh);
+    int rc;
+    for (int l = 0; l < kLayers; ++l) {
+        const int Cin = kCh[l], Cout = kCh[l + 1], Kp = layer_K(l), Np = layer_N(l);
+        if ((rc = set_ptrs(W.ptrs, W.act[l], Cin, 0, st))) return rc;
+        if ((rc = set_ptrs(W.ptrs, W.act[l + 1], Cout, 1, st))) return rc;
+        if ((rc = zero_dev(W.A, (size_t)Mp * Kp * (F32M ? 4 : 2), st))) return rc;
+        nn_transport_kernel<F32M><<<(unsigned)((nq * Cin + 255) / 256), 256, 0, st>>>(
+            g, Cin, Kp, W.ptrs, W.A, op->links[F32], op->det[F32]);
+        QDW_LAUNCH_CHECK();
+        nn_embed_kernel<F32M><<<(Kp * Np + 255) / 256, 256, 0, st>>>(
+            weights + 2 * layer_w_offset(l), Cin, Cout, Kp, Np, W.Bt, W.Bk);
+        QDW_LAUNCH_CHECK();
+        nn_gemm_out_kernel<F32M><<<(unsigned)(Mp / 64), 256, 0, st>>>(g, Kp, Np, Cout, W.A, W.Bt,
+                                                                      W.ptrs + 8);
+        QDW_LAUNCH_CHECK();
+    }
+    return QDW_OK;
+}
+
+// backward from the real gradient of the network output (grad[0][0], times gscale);
+// accumulates dL/dRe W + i dL/dIm W into dW and leaves the input gradient in grad[x][0]
+template <bool F32M>
+int backward(qdw_op* op, const float* weights, float* dW, NnWork& W, float gscale, hipStream_t st,
+             float** gin_out)
+{
+    const Geom& g = op->g;
+    const long Mp = rows_padded(g);
+    const long nq = 2L * padded(g.Vh);
+    const long M = rows_of(g);
+    int rc;
+    int cur = 0;  // grad[cur] holds the gradient of layer l's output
+    for (int l = kLayers - 1; l >= 0; --l) {
+        const int Cin = kCh[l], Cout = kCh[l + 1], Kp = layer_K(l), Np = layer_N(l);
+        // recompute this layer's transported input rows
+        if ((rc = set_ptrs(W.ptrs, W.act[l], Cin, 0, st))) return rc;
+        if ((rc = zero_dev(W.A, (size_t)Mp * Kp * (F32M ? 4 : 2), st))) return rc;
+        nn_transport_kernel<F32M><<<(unsigned)((nq * Cin + 255) / 256), 256, 0, st>>>(
+            g, Cin, Kp, W.ptrs, W.A, op->links[F32], op->det[F32]);
+        QDW_LAUNCH_CHECK();
+        nn_embed_kernel<F32M><<<(Kp * Np + 255) / 256, 256, 0, st>>>(
+            weights + 2 * layer_w_offset(l), Cin, Cout, Kp, Np, W.Bt, W.Bk);
+        QDW_LAUNCH_CHECK();
+        // G rows from the output gradient
+        if ((rc = set_ptrs(W.ptrs, W.grad[cur], Cout, 1, st))) return rc;
+        if ((rc = zero_dev(W.G, (size_t)Mp * Np * (F32M ? 4 : 2), st))) return rc;
+        nn_pack_g_kernel<F32M><<<(unsigned)((nq + 255) / 256), 256, 0, st>>>(
+            g, Cout, Np, W.ptrs + 8, l == kLayers - 1 ? gscale : 1.f, W.G);
+        QDW_LAUNCH_CHECK();
+        // weight gradient dB = A^T G
+        const long rows_per = ((M + kSplit - 1) / kSplit + 15) & ~15L;
+        nn_gemm_db_kernel<F32M><<<dim3(Kp / 16, kSplit), 256, 0, st>>>(M, Kp, Np, (int)rows_per,
+                                                                      W.A, W.G, W.part);
+        QDW_LAUNCH_CHECK();
+        nn_reduce_db_kernel<<<(Kp * Np + 255) / 256, 256, 0, st>>>(W.part, kSplit, Kp * Np, W.dB);
+        QDW_LAUNCH_CHECK();
+        const int nw = kPaths * Cout * Cin * 16;
+        nn_dw_kernel<<<(nw + 255) / 256, 256, 0, st>>>(W.dB, Cin, Cout, Np,
+                                                       dW + 2 * layer_w_offset(l));
+        QDW_LAUNCH_CHECK();
+        // input gradient dA = G B^T, then the adjoint transport
+        nn_gemm_da_kernel<F32M><<<(unsigned)(Mp / 64), 256, 0, st>>>(Kp, Np, W.G, W.Bk, W.dA);
+        QDW_LAUNCH_CHECK();
+        if ((rc = set_ptrs(W.ptrs, W.grad[1 - cur], Cin, 2, st))) return rc;
+        nn_transport_adj_kernel<<<(unsigned)((nq * Cin + 255) / 256), 256, 0, st>>>(
+            g, Cin, Kp, W.dA, W.ptrs + 16, op->links[F32], op->det[F32]);
+        QDW_LAUNCH_CHECK();
+        cur = 1 - cur;
+    }
+    if (gin_out) *gin_out = W.grad[cur][0];
+    return QDW_OK;
+}
+
+char* align_work(void* work) { return (char*)(((uintptr_t)work + 255) & ~(uintptr_t)255); }
+
+}  // namespace
+
+size_t nn_precond_workspace(const qdw_op* op)
+{
+    NnWork W;
+    return nn_layout(op, false, nullptr, &W);
+}
+
+// phi = N(rho): rho, phi FP64 eo-SoA fields; |rho| given (sets the FP32 scale)
+int nn_precondition(qdw_op* op, const void* weights, const void* rho, void* phi, double rho_norm,
+                    char* work, hipStream_t st)
+{
+    NnWork W;
+    nn_layout(op, false, work, &W);
+    const Geom& g = op->g;
+    int rc;
+    if (!(rho_norm > 0.0)) return run_map(op, Zero<F64>{phi, g.Vh}, st);
+    const double s = std::sqrt(24.0 * g.V) / rho_norm;
+    if ((rc = run_map(op, ScaleNorm<F64, F32>{rho, W.act[0][0], s, g.Vh}, st,
+                      op->scalars + S_TMP + 2)))
+        return rc;
+    if ((rc = forward<false>(op, (const float*)weights, W, st))) return rc;
+    return run_map(op, Axpby<F32, F64>{W.act[kLayers][0], phi, 1.0 / s, 0.0, g.Vh}, st);
 }
 
 }  // namespace qdw
+
+using namespace qdw;
+
+extern "C" int qdw_nn_weight_count(void) { return total_weights(); }
+
+extern "C" size_t qdw_nn_workspace_bytes(const qdw_op* op, int training)
+{
+    if (!op) return 0;
+    NnWork W;
+    return nn_layout(op, training != 0, nullptr, &W);
+}
+
+extern "C" int nn_forward(qdw_op* op, const float* weights, const void* in, void* out, int f32_mixing,
+                          void* work, size_t work_bytes, void* stream)
+{
+    QDW_CHECK(op && weights && in && out && work, QDW_EINVAL, "nn_forward: null argument");
+    QDW_CHECK(work_bytes >= qdw_nn_workspace_bytes(op, 0), QDW_EWORKSPACE,
+              "nn_forward: workspace smaller than qdw_nn_workspace_bytes(op, 0)");
+    hipStream_t st = (hipStream_t)stream;
+    NnWork W;
+    nn_layout(op, false, align_work(work), &W);
+    const Geom& g = op->g;
+    int rc;
+    if ((rc = run_map(op, Axpby<F64, F32>{in, W.act[0][0], 1.0, 0.0, g.Vh}, st))) return rc;
+    rc = f32_mixing ? forward<true>(op, weights, W, st) : forward<false>(op, weights, W, st);
+    if (rc) return rc;
+    return run_map(op, Axpby<F32, F64>{W.act[kLayers][0], out, 1.0, 0.0, g.Vh}, st);
+}
+
+extern "C" int nn_backward(qdw_op* op, const float* weights, const void* in, const void* gout,
+                           float* dW, void* gin, int f32_mixing, void* work, size_t work_bytes,
+                           void* stream)
+{
+    QDW_CHECK(op && weights && in && gout && dW && gin && work, QDW_EINVAL,
+              "nn_backward: null argument");
+    QDW_CHECK(work_bytes >= qdw_nn_workspace_bytes(op, 1), QDW_EWORKSPACE,
+              "nn_backward: workspace smaller than qdw_nn_workspace_bytes(op, 1)");
+    hipStream_t st = (hipStream_t)stream;
+    NnWork W;
+    nn_layout(op, true, align_work(work), &W);
+    const Geom& g = op->g;
+    int rc;
+    if ((rc = zero_dev(dW, sizeof(float) * 2 * total_weights(), st))) return rc;
+    if ((rc = run_map(op, Axpby<F64, F32>{in, W.act[0][0], 1.0, 0.0, g.Vh}, st))) return rc;
+    rc = f32_mixing ? forward<true>(op, weights, W, st) : forward<false>(op, weights, W, st);
+    if (rc) return rc;
+    if ((rc = run_map(op, Axpby<F64, F32>{gout, W.grad[0][0], 1.0, 0.0, g.Vh}, st))) return rc;
+    float* gi = nullptr;
+    rc = f32_mixing ? backward<true>(op, weights, dW, W, 1.f, st, &gi)
+                    : backward<false>(op, weights, dW, W, 1.f, st, &gi);
+    if (rc) return rc;
+    return run_map(op, Axpby<F32, F64>{gi, gin, 1.0, 0.0, g.Vh}, st);
+}
+
+namespace {
+
+// x (pair storage precision P) -> FP32 field times s; |x|^2 of the input when want_norm
+template <int P>
+int pair_to_f32(qdw_op* op, const void* x, float* y, double s, hipStream_t st)
+{
+    return run_map(op, Axpby<P, F32>{x, y, s, 0.0, op->g.Vh}, st);
+}
+
+int pair_norm2(qdw_op* op, const void* x, int prec, double* out, hipStream_t st)
+{
+    int rc;
+    switch (prec) {
+    case F64: rc = run_map(op, Norm2<F64>{x, op->g.Vh}, st, op->scalars + S_TMP); break;
+    case F32: rc = run_map(op, Norm2<F32>{x, op->g.Vh}, st, op->scalars + S_TMP); break;
+    default: rc = run_map(op, Norm2<BF16S>{x, op->g.Vh}, st, op->scalars + S_TMP); break;
+    }
+    if (rc) return rc;
+    return read_scalars(op, S_TMP, 1, out, st);
+}
+
+int pair_convert(qdw_op* op, const void* x, int prec, float* y, double s, hipStream_t st)
+{
+    switch (prec) {
+    case F64: return pair_to_f32<F64>(op, x, y, s, st);
+    case F32: return pair_to_f32<F32>(op, x, y, s, st);
+    default: return pair_to_f32<BF16S>(op, x, y, s, st);
+    }
+}
+
+}  // namespace
+
+extern "C" int nn_train_step(qdw_op* op, float* weights, float* adam, int step, double lr,
+                             const void* const* rho, const void* const* err, int nbatch,
+                             qdw_prec pair_prec, int loss_kind, double* loss, void* work,
+                             size_t work_bytes, void* stream)
+{
+    QDW_CHECK(loss_kind == 0 || loss_kind == 1, QDW_EINVAL, "nn_train_step: loss_kind 0 or 1");
+    QDW_CHECK(op && weights && adam && rho && err && loss && work && nbatch >= 1 && step >= 1,
+              QDW_EINVAL, "nn_train_step: bad argument");
+    QDW_CHECK(pair_prec == QDW_F64 || pair_prec == QDW_F32 || pair_prec == QDW_BF16S, QDW_EINVAL,
+              "nn_train_step: pairs must be QDW_F64, QDW_F32 or QDW_BF16S fields");
+    QDW_CHECK(work_bytes >= qdw_nn_workspace_bytes(op, 1) + sizeof(float) * 2 * total_weights() + 512,
+              QDW_EWORKSPACE, "nn_train_step: workspace smaller than "
+                              "qdw_nn_workspace_bytes(op, 1) + 8 * qdw_nn_weight_count() + 512");
+    hipStream_t st = (hipStream_t)stream;
+    NnWork W;
+    char* base = align_work(work);
+    const size_t nb = nn_layout(op, true, base, &W);
+    float* dW = (float*)(base + ((nb + 255) & ~(size_t)255));
+    const int nw2 = 2 * total_weights();
+    const Geom& g = op->g;
+    int rc;
+    if ((rc = zero_dev(dW, sizeof(float) * nw2, st))) return rc;
+    double total = 0.0;
+    for (int k = 0; k < nbatch; ++k) {
+        // scale the pair so that the residual has unit component size (the map is linear)
+        double r2;
+        if ((rc = pair_norm2(op, rho[k], pair_prec, &r2, st))) return rc;
+        QDW_CHECK(r2 > 0.0, QDW_EINVAL, "nn_train_step: a residual is zero");
+        const double s = std::sqrt(24.0 * g.V / r2);
+        if ((rc = pair_convert(op, rho[k], pair_prec, W.act[0][0], s, st))) return rc;
+        if ((rc = pair_convert(op, err[k], pair_prec, W.efield, s, st))) return rc;
+        double e2;
+        if ((rc = run_map(op, Norm2<F32>{W.efield, g.Vh}, st, op->scalars + S_TMP))) return rc;
+        if ((rc = read_scalars(op, S_TMP, 1, &e2, st))) return rc;
+        if ((rc = forward<false>(op, weights, W, st))) return rc;
+        double d2;
+        if ((rc = run_map(op, LossDiff{W.act[kLayers][0], W.efield, W.grad[0][0], g.Vh}, st,
+                          op->scalars + S_TMP)))
+            return rc;
+        if ((rc = read_scalars(op, S_TMP, 1, &d2, st))) return rc;
+        double denom = e2;
+        if (loss_kind == 1) {
+            // D-norm: d = N(rho) - e  ->  t = D d, |t|^2, gradient direction D^+ t; the
+            // normalisation |D e|^2 is |rho|^2 of the stored pair
+            float* t = W.grad[1][0];
+            float* De = W.grad[1][1];
+            if ((rc = dw_launch(op, W.grad[0][0], t, F32, false, st))) return rc;
+            if ((rc = run_map(op, Norm2<F32>{t, g.Vh}, st, op->scalars + S_TMP))) return rc;
+            if ((rc = read_scalars(op, S_TMP, 1, &d2, st))) return rc;
+            if ((rc = dw_launch(op, W.efield, De, F32, false, st))) return rc;
+            if ((rc = run_map(op, Norm2<F32>{De, g.Vh}, st, op->scalars + S_TMP))) return rc;
+            if ((rc = read_scalars(op, S_TMP, 1, &denom, st))) return rc;
+            if ((rc = dw_launch(op, t, W.grad[0][0], F32, true, st))) return rc;
+        }
+        total += d2 / denom;
+        // dL/d(out re, im) = 2 (out - e) / |e|^2, or 2 D^+ D (out - e) / |D e|^2, batch mean
+        const float gs = (float)(2.0 / (denom * nbatch));
+        if ((rc = backward<false>(op, weights, dW, W, gs, st, nullptr))) return rc;
+    }
+    *loss = total / nbatch;
+    const float b1 = 0.9f, b2 = 0.999f;
+    adam_kernel<<<(nw2 + 255) / 256, 256, 0, st>>>(weights, adam, adam + nw2, dW, nw2, (float)lr, b1,
+                                                   b2, 1.f - std::pow(b1, (float)step),
+                                                   1.f - std::pow(b2, (float)step), 1e-8f, 1.f);
+    QDW_LAUNCH_CHECK();
+    QDW_HIP(hipStreamSynchronize(st));
+    return QDW_OK;
+}

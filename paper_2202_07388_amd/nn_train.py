@@ -1,0 +1,90 @@
+"""Training pipeline of the learned preconditioner (library calls only).
+
+Pairs come from the solver itself: for a source eta, plain FP64 flexible GCR is run for
+k = 1, 2, ... steps; its iterate psi_k gives the residual rho_k = eta - D psi_k and the
+error e_k = x* - psi_k = D^-1 rho_k, with x* the solution to 1e-12. The network is then
+fitted to rho_k -> e_k by Adam on the GPU (nn_train_step: forward, loss, backward and
+update all in the library's kernels), with the error measured in the D-norm by default.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import qdw
+
+
+def init_weights(m0: float, seed: int, noise: float = 1e-3):
+    """Start from N(r) = r / (4 + m0) (the inverse of the operator's diagonal in the free
+    field): the identity path of each layer carries (4 + m0)^(-1/3) on channel 0, plus
+    small complex noise everywhere so that all channels can learn."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    c = (4.0 + m0) ** (-1.0 / 3.0)
+    layers = []
+    for cin, cout in zip(qdw.NN_CHANNELS[:-1], qdw.NN_CHANNELS[1:]):
+        shape = (qdw.NN_PATHS, cout, cin, 4, 4)
+        W = noise * (rng.standard_normal(shape) + 1j * rng.standard_normal(shape))
+        W[0, 0, 0] += c * np.eye(4)
+        layers.append(W)
+    return layers
+
+
+def solver_pairs(op: "qdw.Op", etas, steps: int, store: str = "bf16", nkv: int = 16,
+                 log=None):
+    """Residual/error pairs from plain FP64 GCR runs on the given FP64 sources."""
+    rhos, errs = [], []
+    xs = op.new_field("f64")
+    psi = op.new_field("f64")
+    t = op.new_field("f64")
+    for n, eta in enumerate(etas):
+        info = qdw.sap_gcr_solve(op, eta, xs, res=1e-12, nmx=20000, nkv=nkv, precond="none")
+        if info["status"] <= 0:
+            raise qdw.QdwError("pair generation: reference solve failed: %s" % info)
+        for k in range(1, steps + 1):
+            inf = qdw.sap_gcr_solve(op, eta, psi, res=1e-14, nmx=k, nkv=nkv, precond="none")
+            if inf["status"] >= 0:
+                break  # converged: no further useful pairs from this source
+            qdw.dw_apply(op, psi, t, "f64")
+            rho = op.new_field("f64")
+            qdw.axpby(op, 1.0, eta, 0.0, rho)
+            qdw.axpby(op, -1.0, t, 1.0, rho)          # rho = eta - D psi
+            err = op.new_field("f64")
+            qdw.axpby(op, 1.0, xs, 0.0, err)
+            qdw.axpby(op, -1.0, psi, 1.0, err)        # e = x* - psi
+            if store == "f64":
+                rhos.append(rho)
+                errs.append(err)
+            else:
+                r_s, e_s = op.new_field(store), op.new_field(store)
+                n2 = qdw.norm2(op, rho)
+                s = np.sqrt(24.0 * op.V / n2)           # unit component size for storage
+                qdw.convert(op, rho, "f64", r_s, store, s)
+                qdw.convert(op, err, "f64", e_s, store, s)
+                rhos.append(r_s)
+                errs.append(e_s)
+                del rho, err
+        if log:
+            log("pairs: source %d done, %d pairs" % (n, len(rhos)))
+    return rhos, errs
+
+
+def train(op: "qdw.Op", rhos, errs, store: str, epochs: int, batch: int, lr: float,
+          m0: float, seed: int = 0, loss: str = "dnorm", log=None):
+    """Adam on the pairs; returns the weights tensor and the loss per step. The default
+    loss measures N(rho) - e in the D-norm, i.e. the residual a GCR step would leave,
+    which is what the flexible GCR judges a preconditioner by."""
+    import torch
+    w = qdw.nn_weights_tensor(init_weights(m0, seed))
+    adam = torch.zeros(4 * qdw.nn_weight_count(), dtype=torch.float32, device=w.device)
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    losses = []
+    step = 0
+    for ep in range(epochs):
+        order = rng.permutation(len(rhos))
+        for b0 in range(0, len(order) - batch + 1, batch):
+            idx = order[b0:b0 + batch]
+            step += 1
+            losses.append(qdw.nn_train_step(op, w, adam, step, lr, [rhos[i] for i in idx],
+                                            [errs[i] for i in idx], store, loss))
+        if log:
+            log("epoch %d: mean loss %.4f" % (ep, float(np.mean(losses[-max(1, len(order) // batch):]))))
+    return w, losses

@@ -100,6 +100,20 @@ _OPTIONAL: list = [
     ("qdw_sap_workspace_bytes", [_P, ctypes.c_int], ctypes.c_size_t),
     ("sap_apply", [_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int * 4),
                    ctypes.c_int, _P, ctypes.c_size_t, _P], ctypes.c_int),
+    ("qdw_axpby", [_P, ctypes.c_double, _P, ctypes.c_double, _P, ctypes.c_int, _P], ctypes.c_int),
+    ("qdw_norm2", [_P, _P, ctypes.c_int, ctypes.POINTER(ctypes.c_double), _P], ctypes.c_int),
+    ("qdw_cdot", [_P, _P, _P, ctypes.c_int, ctypes.POINTER(ctypes.c_double * 2), _P],
+     ctypes.c_int),
+    ("qdw_convert", [_P, _P, ctypes.c_int, _P, ctypes.c_int, ctypes.c_double, _P],
+     ctypes.c_int),
+    ("qdw_nn_weight_count", [], ctypes.c_int),
+    ("qdw_nn_workspace_bytes", [_P, ctypes.c_int], ctypes.c_size_t),
+    ("nn_forward", [_P, _P, _P, _P, ctypes.c_int, _P, ctypes.c_size_t, _P], ctypes.c_int),
+    ("nn_backward", [_P, _P, _P, _P, _P, _P, ctypes.c_int, _P, ctypes.c_size_t, _P],
+     ctypes.c_int),
+    ("nn_train_step", [_P, _P, _P, ctypes.c_int, ctypes.c_double, _P, _P, ctypes.c_int,
+                       ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double), _P,
+                       ctypes.c_size_t, _P], ctypes.c_int),
     ("qdw_cgne_workspace_bytes", [_P, ctypes.POINTER(CgneParams)], ctypes.c_size_t),
     ("cgne_solve", [_P, _P, _P, ctypes.POINTER(CgneParams), _P, ctypes.c_size_t,
                     ctypes.POINTER(Info), _P], ctypes.c_int),
@@ -213,6 +227,34 @@ def dw_dag_apply(op: Op, x, out, prec: str = "f64"):
     return out
 
 
+def axpby(op: Op, a: float, x, b: float, y, prec: str = "f64"):
+    """y = a x + b y."""
+    _check(load().qdw_axpby(op.handle, a, _ptr(x), b, _ptr(y), PREC[prec], _stream()),
+           "qdw_axpby")
+    return y
+
+
+def norm2(op: Op, x, prec: str = "f64") -> float:
+    out = ctypes.c_double()
+    _check(load().qdw_norm2(op.handle, _ptr(x), PREC[prec], ctypes.byref(out), _stream()),
+           "qdw_norm2")
+    return out.value
+
+
+def cdot(op: Op, x, y, prec: str = "f64") -> complex:
+    out = (ctypes.c_double * 2)()
+    _check(load().qdw_cdot(op.handle, _ptr(x), _ptr(y), PREC[prec], ctypes.byref(out),
+                           _stream()), "qdw_cdot")
+    return complex(out[0], out[1])
+
+
+def convert(op: Op, x, px: str, y, py: str, s: float = 1.0):
+    """y = s x, from precision px to py."""
+    _check(load().qdw_convert(op.handle, _ptr(x), PREC[px], _ptr(y), PREC[py], s, _stream()),
+           "qdw_convert")
+    return y
+
+
 def _workspace(op: Op, nbytes: int):
     """Device workspace owned by the Python Op (grown on demand, reused across calls)."""
     torch = _torch()
@@ -266,3 +308,84 @@ def sap_apply(op: Op, rho, phi, ncy: int = 5, nmr: int = 4, bs=(4, 4, 4, 4),
     _check(L.sap_apply(op.handle, _ptr(rho), _ptr(phi), ncy, nmr, ctypes.byref(b),
                        PREC[sdtype], _ptr(ws), ws.numel(), _stream()), "sap_apply")
     return phi
+
+
+# ---------------------------------------------------------------- learned preconditioner
+
+NN_CHANNELS = (1, 8, 8, 1)
+NN_PATHS = 9
+
+
+def nn_weight_count() -> int:
+    return int(load().qdw_nn_weight_count())
+
+
+def nn_weights_tensor(layers):
+    """Flatten per-layer complex weights [9, Cout, Cin, 4, 4] into the library's FP32
+    interleaved layout on the current device."""
+    torch = _torch()
+    flat = np.concatenate([np.asarray(w, dtype=np.complex128).reshape(-1) for w in layers])
+    if flat.size != nn_weight_count():
+        raise QdwError("weights do not match the 1-8-8-1 network")
+    re_im = np.stack([flat.real, flat.imag], axis=-1).astype(np.float32).reshape(-1)
+    return torch.as_tensor(re_im).to(torch.device("cuda", torch.cuda.current_device()))
+
+
+def nn_weights_layers(t):
+    """Inverse of nn_weights_tensor: list of complex numpy arrays [9, Cout, Cin, 4, 4]."""
+    a = t.detach().cpu().numpy().astype(np.float64).reshape(-1, 2)
+    z = a[:, 0] + 1j * a[:, 1]
+    out, o = [], 0
+    for cin, cout in zip(NN_CHANNELS[:-1], NN_CHANNELS[1:]):
+        n = NN_PATHS * cout * cin * 16
+        out.append(z[o:o + n].reshape(NN_PATHS, cout, cin, 4, 4))
+        o += n
+    return out
+
+
+def _nn_ws(op: Op, training: bool, extra: int = 0):
+    torch = _torch()
+    nb = int(load().qdw_nn_workspace_bytes(op.handle, 1 if training else 0)) + extra
+    attr = "_nnws_t" if training else "_nnws_f"
+    ws = getattr(op, attr, None)
+    if ws is None or ws.numel() < nb:
+        setattr(op, attr, None)
+        ws = torch.empty(nb, dtype=torch.uint8, device=op.device)
+        setattr(op, attr, ws)
+    return ws
+
+
+def nn_forward(op: Op, weights, x, out, f32_mixing: bool = False):
+    """out = N(x) for FP64 eo-SoA fields."""
+    ws = _nn_ws(op, False)
+    _check(load().nn_forward(op.handle, _ptr(weights), _ptr(x), _ptr(out),
+                             1 if f32_mixing else 0, _ptr(ws), ws.numel(), _stream()),
+           "nn_forward")
+    return out
+
+
+def nn_backward(op: Op, weights, x, gout, dW, gin, f32_mixing: bool = False):
+    """Real gradients: dW and gin from gout = dL/dRe N(x) + i dL/dIm N(x)."""
+    ws = _nn_ws(op, True)
+    _check(load().nn_backward(op.handle, _ptr(weights), _ptr(x), _ptr(gout), _ptr(dW),
+                              _ptr(gin), 1 if f32_mixing else 0, _ptr(ws), ws.numel(),
+                              _stream()), "nn_backward")
+
+
+LOSS = {"error": 0, "dnorm": 1}
+
+
+def nn_train_step(op: Op, weights, adam, step: int, lr: float, rhos, errs,
+                  prec: str = "f64", loss: str = "dnorm") -> float:
+    """One Adam step on a batch of (residual, error) fields of precision `prec`; returns
+    the batch loss before the update. loss: "error" (|N(r) - e|^2/|e|^2) or "dnorm"
+    (|D(N(r) - e)|^2/|De|^2)."""
+    n = len(rhos)
+    ws = _nn_ws(op, True, extra=8 * nn_weight_count() + 512)
+    rp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in rhos])
+    ep = (ctypes.c_void_p * n)(*[t.data_ptr() for t in errs])
+    out = ctypes.c_double()
+    _check(load().nn_train_step(op.handle, _ptr(weights), _ptr(adam), step, lr, rp, ep, n,
+                                PREC[prec], LOSS[loss], ctypes.byref(out), _ptr(ws),
+                                ws.numel(), _stream()), "nn_train_step")
+    return out.value

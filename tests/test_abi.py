@@ -30,7 +30,7 @@ def lib():
 
 def test_header_declares_the_four_named_calls():
     names = declared_functions()
-    for n in ("dw_apply", "dw_dag_apply", "cgne_solve", "sap_gcr_solve"):
+    for n in ("dw_apply", "dw_dag_apply", "cgne_solve", "sap_gcr_solve", "qdw_norm2", "nn_forward", "nn_train_step"):
         assert n in names, n
 
 
