@@ -12,6 +12,11 @@ Also reported, each timed on its own outside the K steps:
     against FP32 and FP16 regular steps with FP64 reset steps;
   * the 24^3 x 48 solve of D psi = eta to 1e-10 (eps = 0.35, m0 = -0.08): plain FP64 GCR
     against SAP-preconditioned GCR (4^4 blocks, 5 cycles, 4 MR steps, FP16 and FP32);
+  * a batch of 40 right-hand sides over three lattices of different volumes (16^3 x 32
+    with 12 point sources, one per spin and colour; 24^3 x 48 with 4 Gaussian sources;
+    8^3 x 16 with 24 Gaussian sources; three independent fields, eps = 0.3, m0 = -0.05),
+    mixed-precision SAP-GCR to 1e-10 as one graph-replayed batch against the same 40
+    solves one after another, with the D-kernel shape the autotuner picked per lattice;
   * the FP64 oracle timed on the host on a bounded sample (cpu_baseline).
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-solves]
@@ -137,6 +142,66 @@ def gcr_solves(qdw, syn):
     return out
 
 
+BATCH = (((32, 16, 16, 16), "point", 12, 7388 + 31), ((48, 24, 24, 24), "gauss", 4, 7388 + 32),
+         ((16, 8, 8, 8), "gauss", 24, 7388 + 33))
+
+
+def batched_solves(qdw, syn):
+    """40 right-hand sides over three lattices: one batched SAP-GCR against 40 single solves."""
+    import torch
+    ops, etas, shapes = [], [], {}
+    for dims, kind, n, seed in BATCH:
+        su3, th = syn.gauge_field(dims, EPS, EPS_U1, seed)
+        op = qdw.Op(dims, su3, th, M0, CSW, -1)
+        del su3, th
+        name = "%dc%d" % (dims[1], dims[0])
+        shapes[name] = qdw.autotune(op, "f64", n).split(";")[0]
+        for r in range(n):
+            src = (syn.point_spinor(dims, r // 3, r % 3, 0) if kind == "point"
+                   else syn.gaussian_spinor(dims, seed + 1000 + r))
+            ops.append(op)
+            etas.append(op.pack(src, "f64"))
+    kw = dict(res=1e-10, nmx=2000, nkv=16, ncy=5, nmr=4, bs=(4, 4, 4, 4), sdtype="f16",
+              precond="sap")
+    psis = [o.new_field("f64") for o in ops]
+    qdw.sap_gcr_solve_batched(ops[:2], etas[:2], psis[:2], **kw)  # warm-up (code objects)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos, graph_ms = qdw.sap_gcr_solve_batched(ops, etas, psis, **kw)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    single = []
+    for o, e in zip(ops, etas):
+        x = o.new_field("f64")
+        single.append(qdw.sap_gcr_solve(o, e, x, **kw))
+        del x
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    per = {}
+    i = 0
+    for dims, kind, n, seed in BATCH:
+        name = "%dc%d" % (dims[1], dims[0])
+        inf = infos[i:i + n]
+        per[name] = {"rhs": n, "source": kind,
+                     "steps": [x["n_steps"] for x in inf],
+                     "max_rel_res_true": max(x["rel_res_true"] for x in inf),
+                     "all_converged": all(x["status"] > 0 for x in inf),
+                     "same_steps_as_single": all(a["status"] == b["status"]
+                                                 for a, b in zip(inf, single[i:i + n])),
+                     "dw_shape": shapes[name]}
+        i += n
+    site_rhs = sum(int(np.prod(d)) * n for d, _, n, _ in BATCH)
+    rec = {"rhs": len(ops), "site_rhs": site_rhs, "s_batched": round(t_batch, 4),
+           "graph_setup_ms": round(graph_ms, 2), "s_sequential_single": round(t_seq, 4),
+           "speedup": round(t_seq / t_batch, 3), "lattices": per,
+           "settings": "SAP-GCR nkv 16, 4^4 blocks, ncy 5, nmr 4, FP16 SAP storage, res 1e-10"}
+    log("  batched: %s" % json.dumps(rec))
+    for o in set(ops):
+        o.close()
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -144,6 +209,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solves", action="store_true")
+    ap.add_argument("--dw-shape", default=None,
+                    help="ts,nt,pipe: pin the FP64 D-kernel shape instead of autotuning it "
+                         "(profiling runs pin the shape the autotuner reported)")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run a plain elementwise kernel that reads and writes 1 GiB "
                          "(3 launches), to scale hardware byte counters")
@@ -169,6 +237,13 @@ def main():
     op = qdw.Op(DIMS, su3, th, M0, CSW, -1)
     del su3, th
     V = op.V
+    if args.dw_shape:
+        qdw.set_dw_shape(op, "f64", *[int(v) for v in args.dw_shape.split(",")])
+        tuned = {"f64": "pinned ts,nt,pipe = %s" % args.dw_shape}
+    else:
+        log("autotuning the D kernel ...")
+        tuned = {p: qdw.autotune(op, p, 1).split(";")[0] for p in ("f64", "f32", "f16")}
+    log("  D-kernel shapes: %s" % tuned)
     fields = {}
     for prec in ("f64", "f32", "f16"):
         fields[prec] = (op.pack(psi, prec), op.new_field(prec))
@@ -232,6 +307,8 @@ def main():
                      "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
                      "traffic": traffic},
         "dw_other_precisions": other,
+        "dw_shapes": {p: list(qdw.get_dw_shape(op, p)) for p in ("f64", "f32", "f16")},
+        "autotune": tuned,
         "wall_s_timed_region": round(wall, 4),
     }
     if not args.no_solves:
@@ -239,6 +316,7 @@ def main():
         out["cgne_32c64"] = cgne_solves(op, qdw, psi)
         op.close()
         out["sap_gcr_24c48"] = gcr_solves(qdw, syn)
+        out["batched_40rhs"] = batched_solves(qdw, syn)
     if not args.no_cpu_baseline:
         log("timing the oracle on the host (bounded sample) ...")
         out["cpu_baseline"] = cpu_baseline()

@@ -102,6 +102,30 @@ int qdw_unpack(const qdw_op* op, const void* eo, double* canonical, qdw_prec pre
 int dw_apply(qdw_op* op, const void* in, void* out, qdw_prec prec, void* stream);
 int dw_dag_apply(qdw_op* op, const void* in, void* out, qdw_prec prec, void* stream);
 
+/* out[r] = D in[r] for r < nrhs (1 <= nrhs <= 64) in one launch: several right-hand sides
+ * on one gauge field (Sec. 2 and 3 solve one system per source; the batch shares the
+ * operator). in, out: host arrays of device eo-SoA fields of precision prec; no output may
+ * alias any input. Workgroups of different right-hand sides on the same tile run side by
+ * side, so the links and clover blocks of a tile come from HBM about once for the batch.
+ * Results equal dw_apply on each field. */
+int dw_apply_multi(qdw_op* op, const void* const* in, void* const* out, int nrhs,
+                   qdw_prec prec, void* stream);
+
+/* Autotuner of the D kernel for this operator (not from the paper): times every
+ * workgroup shape (64 or 128 sites per parity), walk chunk (1, 2, 4, 8 time slices,
+ * dividing T) and hop-loop form (plain or software-pipelined) for precision prec and
+ * nrhs right-hand sides on the stream, keeps the fastest in op (used by dw_apply,
+ * dw_apply_multi, the solvers and the SAP boundary kernel from then on), and writes a
+ * one-line report (best shape, then every candidate's time in ms) to report
+ * (host, may be NULL). Allocates and frees two scratch fields per right-hand side;
+ * synchronises the stream. Results of D do not depend on the shape. */
+int qdw_autotune(qdw_op* op, qdw_prec prec, int nrhs, char* report, size_t report_len,
+                 void* stream);
+/* Set / read the D kernel's shape for precision prec by hand (ts 64 or 128, nt in 1..8
+ * dividing T, pipe 0 or 1; shape3 = {ts, nt, pipe}); QDW_EINVAL for anything else. */
+int qdw_set_dw_shape(qdw_op* op, qdw_prec prec, int ts, int nt, int pipe);
+int qdw_get_dw_shape(const qdw_op* op, qdw_prec prec, int* shape3);
+
 /* Fused BLAS-1 on eo-SoA fields of one precision (device), every reduction accumulated in
  * binary64 (Sec. 2.1: reduction variables in binary64 whatever the working type) in a
  * fixed order, so results are bitwise reproducible. qdw_norm2 and qdw_cdot write their
@@ -199,6 +223,24 @@ size_t qdw_sap_gcr_workspace_bytes(const qdw_op* op, const qdw_sap_gcr_params* p
  * sweeps of the full lattice per preconditioner application. Synchronises the stream. */
 int sap_gcr_solve(qdw_op* op, const void* eta, void* psi, const qdw_sap_gcr_params* prm,
                   void* work, size_t work_bytes, qdw_info* info, void* stream);
+
+/* Several flexible-GCR solves at once (not from the paper: batching across right-hand
+ * sides and lattices): problem j solves D_j psi_j = eta_j with operator ops[j] (ops may
+ * repeat: the right-hand sides of one operator are solved together; operators may have
+ * different lattice volumes), all with settings p (precond QDW_PRECOND_NONE or
+ * QDW_PRECOND_SAP). Each solve takes the same steps, with the same arithmetic, as
+ * sap_gcr_solve on its own; all convergence decisions are made on the device, one
+ * restart cycle (nkv steps + restart step) of the whole batch is captured once as a HIP
+ * graph and replayed until every solve has finished (the host waits once per replay).
+ * etas, psis: host arrays of n device FP64 eo-SoA fields (psi distinct from each other and
+ * from every eta); work: device scratch of qdw_sap_gcr_batched_workspace_bytes bytes;
+ * infos: n results (host; t_sec = wall time of the whole batch); graph_ms (host, may be
+ * NULL): time to capture and instantiate the graph. Synchronises with the stream. */
+size_t qdw_sap_gcr_batched_workspace_bytes(qdw_op* const* ops, int n,
+                                           const qdw_sap_gcr_params* p);
+int sap_gcr_solve_batched(qdw_op* const* ops, const void* const* etas, void* const* psis, int n,
+                          const qdw_sap_gcr_params* p, void* work, size_t work_bytes,
+                          qdw_info* infos, double* graph_ms, void* stream);
 
 /* ---- learned gauge-covariant preconditioner (not from the paper) ----------------------
  * Three linear parallel-transport layers, 1 -> 8 -> 8 -> 1 spinor channels:

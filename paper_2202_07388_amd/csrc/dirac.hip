@@ -1,11 +1,12 @@
 // dirac.hip -- the Wilson-clover operator D and D^+ on eo-SoA fields.
 //
-// One lane per output site; a 256-lane workgroup owns 128 consecutive even-odd indices
-// of BOTH parities (lanes 0..127 even, 128..255 odd). The even site with index i and the
-// odd site with index i are lexicographic neighbours along x3, so a workgroup covers a
-// compact run of the lattice: the eight links a site reads are mostly the same links its
-// neighbours in the workgroup read (every link joins an even and an odd site), and the
-// neighbour spinors are shared through L1/L2. Workgroups are mapped XCD-contiguously.
+// One lane per output site; a workgroup of 2*ts lanes owns ts consecutive even-odd
+// indices of one time slice in BOTH parities (lanes 0..ts-1 even, ts..2ts-1 odd). The even
+// site with index i and the odd site with index i are lexicographic neighbours along x3,
+// so a workgroup covers a compact run of the lattice: the eight links a site reads are
+// mostly the same links its neighbours in the workgroup read (every link joins an even and
+// an odd site), and the neighbour spinors are shared through L1/L2. Workgroups are mapped
+// XCD-contiguously and walk time-slice-first within a spatial tile (walk_site).
 //
 // Per hop the neighbour spinor is spin-projected with (1 -+ gamma_mu) to two spin
 // components, multiplied by the link (row 2 rebuilt from rows 0, 1 and det U; the U(1)
@@ -14,16 +15,34 @@
 // hopping term is applied once at the end. D^+ = gamma_5 D gamma_5 flips the projector
 // signs.
 //
-// The eight hops form a runtime loop; for FP64 and FP32 it is software-pipelined over two
-// register buffers (the loads of hop k+1 are in flight while hop k is computed). Workgroups
-// walk the lattice time-slice-first within a spatial tile (walk_site). Loop-carried site indices
-// pass through an empty asm statement so the optimiser cannot hoist all eight hops'
-// address computations out of the loop (that would pin ~80 registers and halve the
+// The eight hops form a runtime loop; optionally (PIPE) it is software-pipelined over two
+// register buffers: the loads of hop k+1 are in flight while hop k is computed. Loop-carried
+// site indices pass through an empty asm statement so the optimiser cannot hoist all eight
+// hops' address computations out of the loop (that would pin ~80 registers and halve the
 // occupancy).
+//
+// Several right-hand sides on one operator (a table of up to kMaxRhs fields) run in one
+// launch with the right-hand side as the fastest-varying workgroup index: the workgroups
+// that read a tile's links and clover blocks for different right-hand sides run together,
+// so L2 serves those bytes once for all of them.
+#include <chrono>
+#include <cstdio>
+#include <string>
+#include <vector>
+
 #include "qdw_host.h"
 #include "dirac_core.h"
 
 using namespace qdw;
+
+namespace qdw {
+struct RhsTable {
+    const void* in[kMaxRhs];
+    void* out[kMaxRhs];
+    const int* gate;  // optional: right-hand side r is skipped when gate[r * gstride] == 0
+    int gstride;
+};
+}  // namespace qdw
 
 namespace {
 
@@ -97,24 +116,27 @@ __device__ __forceinline__ void compute_k(int k, const Geom& g, const int x[4], 
     }
 }
 
-template <int P, bool DAG>
-__global__ __launch_bounds__(256) void dw_kernel(Geom g, const void* __restrict__ in,
-                                                 void* __restrict__ out,
+template <int P, bool DAG, bool PIPE>
+__global__ __launch_bounds__(256) void dw_kernel(Geom g, RhsTable tab, int nrhs,
                                                  const void* __restrict__ links,
                                                  const void* __restrict__ dets,
                                                  const void* __restrict__ clover)
 {
     using R = typename Traits<P>::real;
-    const int par = threadIdx.x >> 7;
-    int i;
-    if (!walk_site(g, xcd_tile(blockIdx.x, gridDim.x), threadIdx.x & 127, i)) return;
+    const int logical = xcd_tile(blockIdx.x, gridDim.x);
+    const int tile = logical / nrhs;
+    const int rhs = logical - tile * nrhs;
+    if (tab.gate && !tab.gate[(long)rhs * tab.gstride]) return;
+    const void* __restrict__ in = tab.in[rhs];
+    void* __restrict__ out = tab.out[rhs];
+    int par, i;
+    if (!walk_site(g, tile, threadIdx.x, par, i)) return;
     int x[4], lex;
     eo_coords(g, par, i, x, lex);
     cx<R> hop[12];
 #pragma unroll
     for (int c = 0; c < 12; ++c) hop[c] = {(R)0, (R)0};
-    if constexpr (P == F64 || P == F32) {
-        // bandwidth-bound formats: two buffers, loads of the next hop in flight
+    if constexpr (PIPE) {
         HopIn<P> A, B;
         load_k<P>(0, g, in, links, dets, par, i, x, lex, A);
 #pragma unroll 1
@@ -127,8 +149,6 @@ __global__ __launch_bounds__(256) void dw_kernel(Geom g, const void* __restrict_
             compute_k<P, DAG>(k + 1, g, xx, B, hop);
         }
     } else {
-        // 16-bit storage is limited by the conversions and arithmetic, not by loads: one
-        // buffer keeps the register count (and so the occupancy) lower
         HopIn<P> A;
 #pragma unroll 1
         for (int k = 0; k < 8; ++k) {
@@ -146,48 +166,210 @@ __global__ __launch_bounds__(256) void dw_kernel(Geom g, const void* __restrict_
     store_spinor<P>(out, g.Vh, par, i, acc);
 }
 
-template <int P, bool DAG>
-int launch(qdw_op* op, const void* in, void* out, hipStream_t st)
+// the operator's geometry with the D kernel's own shape for precision P
+inline Geom shaped(const qdw_op* op, int P)
 {
-    const Geom& g = op->g;
-    dw_kernel<P, DAG><<<walk_blocks(g), 256, 0, st>>>(g, in, out, op->links[P], op->det[P],
-                                                      op->clover[P]);
+    Geom g = op->g;
+    g.ts = op->dw_shape[P].ts;
+    g.nt = op->dw_shape[P].nt;
+    g.ntile = (g.S + g.ts - 1) / g.ts;
+    return g;
+}
+
+template <int P, bool DAG>
+int launch(qdw_op* op, const RhsTable& tab, int nrhs, hipStream_t st)
+{
+    const Geom g = shaped(op, P);
+    const int nblk = walk_blocks(g) * nrhs;
+    if (op->dw_shape[P].pipe)
+        dw_kernel<P, DAG, true><<<nblk, 2 * g.ts, 0, st>>>(g, tab, nrhs, op->links[P], op->det[P],
+                                                           op->clover[P]);
+    else
+        dw_kernel<P, DAG, false><<<nblk, 2 * g.ts, 0, st>>>(g, tab, nrhs, op->links[P], op->det[P],
+                                                            op->clover[P]);
     QDW_LAUNCH_CHECK();
     return QDW_OK;
 }
 
-template <bool DAG>
-int dispatch(qdw_op* op, const void* in, void* out, qdw_prec prec, void* stream)
+int dispatch(qdw_op* op, const RhsTable& tab, int nrhs, int prec, bool dag, hipStream_t st)
+{
+    switch (prec) {
+    case QDW_F64: return dag ? launch<F64, true>(op, tab, nrhs, st) : launch<F64, false>(op, tab, nrhs, st);
+    case QDW_F32: return dag ? launch<F32, true>(op, tab, nrhs, st) : launch<F32, false>(op, tab, nrhs, st);
+    case QDW_F16S: return dag ? launch<F16S, true>(op, tab, nrhs, st) : launch<F16S, false>(op, tab, nrhs, st);
+    case QDW_BF16S: return dag ? launch<BF16S, true>(op, tab, nrhs, st) : launch<BF16S, false>(op, tab, nrhs, st);
+    default: QDW_CHECK(false, QDW_EINVAL, "dw_apply: bad precision");
+    }
+}
+
+int apply_checked(qdw_op* op, const void* in, void* out, qdw_prec prec, bool dag, void* stream)
 {
     QDW_CHECK(op && in && out, QDW_EINVAL, "dw_apply: null argument");
     QDW_CHECK(in != out, QDW_EINVAL, "dw_apply: in and out must be distinct fields");
-    hipStream_t st = (hipStream_t)stream;
-    switch (prec) {
-    case QDW_F64: return launch<F64, DAG>(op, in, out, st);
-    case QDW_F32: return launch<F32, DAG>(op, in, out, st);
-    case QDW_F16S: return launch<F16S, DAG>(op, in, out, st);
-    case QDW_BF16S: return launch<BF16S, DAG>(op, in, out, st);
-    default: QDW_CHECK(false, QDW_EINVAL, "dw_apply: bad precision");
-    }
+    RhsTable tab{};
+    tab.in[0] = in;
+    tab.out[0] = out;
+    return dispatch(op, tab, 1, prec, dag, (hipStream_t)stream);
 }
 
 }  // namespace
 
 namespace qdw {
-// internal entry used by the solvers (same kernels, no argument re-validation)
+// internal entries used by the solvers (same kernels, no argument re-validation)
 int dw_launch(qdw_op* op, const void* in, void* out, int prec, bool dag, hipStream_t st)
 {
-    if (dag) return dispatch<true>(op, in, out, (qdw_prec)prec, st);
-    return dispatch<false>(op, in, out, (qdw_prec)prec, st);
+    RhsTable tab{};
+    tab.in[0] = in;
+    tab.out[0] = out;
+    return dispatch(op, tab, 1, prec, dag, st);
+}
+
+int dw_launch_multi(qdw_op* op, const void* const* in, void* const* out, int nrhs, int prec,
+                    bool dag, const int* gate, int gstride, hipStream_t st)
+{
+    RhsTable tab{};
+    tab.gate = gate;
+    tab.gstride = gstride;
+    for (int r = 0; r < nrhs; ++r) {
+        tab.in[r] = in[r];
+        tab.out[r] = out[r];
+    }
+    return dispatch(op, tab, nrhs, prec, dag, st);
 }
 }  // namespace qdw
 
 extern "C" int dw_apply(qdw_op* op, const void* in, void* out, qdw_prec prec, void* stream)
 {
-    return dispatch<false>(op, in, out, prec, stream);
+    return apply_checked(op, in, out, prec, false, stream);
 }
 
 extern "C" int dw_dag_apply(qdw_op* op, const void* in, void* out, qdw_prec prec, void* stream)
 {
-    return dispatch<true>(op, in, out, prec, stream);
+    return apply_checked(op, in, out, prec, true, stream);
+}
+
+extern "C" int dw_apply_multi(qdw_op* op, const void* const* in, void* const* out, int nrhs,
+                              qdw_prec prec, void* stream)
+{
+    QDW_CHECK(op && in && out, QDW_EINVAL, "dw_apply_multi: null argument");
+    QDW_CHECK(nrhs >= 1 && nrhs <= kMaxRhs, QDW_EINVAL, "dw_apply_multi: need 1 <= nrhs <= 64");
+    for (int r = 0; r < nrhs; ++r) {
+        QDW_CHECK(in[r] && out[r], QDW_EINVAL, "dw_apply_multi: null field");
+        for (int q = 0; q < nrhs; ++q)
+            QDW_CHECK(in[r] != out[q], QDW_EINVAL, "dw_apply_multi: an output aliases an input");
+    }
+    return qdw::dw_launch_multi(op, in, out, nrhs, prec, false, nullptr, 0, (hipStream_t)stream);
+}
+
+// ------------------------------------------------------------------ shapes and autotuner
+
+namespace {
+int check_shape(const qdw_op* op, int ts, int nt, int pipe)
+{
+    QDW_CHECK(ts == 64 || ts == 128, QDW_EINVAL, "D kernel shape: ts must be 64 or 128");
+    QDW_CHECK(nt >= 1 && nt <= 8 && op->g.L[0] % nt == 0, QDW_EINVAL,
+              "D kernel shape: nt must divide T and lie in 1..8");
+    QDW_CHECK(pipe == 0 || pipe == 1, QDW_EINVAL, "D kernel shape: pipe must be 0 or 1");
+    return QDW_OK;
+}
+}  // namespace
+
+extern "C" int qdw_set_dw_shape(qdw_op* op, qdw_prec prec, int ts, int nt, int pipe)
+{
+    QDW_CHECK(op, QDW_EINVAL, "qdw_set_dw_shape: null operator");
+    QDW_CHECK(prec >= QDW_F64 && prec <= QDW_BF16S, QDW_EINVAL, "qdw_set_dw_shape: bad precision");
+    const int rc = check_shape(op, ts, nt, pipe);
+    if (rc) return rc;
+    op->dw_shape[prec].ts = ts;
+    op->dw_shape[prec].nt = nt;
+    op->dw_shape[prec].pipe = pipe;
+    return QDW_OK;
+}
+
+extern "C" int qdw_get_dw_shape(const qdw_op* op, qdw_prec prec, int* shape3)
+{
+    QDW_CHECK(op && shape3, QDW_EINVAL, "qdw_get_dw_shape: null argument");
+    QDW_CHECK(prec >= QDW_F64 && prec <= QDW_BF16S, QDW_EINVAL, "qdw_get_dw_shape: bad precision");
+    shape3[0] = op->dw_shape[prec].ts;
+    shape3[1] = op->dw_shape[prec].nt;
+    shape3[2] = op->dw_shape[prec].pipe;
+    return QDW_OK;
+}
+
+extern "C" int qdw_autotune(qdw_op* op, qdw_prec prec, int nrhs, char* report, size_t report_len,
+                            void* stream)
+{
+    QDW_CHECK(op, QDW_EINVAL, "qdw_autotune: null operator");
+    QDW_CHECK(prec >= QDW_F64 && prec <= QDW_BF16S, QDW_EINVAL, "qdw_autotune: bad precision");
+    QDW_CHECK(nrhs >= 1 && nrhs <= kMaxRhs, QDW_EINVAL, "qdw_autotune: need 1 <= nrhs <= 64");
+    hipStream_t st = (hipStream_t)stream;
+    const Geom& g = op->g;
+    const size_t fb = spinor_bytes(g, prec);
+    char* buf = nullptr;
+    QDW_HIP(hipMalloc((void**)&buf, 2 * fb * nrhs));
+    RhsTable tab{};
+    for (int r = 0; r < nrhs; ++r) {
+        tab.in[r] = buf + (size_t)r * fb;
+        tab.out[r] = buf + (size_t)(nrhs + r) * fb;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const auto keep = op->dw_shape[prec];
+    struct Cand { int ts, nt, pipe; float ms; };
+    std::vector<Cand> cands;
+    for (int ts : {64, 128})
+        for (int nt = 1; nt <= 8; nt *= 2) {
+            if (g.L[0] % nt) continue;
+            for (int pipe = 0; pipe < 2; ++pipe) cands.push_back({ts, nt, pipe, 0.f});
+        }
+    int rc = QDW_OK;
+    auto run = [&]() -> int {
+        // the timed fields hold zeros: D's cost does not depend on the values
+        QDW_HIP(hipMemsetAsync(buf, 0, 2 * fb * nrhs, st));
+        QDW_HIP(hipEventCreate(&e0));
+        QDW_HIP(hipEventCreate(&e1));
+        for (Cand& c : cands) {
+            op->dw_shape[prec] = {c.ts, c.nt, c.pipe};
+            int r;
+            for (int w = 0; w < 2; ++w)
+                if ((r = dispatch(op, tab, nrhs, prec, false, st))) return r;
+            const int reps = 8;
+            QDW_HIP(hipEventRecord(e0, st));
+            for (int w = 0; w < reps; ++w)
+                if ((r = dispatch(op, tab, nrhs, prec, false, st))) return r;
+            QDW_HIP(hipEventRecord(e1, st));
+            QDW_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            QDW_HIP(hipEventElapsedTime(&ms, e0, e1));
+            c.ms = ms / reps;
+        }
+        return QDW_OK;
+    };
+    rc = run();
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(buf);
+    if (rc) {
+        op->dw_shape[prec] = keep;
+        return rc;
+    }
+    const Cand* best = &cands[0];
+    for (const Cand& c : cands)
+        if (c.ms < best->ms) best = &c;
+    op->dw_shape[prec] = {best->ts, best->nt, best->pipe};
+    if (report && report_len) {
+        std::string s;
+        char line[200];
+        std::snprintf(line, sizeof line,
+                      "lattice %dx%dx%dx%d prec %d nrhs %d: best ts=%d nt=%d pipe=%d %.4f ms;",
+                      g.L[0], g.L[1], g.L[2], g.L[3], (int)prec, nrhs, best->ts, best->nt,
+                      best->pipe, best->ms);
+        s += line;
+        for (const Cand& c : cands) {
+            std::snprintf(line, sizeof line, " [%d,%d,%d]=%.4f", c.ts, c.nt, c.pipe, c.ms);
+            s += line;
+        }
+        std::snprintf(report, report_len, "%s", s.c_str());
+    }
+    return QDW_OK;
 }

@@ -18,6 +18,9 @@ struct qdw_op {
     void* links[4];
     void* det[4];
     void* clover[4];
+    // per precision: shape of the D kernel (sites per parity of a workgroup, time slices
+    // per walk chunk, software-pipelined hop loop); other site kernels use g.ts and g.nt
+    struct { int ts, nt, pipe; } dw_shape[4];
     // reduction scratch: per-workgroup partial sums and the final scalars
     double* partials;      // device, kMaxPartials * kMaxScalars doubles
     double* scalars;       // device, kMaxScalars doubles
@@ -29,6 +32,7 @@ namespace qdw {
 constexpr int kMaxPartials = 2048;  // workgroups of a reduction launch
 constexpr int kMaxScalars = 64;     // doubles produced by one fused reduction
 constexpr int kHostScalars = 1024;  // doubles the host can read back in one copy
+constexpr int kMaxRhs = 64;         // right-hand sides of one multi-right-hand-side launch
 
 void set_error(const std::string& msg);
 

@@ -33,7 +33,8 @@ struct Geom {
     int V, Vh;
     int bc_t;      // -1 antiperiodic, +1 periodic in time
     int S;         // even-odd sites per time slice and parity (L1*L2*L3/2)
-    int ntile;     // 128-site tiles per time slice (ceil(S/128))
+    int ts;        // sites per parity of a site-kernel workgroup (64 or 128; 2*ts lanes)
+    int ntile;     // ts-site tiles per time slice (ceil(S/ts))
     int nt;        // time slices per chunk of the workgroup walk (a divisor of T, <= 8)
 };
 
@@ -237,25 +238,37 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblk)
     return x * q + (x < r ? x : r) + k;
 }
 
-// Workgroup walk of the site kernels: a workgroup handles one 128-site tile of one time
-// slice (T * ntile workgroups). Consecutive logical workgroups step through the nt time
-// slices of a chunk for one spatial tile before moving to the next tile, so the sites'
-// t +- 1 neighbours are loaded by workgroups running at the same time, and the x1 +- 1
-// neighbours (4 tiles away at 32^3) by workgroups a few dozen positions away -- on the
-// same XCD, whose L2 then serves the halo instead of HBM. Returns false for the lanes
-// of the last, ragged tile of a slice.
-__device__ __forceinline__ bool walk_site(const Geom& g, int logical, int lane, int& i)
+// Workgroup walk of the site kernels: a workgroup handles one ts-site tile of one time
+// slice in both parities (T * ntile workgroups of 2*ts lanes). Consecutive logical
+// workgroups step through the nt time slices of a chunk for one spatial tile before moving
+// to the next tile, so the sites' t +- 1 neighbours are loaded by workgroups running at
+// the same time, and the x1 +- 1 neighbours by workgroups a few dozen positions away -- on
+// the same XCD, whose L2 then serves the halo instead of HBM. ts and nt are chosen per
+// lattice by the autotuner. Returns false for the lanes of the last, ragged tile of a
+// slice; `par` and the lane come from the thread index.
+__device__ __forceinline__ bool walk_site(const Geom& g, int logical, int tid, int& par, int& i)
 {
+    par = tid >= g.ts ? 1 : 0;
+    const int lane = tid - par * g.ts;
     const int per_chunk = g.nt * g.ntile;
     const int c = logical / per_chunk;
     const int r = logical - c * per_chunk;
     const int s = r / g.nt;
     const int t = c * g.nt + (r - s * g.nt);
-    const int k = s * 128 + lane;
+    const int k = s * g.ts + lane;
     i = t * g.S + k;
     return k < g.S;
 }
 
 inline int walk_blocks(const Geom& g) { return g.L[0] * g.ntile; }
+
+// Several right-hand sides of one lattice in one launch (blockIdx.y = right-hand side): their
+// fields sit at a fixed byte stride, and gate[r * gstride] == 0 marks a finished one, whose
+// workgroups return at once. The default is a single field and no gate.
+struct RhsStride {
+    long fstride = 0;
+    const int* gate = nullptr;
+    int gstride = 0;
+};
 
 }  // namespace qdw

@@ -25,4 +25,9 @@ size_t sap_workspace(const qdw_op* op, int sdtype);
 int sap_run(qdw_op* op, const void* rho, void* phi, double rho_norm, int ncy, int nmr,
             const BlockGeom& B, int sdtype, char* work, hipStream_t st);
 
+// ncy Schwarz cycles on the storage-precision fields rs (residual, updated), psis
+// (solution, accumulated) and delta (scratch), for nrhs right-hand sides at bat's stride
+int sap_cycles(qdw_op* op, const BlockGeom& B, int sdtype, int ncy, int nmr, void* rs,
+               void* psis, void* delta, const RhsStride& bat, int nrhs, hipStream_t st);
+
 }  // namespace qdw

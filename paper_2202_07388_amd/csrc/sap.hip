@@ -101,11 +101,17 @@ __global__ __launch_bounds__(256) void sap_mr_kernel(Geom g, BlockGeom B, int co
                                                      void* __restrict__ delta,
                                                      const void* __restrict__ links,
                                                      const void* __restrict__ dets,
-                                                     const void* __restrict__ clover)
+                                                     const void* __restrict__ clover,
+                                                     RhsStride bat)
 {
     __shared__ float rl[24][kBMax];
     __shared__ float hb[4][12][kBMax];
     __shared__ double red[4][3];
+    // right-hand side blockIdx.y of a batch (fields at a fixed byte stride)
+    if (bat.gate && !bat.gate[(long)blockIdx.y * bat.gstride]) return;
+    rs = (char*)rs + blockIdx.y * bat.fstride;
+    psis = (char*)psis + blockIdx.y * bat.fstride;
+    delta = (char*)delta + blockIdx.y * bat.fstride;
     const int t = threadIdx.x;
     const int nw = B.bvol >> 6;
     // the blockIdx-th block of this colour (blocks per x3 row is even, so colours alternate)
@@ -258,11 +264,14 @@ __global__ __launch_bounds__(256) void sap_boundary_kernel(Geom g, BlockGeom B, 
                                                            void* __restrict__ rs,
                                                            const void* __restrict__ delta,
                                                            const void* __restrict__ links,
-                                                           const void* __restrict__ dets)
+                                                           const void* __restrict__ dets,
+                                                           RhsStride bat)
 {
-    const int par = threadIdx.x >> 7;
-    int i;
-    if (!walk_site(g, xcd_tile(blockIdx.x, gridDim.x), threadIdx.x & 127, i)) return;
+    if (bat.gate && !bat.gate[(long)blockIdx.y * bat.gstride]) return;
+    rs = (char*)rs + blockIdx.y * bat.fstride;
+    delta = (const char*)delta + blockIdx.y * bat.fstride;
+    int par, i;
+    if (!walk_site(g, xcd_tile(blockIdx.x, gridDim.x), threadIdx.x, par, i)) return;
     int x[4], lex;
     eo_coords(g, par, i, x, lex);
     const int bc = (x[0] / B.bs[0] + x[1] / B.bs[1] + x[2] / B.bs[2] + x[3] / B.bs[3]) & 1;
@@ -284,6 +293,24 @@ __global__ __launch_bounds__(256) void sap_boundary_kernel(Geom g, BlockGeom B, 
 }
 
 template <int SP>
+int cycles_impl(qdw_op* op, const BlockGeom& B, int ncy, int nmr, void* rs, void* psis,
+                void* delta, const RhsStride& bat, int nrhs, hipStream_t st)
+{
+    const Geom& g = op->g;
+    const dim3 gmr(B.nblk / 2, nrhs), gbd(walk_blocks(g), nrhs);
+    for (int cy = 0; cy < ncy; ++cy)
+        for (int c = 0; c < 2; ++c) {
+            sap_mr_kernel<SP><<<gmr, B.bvol, 0, st>>>(g, B, c, nmr, rs, psis, delta, op->links[SP],
+                                                      op->det[SP], op->clover[SP], bat);
+            QDW_LAUNCH_CHECK();
+            sap_boundary_kernel<SP><<<gbd, 2 * g.ts, 0, st>>>(g, B, c, rs, delta, op->links[SP],
+                                                              op->det[SP], bat);
+            QDW_LAUNCH_CHECK();
+        }
+    return QDW_OK;
+}
+
+template <int SP>
 int sap_impl(qdw_op* op, const void* rho, void* phi, double rho_norm, int ncy, int nmr,
              const BlockGeom& B, char* work, hipStream_t st)
 {
@@ -300,21 +327,22 @@ int sap_impl(qdw_op* op, const void* rho, void* phi, double rho_norm, int ncy, i
     const double s = std::sqrt(24.0 * g.V) / rho_norm;
     if ((rc = run_map(op, ScaleNorm<F64, SP>{rho, rs, s, g.Vh}, st, op->scalars + S_SAP))) return rc;
     if ((rc = run_map(op, Zero<SP>{psis, g.Vh}, st))) return rc;
-    const int nbdw = walk_blocks(g);
-    for (int cy = 0; cy < ncy; ++cy)
-        for (int c = 0; c < 2; ++c) {
-            sap_mr_kernel<SP><<<B.nblk / 2, B.bvol, 0, st>>>(g, B, c, nmr, rs, psis, delta,
-                                                             op->links[SP], op->det[SP],
-                                                             op->clover[SP]);
-            QDW_LAUNCH_CHECK();
-            sap_boundary_kernel<SP><<<nbdw, 256, 0, st>>>(g, B, c, rs, delta, op->links[SP],
-                                                          op->det[SP]);
-            QDW_LAUNCH_CHECK();
-        }
+    if ((rc = sap_cycles(op, B, SP, ncy, nmr, rs, psis, delta, RhsStride{}, 1, st))) return rc;
     return run_map(op, Axpby<SP, F64>{psis, phi, 1.0 / s, 0.0, g.Vh}, st);
 }
 
 }  // namespace
+
+int sap_cycles(qdw_op* op, const BlockGeom& B, int sdtype, int ncy, int nmr, void* rs,
+               void* psis, void* delta, const RhsStride& bat, int nrhs, hipStream_t st)
+{
+    switch (sdtype) {
+    case F32: return cycles_impl<F32>(op, B, ncy, nmr, rs, psis, delta, bat, nrhs, st);
+    case F16S: return cycles_impl<F16S>(op, B, ncy, nmr, rs, psis, delta, bat, nrhs, st);
+    case BF16S: return cycles_impl<BF16S>(op, B, ncy, nmr, rs, psis, delta, bat, nrhs, st);
+    default: QDW_CHECK(false, QDW_EINVAL, "SAP: sdtype must be QDW_F32, QDW_F16S or QDW_BF16S");
+    }
+}
 
 size_t sap_workspace(const qdw_op* op, int sdtype) { return 3 * spinor_bytes(op->g, sdtype) + 256; }
 

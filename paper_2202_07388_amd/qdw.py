@@ -114,6 +114,17 @@ _OPTIONAL: list = [
     ("nn_train_step", [_P, _P, _P, ctypes.c_int, ctypes.c_double, _P, _P, ctypes.c_int,
                        ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double), _P,
                        ctypes.c_size_t, _P], ctypes.c_int),
+    ("dw_apply_multi", [_P, _P, _P, ctypes.c_int, ctypes.c_int, _P], ctypes.c_int),
+    ("qdw_autotune", [_P, ctypes.c_int, ctypes.c_int, ctypes.c_char_p, ctypes.c_size_t, _P],
+     ctypes.c_int),
+    ("qdw_set_dw_shape", [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int],
+     ctypes.c_int),
+    ("qdw_get_dw_shape", [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int * 3)], ctypes.c_int),
+    ("qdw_sap_gcr_batched_workspace_bytes", [_P, ctypes.c_int, ctypes.POINTER(SapGcrParams)],
+     ctypes.c_size_t),
+    ("sap_gcr_solve_batched", [_P, _P, _P, ctypes.c_int, ctypes.POINTER(SapGcrParams), _P,
+                               ctypes.c_size_t, _P, ctypes.POINTER(ctypes.c_double), _P],
+     ctypes.c_int),
     ("qdw_cgne_workspace_bytes", [_P, ctypes.POINTER(CgneParams)], ctypes.c_size_t),
     ("cgne_solve", [_P, _P, _P, ctypes.POINTER(CgneParams), _P, ctypes.c_size_t,
                     ctypes.POINTER(Info), _P], ctypes.c_int),
@@ -294,6 +305,65 @@ def sap_gcr_solve(op: Op, eta, psi, res: float = 1e-10, nmx: int = 2000, nkv: in
     _check(L.sap_gcr_solve(op.handle, _ptr(eta), _ptr(psi), ctypes.byref(prm), _ptr(ws),
                            ws.numel(), ctypes.byref(info), _stream()), "sap_gcr_solve")
     return info.as_dict()
+
+
+def _ptr_array(ts):
+    return (ctypes.c_void_p * len(ts))(*[_ptr(t).value for t in ts])
+
+
+def dw_apply_multi(op: Op, xs, outs, prec: str = "f64"):
+    """outs[r] = D xs[r] for every r, in one launch."""
+    if len(xs) != len(outs):
+        raise QdwError("dw_apply_multi: as many outputs as inputs")
+    _check(load().dw_apply_multi(op.handle, _ptr_array(xs), _ptr_array(outs), len(xs),
+                                 PREC[prec], _stream()), "dw_apply_multi")
+    return outs
+
+
+def autotune(op: Op, prec: str = "f64", nrhs: int = 1) -> str:
+    """Pick the fastest D-kernel shape for this operator; returns the tuner's report."""
+    buf = ctypes.create_string_buffer(4096)
+    _check(load().qdw_autotune(op.handle, PREC[prec], nrhs, buf, len(buf), _stream()),
+           "qdw_autotune")
+    return buf.value.decode()
+
+
+def set_dw_shape(op: Op, prec: str, ts: int, nt: int, pipe: int):
+    """Pin the D kernel's shape for one precision (what the autotuner would choose)."""
+    _check(load().qdw_set_dw_shape(op.handle, PREC[prec], ts, nt, pipe), "qdw_set_dw_shape")
+
+
+def get_dw_shape(op: Op, prec: str = "f64"):
+    """(ts, nt, pipe) of the D kernel for one precision."""
+    out = (ctypes.c_int * 3)()
+    _check(load().qdw_get_dw_shape(op.handle, PREC[prec], ctypes.byref(out)), "qdw_get_dw_shape")
+    return tuple(out)
+
+
+def sap_gcr_solve_batched(ops, etas, psis, res: float = 1e-10, nmx: int = 2000, nkv: int = 16,
+                          ncy: int = 5, nmr: int = 4, bs=(4, 4, 4, 4), sdtype: str = "f16",
+                          precond: str = "sap", work=None):
+    """Solve D_j psi_j = eta_j for every j together (ops may repeat and differ in volume);
+    returns (list of per-solve result dicts, graph set-up time in ms)."""
+    L = load()
+    torch = _torch()
+    n = len(ops)
+    if not (len(etas) == n and len(psis) == n):
+        raise QdwError("sap_gcr_solve_batched: one source and one solution per operator")
+    prm = SapGcrParams(res, nmx, nkv, ncy, nmr, (ctypes.c_int * 4)(*bs), PREC[sdtype],
+                       PRECOND[precond], None)
+    hs = (ctypes.c_void_p * n)(*[o.handle for o in ops])
+    nb = int(L.qdw_sap_gcr_batched_workspace_bytes(hs, n, ctypes.byref(prm)))
+    if nb == 0:
+        raise QdwError("bad batched SAP-GCR settings")
+    if work is None or work.numel() < nb:
+        work = torch.empty(nb, dtype=torch.uint8, device=ops[0].device)
+    infos = (Info * n)()
+    gms = ctypes.c_double(0.0)
+    _check(L.sap_gcr_solve_batched(hs, _ptr_array(etas), _ptr_array(psis), n, ctypes.byref(prm),
+                                   _ptr(work), work.numel(), infos, ctypes.byref(gms),
+                                   _stream()), "sap_gcr_solve_batched")
+    return [i.as_dict() for i in infos], gms.value
 
 
 def sap_apply(op: Op, rho, phi, ncy: int = 5, nmr: int = 4, bs=(4, 4, 4, 4),

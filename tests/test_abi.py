@@ -61,3 +61,19 @@ def test_format_eps_match_paper_table():
     for name, key in (("binary64", "f64"), ("binary32", "f32"), ("binary16", "f16"),
                       ("bfloat16", "bf16")):
         assert abs(qdw.EPS[key] - table[name]) <= 0.05 * table[name]
+
+
+def test_batched_and_tuning_entry_points_reject_bad_arguments_without_gpu(lib):
+    import ctypes
+    assert lib.dw_apply_multi(None, None, None, 1, 0, None) == -1
+    assert b"null" in lib.qdw_last_error()
+    assert lib.qdw_autotune(None, 0, 1, None, 0, None) == -1
+    prm = qdw.SapGcrParams(1e-10, 100, 16, 5, 4, (ctypes.c_int * 4)(4, 4, 4, 4), 2, 1, None)
+    assert lib.qdw_sap_gcr_batched_workspace_bytes(None, 1, ctypes.byref(prm)) == 0
+    infos = (qdw.Info * 1)()
+    rc = lib.sap_gcr_solve_batched(None, None, None, 1, ctypes.byref(prm), None, 0, infos,
+                                   None, None)
+    assert rc == -1
+    # the learned preconditioner is not offered in batched form
+    prm.precond = qdw.PRECOND["nn"]
+    assert lib.qdw_sap_gcr_batched_workspace_bytes(None, 1, ctypes.byref(prm)) == 0
