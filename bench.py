@@ -12,6 +12,10 @@ Also reported, each timed on its own outside the K steps:
     against FP32 and FP16 regular steps with FP64 reset steps;
   * the 24^3 x 48 solve of D psi = eta to 1e-10 (eps = 0.35, m0 = -0.08): plain FP64 GCR
     against SAP-preconditioned GCR (4^4 blocks, 5 cycles, 4 MR steps, FP16 and FP32);
+  * the learned preconditioner: trained on the GPU on 2000 residual/error pairs from
+    plain FP64 GCR solves on four 16^3 x 32 fields (eps = 0.3, m0 = -0.05), then used as
+    the flexible-GCR preconditioner on the 32^3 x 64 field against SAP-GCR and plain GCR,
+    all to 1e-10;
   * a batch of 40 right-hand sides over three lattices of different volumes (16^3 x 32
     with 12 point sources, one per spin and colour; 24^3 x 48 with 4 Gaussian sources;
     8^3 x 16 with 24 Gaussian sources; three independent fields, eps = 0.3, m0 = -0.05),
@@ -142,6 +146,63 @@ def gcr_solves(qdw, syn):
     return out
 
 
+NN_DIMS = (32, 16, 16, 16)
+NN_FIELDS, NN_SOURCES, NN_STEPS, NN_PAIRS = 4, 6, 100, 2000
+
+
+def learned_preconditioner(qdw, syn, op, psi):
+    """Train the network on solver pairs at 16^3x32; evaluate it as the FGCR
+    preconditioner on the 32^3x64 operator against SAP-GCR and plain GCR."""
+    import torch
+    from paper_2202_07388_amd import nn_train
+    t0 = time.perf_counter()
+    groups = []
+    for f in range(NN_FIELDS):
+        seed = 7388 + 40 + f
+        su3, th = syn.gauge_field(NN_DIMS, EPS, EPS_U1, seed)
+        top = qdw.Op(NN_DIMS, su3, th, M0, CSW, -1)
+        del su3, th
+        etas = [top.pack(syn.gaussian_spinor(NN_DIMS, seed + 1000 + k)) for k in range(NN_SOURCES)]
+        r, e = nn_train.solver_pairs(top, etas, NN_STEPS, store="bf16")
+        groups.append((top, r, e))
+    torch.cuda.synchronize()
+    t_pairs = time.perf_counter() - t0
+    # keep NN_PAIRS pairs, drawn evenly from the fields
+    rng = np.random.Generator(np.random.PCG64(7388))
+    per = NN_PAIRS // NN_FIELDS
+    for f, (top, r, e) in enumerate(groups):
+        keep = sorted(rng.permutation(len(r))[:per])
+        groups[f] = (top, [r[i] for i in keep], [e[i] for i in keep])
+    npairs = sum(len(g[1]) for g in groups)
+    log("  nn: %d pairs in %.1f s" % (npairs, t_pairs))
+    t0 = time.perf_counter()
+    w, losses = nn_train.train(None, None, None, "bf16", epochs=3, batch=16, lr=5e-3, m0=M0,
+                               groups=groups)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    for g in groups:
+        g[0].close()
+    del groups
+    log("  nn: trained %d steps in %.1f s, loss %.4f -> %.4f" % (
+        len(losses), t_train, float(np.mean(losses[:10])), float(np.mean(losses[-10:]))))
+    eta = op.pack(psi, "f64")
+    out = {"pairs": npairs, "train_steps": len(losses),
+           "s_pairs": round(t_pairs, 2), "s_train": round(t_train, 2),
+           "loss_first10": round(float(np.mean(losses[:10])), 5),
+           "loss_last10": round(float(np.mean(losses[-10:])), 5)}
+    for name, kw in (("plain_fp64", dict(precond="none")),
+                     ("nn", dict(precond="nn", nn_weights=w)),
+                     ("nn_then_sap_fp16", dict(precond="nn_sap", nn_weights=w, sdtype="f16")),
+                     ("sap_fp16", dict(precond="sap", sdtype="f16"))):
+        x = op.new_field("f64")
+        info = qdw.sap_gcr_solve(op, eta, x, res=1e-10, nmx=5000, nkv=16, ncy=5, nmr=4,
+                                 bs=(4, 4, 4, 4), **kw)
+        out[name] = solve_record(info)
+        log("  gcr 32c64 %s: %s" % (name, out[name]))
+        del x
+    return out
+
+
 BATCH = (((32, 16, 16, 16), "point", 12, 7388 + 31), ((48, 24, 24, 24), "gauss", 4, 7388 + 32),
          ((16, 8, 8, 8), "gauss", 24, 7388 + 33))
 
@@ -209,8 +270,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solves", action="store_true")
+    ap.add_argument("--no-nn", action="store_true", help="skip training the learned preconditioner")
     ap.add_argument("--dw-shape", default=None,
-                    help="ts,nt,pipe: pin the FP64 D-kernel shape instead of autotuning it "
+                    help="ts,nt,pipe,walk: pin the FP64 D-kernel shape instead of autotuning it "
                          "(profiling runs pin the shape the autotuner reported)")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run a plain elementwise kernel that reads and writes 1 GiB "
@@ -239,7 +301,7 @@ def main():
     V = op.V
     if args.dw_shape:
         qdw.set_dw_shape(op, "f64", *[int(v) for v in args.dw_shape.split(",")])
-        tuned = {"f64": "pinned ts,nt,pipe = %s" % args.dw_shape}
+        tuned = {"f64": "pinned ts,nt,pipe,walk = %s" % args.dw_shape}
     else:
         log("autotuning the D kernel ...")
         tuned = {p: qdw.autotune(op, p, 1).split(";")[0] for p in ("f64", "f32", "f16")}
@@ -314,6 +376,8 @@ def main():
     if not args.no_solves:
         log("solves ...")
         out["cgne_32c64"] = cgne_solves(op, qdw, psi)
+        if not args.no_nn:
+            out["learned_precond_32c64"] = learned_preconditioner(qdw, syn, op, psi)
         op.close()
         out["sap_gcr_24c48"] = gcr_solves(qdw, syn)
         out["batched_40rhs"] = batched_solves(qdw, syn)

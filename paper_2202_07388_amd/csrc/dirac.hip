@@ -170,9 +170,7 @@ __global__ __launch_bounds__(256) void dw_kernel(Geom g, RhsTable tab, int nrhs,
 inline Geom shaped(const qdw_op* op, int P)
 {
     Geom g = op->g;
-    g.ts = op->dw_shape[P].ts;
-    g.nt = op->dw_shape[P].nt;
-    g.ntile = (g.S + g.ts - 1) / g.ts;
+    set_walk(g, op->dw_shape[P].ts, op->dw_shape[P].nt, op->dw_shape[P].walk);
     return g;
 }
 
@@ -264,35 +262,63 @@ extern "C" int dw_apply_multi(qdw_op* op, const void* const* in, void* const* ou
 // ------------------------------------------------------------------ shapes and autotuner
 
 namespace {
-int check_shape(const qdw_op* op, int ts, int nt, int pipe)
+// timing input of the autotuner: every stored value a hashed number in [-0.5, 0.5) (all-zero
+// fields would time a faster memory path than real data)
+template <int P>
+__global__ void fill_pattern_kernel(void* buf, long n)
+{
+    using S = typename Traits<P>::store;
+    for (long j = (long)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (long)gridDim.x * blockDim.x) {
+        uint32_t h = (uint32_t)j * 2654435761u;
+        h ^= h >> 15;
+        h *= 2246822519u;
+        h ^= h >> 13;
+        const float v = (float)(h & 0xFFFFu) * (1.0f / 65536.0f) - 0.5f;
+        ((S*)buf)[j] = to_store<P>((typename Traits<P>::real)v);
+    }
+}
+
+int fill_pattern(void* buf, size_t bytes, int prec, hipStream_t st)
+{
+    switch (prec) {
+    case F64: fill_pattern_kernel<F64><<<1024, 256, 0, st>>>(buf, (long)(bytes / 8)); break;
+    case F32: fill_pattern_kernel<F32><<<1024, 256, 0, st>>>(buf, (long)(bytes / 4)); break;
+    case F16S: fill_pattern_kernel<F16S><<<1024, 256, 0, st>>>(buf, (long)(bytes / 2)); break;
+    default: fill_pattern_kernel<BF16S><<<1024, 256, 0, st>>>(buf, (long)(bytes / 2)); break;
+    }
+    QDW_LAUNCH_CHECK();
+    return QDW_OK;
+}
+
+int check_shape(const qdw_op* op, int ts, int nt, int pipe, int walk)
 {
     QDW_CHECK(ts == 64 || ts == 128, QDW_EINVAL, "D kernel shape: ts must be 64 or 128");
-    QDW_CHECK(nt >= 1 && nt <= 8 && op->g.L[0] % nt == 0, QDW_EINVAL,
-              "D kernel shape: nt must divide T and lie in 1..8");
+    QDW_CHECK(nt >= 1 && nt <= 16 && op->g.L[0] % nt == 0, QDW_EINVAL,
+              "D kernel shape: nt must divide T and lie in 1..16");
     QDW_CHECK(pipe == 0 || pipe == 1, QDW_EINVAL, "D kernel shape: pipe must be 0 or 1");
+    QDW_CHECK(walk == 0 || walk == 1, QDW_EINVAL, "D kernel shape: walk must be 0 or 1");
     return QDW_OK;
 }
 }  // namespace
 
-extern "C" int qdw_set_dw_shape(qdw_op* op, qdw_prec prec, int ts, int nt, int pipe)
+extern "C" int qdw_set_dw_shape(qdw_op* op, qdw_prec prec, int ts, int nt, int pipe, int walk)
 {
     QDW_CHECK(op, QDW_EINVAL, "qdw_set_dw_shape: null operator");
     QDW_CHECK(prec >= QDW_F64 && prec <= QDW_BF16S, QDW_EINVAL, "qdw_set_dw_shape: bad precision");
-    const int rc = check_shape(op, ts, nt, pipe);
+    const int rc = check_shape(op, ts, nt, pipe, walk);
     if (rc) return rc;
-    op->dw_shape[prec].ts = ts;
-    op->dw_shape[prec].nt = nt;
-    op->dw_shape[prec].pipe = pipe;
+    op->dw_shape[prec] = {ts, nt, pipe, walk};
     return QDW_OK;
 }
 
-extern "C" int qdw_get_dw_shape(const qdw_op* op, qdw_prec prec, int* shape3)
+extern "C" int qdw_get_dw_shape(const qdw_op* op, qdw_prec prec, int* shape4)
 {
-    QDW_CHECK(op && shape3, QDW_EINVAL, "qdw_get_dw_shape: null argument");
+    QDW_CHECK(op && shape4, QDW_EINVAL, "qdw_get_dw_shape: null argument");
     QDW_CHECK(prec >= QDW_F64 && prec <= QDW_BF16S, QDW_EINVAL, "qdw_get_dw_shape: bad precision");
-    shape3[0] = op->dw_shape[prec].ts;
-    shape3[1] = op->dw_shape[prec].nt;
-    shape3[2] = op->dw_shape[prec].pipe;
+    shape4[0] = op->dw_shape[prec].ts;
+    shape4[1] = op->dw_shape[prec].nt;
+    shape4[2] = op->dw_shape[prec].pipe;
+    shape4[3] = op->dw_shape[prec].walk;
     return QDW_OK;
 }
 
@@ -314,21 +340,22 @@ extern "C" int qdw_autotune(qdw_op* op, qdw_prec prec, int nrhs, char* report, s
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const auto keep = op->dw_shape[prec];
-    struct Cand { int ts, nt, pipe; float ms; };
+    struct Cand { int ts, nt, pipe, walk; float ms; };
     std::vector<Cand> cands;
-    for (int ts : {64, 128})
-        for (int nt = 1; nt <= 8; nt *= 2) {
-            if (g.L[0] % nt) continue;
-            for (int pipe = 0; pipe < 2; ++pipe) cands.push_back({ts, nt, pipe, 0.f});
-        }
+    for (int walk = 0; walk < 2; ++walk)
+        for (int ts : {64, 128})
+            for (int nt = 1; nt <= 16; nt *= 2) {
+                if (g.L[0] % nt) continue;
+                for (int pipe = 0; pipe < 2; ++pipe) cands.push_back({ts, nt, pipe, walk, 0.f});
+            }
     int rc = QDW_OK;
     auto run = [&]() -> int {
-        // the timed fields hold zeros: D's cost does not depend on the values
-        QDW_HIP(hipMemsetAsync(buf, 0, 2 * fb * nrhs, st));
+        int r0 = fill_pattern(buf, 2 * fb * nrhs, prec, st);
+        if (r0) return r0;
         QDW_HIP(hipEventCreate(&e0));
         QDW_HIP(hipEventCreate(&e1));
         for (Cand& c : cands) {
-            op->dw_shape[prec] = {c.ts, c.nt, c.pipe};
+            op->dw_shape[prec] = {c.ts, c.nt, c.pipe, c.walk};
             int r;
             for (int w = 0; w < 2; ++w)
                 if ((r = dispatch(op, tab, nrhs, prec, false, st))) return r;
@@ -356,17 +383,18 @@ extern "C" int qdw_autotune(qdw_op* op, qdw_prec prec, int nrhs, char* report, s
     const Cand* best = &cands[0];
     for (const Cand& c : cands)
         if (c.ms < best->ms) best = &c;
-    op->dw_shape[prec] = {best->ts, best->nt, best->pipe};
+    op->dw_shape[prec] = {best->ts, best->nt, best->pipe, best->walk};
     if (report && report_len) {
         std::string s;
         char line[200];
         std::snprintf(line, sizeof line,
-                      "lattice %dx%dx%dx%d prec %d nrhs %d: best ts=%d nt=%d pipe=%d %.4f ms;",
+                      "lattice %dx%dx%dx%d prec %d nrhs %d: best ts=%d nt=%d pipe=%d walk=%d %.4f ms;",
                       g.L[0], g.L[1], g.L[2], g.L[3], (int)prec, nrhs, best->ts, best->nt,
-                      best->pipe, best->ms);
+                      best->pipe, best->walk, best->ms);
         s += line;
         for (const Cand& c : cands) {
-            std::snprintf(line, sizeof line, " [%d,%d,%d]=%.4f", c.ts, c.nt, c.pipe, c.ms);
+            std::snprintf(line, sizeof line, " [%d,%d,%d,%d]=%.4f", c.ts, c.nt, c.pipe, c.walk,
+                          c.ms);
             s += line;
         }
         std::snprintf(report, report_len, "%s", s.c_str());

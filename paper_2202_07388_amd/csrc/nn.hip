@@ -9,7 +9,9 @@
 // so the network commutes with gauge transformations.
 //
 // GPU mapping of a layer: (1) a transport kernel writes, for every site x and colour c,
-// one row of the matrix A[(x, c)][(p, b, t, re/im)] (t a spin index); (2) the channel
+// one row of the matrix A[(x, c)][(p, b, t, re/im)] (t a spin index), stored in panels of
+// eight columns (one (p, b) group per panel, so each lane writes contiguous runs and
+// consecutive lanes write consecutive runs); (2) the channel
 // mixing is the real GEMM out[(x, c)][(a, s, re/im)] = A B with B the real embedding of the
 // complex weights, run on the matrix cores: bf16 operands and FP32 accumulation
 // (v_mfma_f32_16x16x16_bf16), or FP32 operands (v_mfma_f32_16x16x4_f32) for gradient
@@ -48,6 +50,30 @@ inline int total_weights() { return layer_w_offset(kLayers); }
 inline long rows_of(const Geom& g) { return (long)2 * padded(g.Vh) * 3; }
 inline long rows_padded(const Geom& g) { return (rows_of(g) + 63) & ~63L; }
 
+// A and dA in panels of 8 columns: element (row m, column k) of a matrix with Mp rows
+__device__ __forceinline__ long pidx(long Mp, long m, int k)
+{
+    return (((long)(k >> 3) * Mp + m) << 3) + (k & 7);
+}
+
+// 8 consecutive values of one panel row
+template <bool F32M>
+__device__ __forceinline__ void put8(void* A, long at, const float v[8])
+{
+    if constexpr (F32M) {
+        float4* d = (float4*)((float*)A + at);
+        d[0] = make_float4(v[0], v[1], v[2], v[3]);
+        d[1] = make_float4(v[4], v[5], v[6], v[7]);
+    } else {
+        uint4 r;
+        r.x = (uint32_t)float_to_bf16(v[0]) | ((uint32_t)float_to_bf16(v[1]) << 16);
+        r.y = (uint32_t)float_to_bf16(v[2]) | ((uint32_t)float_to_bf16(v[3]) << 16);
+        r.z = (uint32_t)float_to_bf16(v[4]) | ((uint32_t)float_to_bf16(v[5]) << 16);
+        r.w = (uint32_t)float_to_bf16(v[6]) | ((uint32_t)float_to_bf16(v[7]) << 16);
+        *(uint4*)((uint16_t*)A + at) = r;
+    }
+}
+
 __device__ __forceinline__ uint16_t bf16_bits(float f) { return float_to_bf16(f); }
 
 template <bool F32M>
@@ -66,9 +92,11 @@ __device__ __forceinline__ long f32_addr(int Vh, int par, int i, int s, int c)
 
 // ------------------------------------------------------------------ transport
 //
-// A[(q, c)][((p*Cin + b)*4 + t)*2 + re/im] = (T_p in_b)(q)[t][c], q = par*Vp + i.
+// A[(q, c)][((p*Cin + b)*4 + t)*2 + re/im] = (T_p in_b)(q)[t][c], q = par*Vp + i. Rows of
+// padded sites and the padding columns K..Kpad-1 are written as zeros, so the matrix holds
+// no stale values from earlier use of the workspace.
 template <bool F32M>
-__global__ __launch_bounds__(256) void nn_transport_kernel(Geom g, int Cin, int Kpad,
+__global__ __launch_bounds__(256) void nn_transport_kernel(Geom g, int Cin, int Kpad, long Mp,
                                                            const float* const* in, void* A,
                                                            const void* links, const void* dets)
 {
@@ -79,7 +107,15 @@ __global__ __launch_bounds__(256) void nn_transport_kernel(Geom g, int Cin, int 
     const int b = (int)(tid / nq);
     const long q = tid - (long)b * nq;
     const int par = (int)(q / Vp), i = (int)(q - (long)par * Vp);
-    if (i >= g.Vh) return;  // padded sites keep their zero rows
+    const float zero[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (b == Cin - 1)
+        for (int kg = kPaths * Cin; kg < Kpad / 8; ++kg)
+            for (int c = 0; c < 3; ++c) put8<F32M>(A, pidx(Mp, q * 3 + c, kg * 8), zero);
+    if (i >= g.Vh) {
+        for (int p = 0; p < kPaths; ++p)
+            for (int c = 0; c < 3; ++c) put8<F32M>(A, pidx(Mp, q * 3 + c, (p * Cin + b) * 8), zero);
+        return;
+    }
     int x[4], lex;
     eo_coords(g, par, i, x, lex);
     const float* v = in[b];
@@ -111,20 +147,21 @@ __global__ __launch_bounds__(256) void nn_transport_kernel(Geom g, int Cin, int 
                 for (int k = 0; k < 6; ++k) w[6 * half + k] = o[k];
             }
         }
-        // rows (q, c): 8 consecutive entries (t, re/im) for this (p, b)
-        const int k0 = ((p * Cin + b) * 4) * 2;
+        // rows (q, c): 8 consecutive entries (t, re/im) of the (p, b) panel
+        const int k0 = (p * Cin + b) * 8;
         for (int c = 0; c < 3; ++c) {
-            const long row = (q * 3 + c) * (long)Kpad + k0;
+            float v[8];
             for (int t = 0; t < 4; ++t) {
-                put_el<F32M>(A, row + 2 * t, w[t * 3 + c].re);
-                put_el<F32M>(A, row + 2 * t + 1, w[t * 3 + c].im);
+                v[2 * t] = w[t * 3 + c].re;
+                v[2 * t + 1] = w[t * 3 + c].im;
             }
+            put8<F32M>(A, pidx(Mp, q * 3 + c, k0), v);
         }
     }
 }
 
 // g_b(x) = sum_p T_p^+ dA[p][b](x): T_{+mu}^+ = T_{-mu}, T_{-mu}^+ = T_{+mu}
-__global__ __launch_bounds__(256) void nn_transport_adj_kernel(Geom g, int Cin, int Kpad,
+__global__ __launch_bounds__(256) void nn_transport_adj_kernel(Geom g, int Cin, long Mp,
                                                                const float* dA, float* const* gout,
                                                                const void* links, const void* dets)
 {
@@ -140,10 +177,14 @@ __global__ __launch_bounds__(256) void nn_transport_adj_kernel(Geom g, int Cin, 
     eo_coords(g, par, i, x, lex);
     cx<float> acc[12];
     auto rows = [&](long qq, int p, cx<float> w[12]) {
-        const int k0 = ((p * Cin + b) * 4) * 2;
+        const int k0 = (p * Cin + b) * 8;
         for (int c = 0; c < 3; ++c) {
-            const float* r = dA + (qq * 3 + c) * (long)Kpad + k0;
-            for (int t = 0; t < 4; ++t) w[t * 3 + c] = {r[2 * t], r[2 * t + 1]};
+            const float4* r = (const float4*)(dA + pidx(Mp, qq * 3 + c, k0));
+            const float4 lo = r[0], hi = r[1];
+            w[c] = {lo.x, lo.y};
+            w[3 + c] = {lo.z, lo.w};
+            w[6 + c] = {hi.x, hi.y};
+            w[9 + c] = {hi.z, hi.w};
         }
     };
     rows(q, 0, acc);
@@ -221,19 +262,22 @@ __global__ void nn_dw_kernel(const float* dB, int Cin, int Cout, int Npad, float
 
 // ------------------------------------------------------------------ GEMMs on matrix cores
 
-// acc[j] += A[m0 : m0+16][k0 : k0+KS] * B[k0 : k0+KS][16 j : 16 j + 16] for one wave
+// acc[j] += A[m0 : m0+16][k0 : k0+KS] * B[k0 : k0+KS][16 j : 16 j + 16] for one wave;
+// A row-major (element (m, k) at arow + k for this lane's row) or, with Mp > 0, in panels
 template <bool F32M>
 __device__ __forceinline__ void mfma_step(const void* A, long arow, const void* Bt, long brow0,
-                                          long bstride, int kofs, int nt, f4 acc[4])
+                                          long bstride, int kofs, int nt, f4 acc[4], long Mp = 0,
+                                          long row = 0)
 {
+    const long ai = Mp > 0 ? pidx(Mp, row, kofs) : arow + kofs;
     if constexpr (!F32M) {
-        const s4 a = *(const s4*)((const uint16_t*)A + arow + kofs);
+        const s4 a = *(const s4*)((const uint16_t*)A + ai);
         for (int j = 0; j < nt; ++j) {
             const s4 b = *(const s4*)((const uint16_t*)Bt + brow0 + j * 16 * bstride + kofs);
             acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[j], 0, 0, 0);
         }
     } else {
-        const float a = ((const float*)A)[arow + kofs];
+        const float a = ((const float*)A)[ai];
         for (int j = 0; j < nt; ++j) {
             const float b = ((const float*)Bt)[brow0 + j * 16 * bstride + kofs];
             acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[j], 0, 0, 0);
@@ -244,7 +288,7 @@ __device__ __forceinline__ void mfma_step(const void* A, long arow, const void* 
 // out channels (FP32 fields) = A Bt^T; a workgroup computes 64 rows, a wave 16 rows x Npad
 template <bool F32M>
 __global__ __launch_bounds__(256) void nn_gemm_out_kernel(Geom g, int Kpad, int Npad, int Cout,
-                                                          const void* A, const void* Bt,
+                                                          long Mp, const void* A, const void* Bt,
                                                           float* const* out)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -253,11 +297,11 @@ __global__ __launch_bounds__(256) void nn_gemm_out_kernel(Geom g, int Kpad, int 
     f4 acc[4];
     for (int j = 0; j < 4; ++j) acc[j] = f4{0.f, 0.f, 0.f, 0.f};
     const int KS = F32M ? 4 : 16;
-    const long arow = (m0 + (lane & 15)) * Kpad;
+    const long row = m0 + (lane & 15);
     const long brow0 = (long)(lane & 15) * Kpad;
     const int kl = F32M ? (lane >> 4) : 4 * (lane >> 4);
     for (int k0 = 0; k0 < Kpad; k0 += KS)
-        mfma_step<F32M>(A, arow, Bt, brow0, Kpad, k0 + kl, nt, acc);
+        mfma_step<F32M>(A, 0, Bt, brow0, Kpad, k0 + kl, nt, acc, Mp, row);
     const int Vp = padded(g.Vh);
     for (int j = 0; j < nt; ++j)
         for (int r = 0; r < 4; ++r) {
@@ -275,7 +319,7 @@ __global__ __launch_bounds__(256) void nn_gemm_out_kernel(Geom g, int Kpad, int 
 
 // dA[m][k] = sum_n G[m][n] Bk[k][n]  (G = gradient of the layer output, FP32 rows)
 template <bool F32M>
-__global__ __launch_bounds__(256) void nn_gemm_da_kernel(int Kpad, int Npad, const void* G,
+__global__ __launch_bounds__(256) void nn_gemm_da_kernel(int Kpad, int Npad, long Mp, const void* G,
                                                          const void* Bk, float* dA)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -292,14 +336,14 @@ __global__ __launch_bounds__(256) void nn_gemm_da_kernel(int Kpad, int Npad, con
             mfma_step<F32M>(G, arow, Bk, brow0, Npad, n0 + kl, nt, acc);
         for (int j = 0; j < nt; ++j)
             for (int r = 0; r < 4; ++r)
-                dA[(m0 + 4 * (lane >> 4) + r) * Kpad + (kt + j) * 16 + (lane & 15)] = acc[j][r];
+                dA[pidx(Mp, m0 + 4 * (lane >> 4) + r, (kt + j) * 16 + (lane & 15))] = acc[j][r];
     }
 }
 
 // partial dB[k][n] over a slice of rows: D[k][n] += sum_m A[m][k] G[m][n]
 template <bool F32M>
 __global__ __launch_bounds__(256) void nn_gemm_db_kernel(long M, int Kpad, int Npad, int rows_per,
-                                                         const void* A, const void* G,
+                                                         long Mp, const void* A, const void* G,
                                                          float* part)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -319,7 +363,7 @@ __global__ __launch_bounds__(256) void nn_gemm_db_kernel(long M, int Kpad, int N
             s4 a, b;
             for (int j = 0; j < 4; ++j) {
                 const long mm = m + 4 * (lane >> 4) + j;
-                a[j] = (short)Au[mm * Kpad + kcol];
+                a[j] = (short)Au[pidx(Mp, mm, kcol)];
                 b[j] = (short)Gu[mm * Npad + ncol];
             }
             acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
@@ -329,7 +373,7 @@ __global__ __launch_bounds__(256) void nn_gemm_db_kernel(long M, int Kpad, int N
         const float* Gf = (const float*)G;
         for (long m = mbeg; m < mend; m += 4) {
             const long mm = m + (lane >> 4);
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(Af[mm * Kpad + kcol], Gf[mm * Npad + ncol],
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(Af[pidx(Mp, mm, kcol)], Gf[mm * Npad + ncol],
                                                         acc, 0, 0, 0);
         }
     }
@@ -365,6 +409,192 @@ __global__ __launch_bounds__(256) void nn_pack_g_kernel(Geom g, int Cout, int Np
             if (a < Cout && i < g.Vh) v = scale * gf[a][f32_addr(g.Vh, par, i, s, c) + ri];
             put_el<F32M>(G, (tid * 3 + c) * Npad + n, v);
         }
+}
+
+// ------------------------------------------------------------------ fused forward layer
+//
+// The production forward pass (bf16 operands) fuses transport and mixing: a workgroup
+// owns 64 consecutive sites q (192 rows (q, c)); for each batch of paths (one path when
+// Cin = 8, all nine when Cin = 1) its lanes transport the input channels into an LDS tile
+// of the rows' columns for that batch, then the four wavefronts multiply the tile by the
+// batch's rows of B on the matrix cores, 48 rows each, accumulating in FP32. Columns are
+// visited in the same order as by the unfused kernels, so both give the same sums; the
+// difference is that A never goes to HBM. A lane always transports for the same site
+// (lane mod 64): its coordinates are computed once, and with Cin = 8 one link load serves
+// the lane's two channels.
+
+// neighbour index, boundary sign and link of path p (1..8) at site (par, i)
+__device__ __forceinline__ void nn_path_setup(const Geom& g, int par, int i, const int x[4], int lex,
+                                              int p, const void* links, const void* dets, int& j,
+                                              float& sg, cx<float> u[6], cx<float>& d)
+{
+    const int mu = (p - 1) >> 1;
+    const bool fwd = ((p - 1) & 1) == 0;
+    j = (fwd ? lex_fwd(g, x, lex, mu) : lex_bwd(g, x, lex, mu)) >> 1;
+    sg = 1.f;
+    if (fwd) {
+        load_link<F32>(links, dets, g.Vh, par, i, mu, u, d);
+        if (mu == 0 && x[0] == g.L[0] - 1) sg = (float)g.bc_t;
+    } else {
+        load_link<F32>(links, dets, g.Vh, 1 - par, j, mu, u, d);
+        if (mu == 0 && x[0] == 0) sg = (float)g.bc_t;
+    }
+}
+
+// w = s U sp (forward path) or s U^+ sp (backward path), spin by spin pairs
+__device__ __forceinline__ void nn_path_apply(bool fwd, const cx<float> u[6], cx<float> d, float sg,
+                                              const cx<float> sp[12], cx<float> w[12])
+{
+    cx<float> h[6], o[6];
+    for (int half = 0; half < 2; ++half) {
+        for (int k = 0; k < 6; ++k) h[k] = scale(sp[6 * half + k], sg);
+        if (fwd) su3_mul<float, false>(u, d, h, o);
+        else su3_mul<float, true>(u, d, h, o);
+        for (int k = 0; k < 6; ++k) w[6 * half + k] = o[k];
+    }
+}
+
+// the three rows (site sl, colour c) of one (path, channel) group, as bf16, into the tile
+template <int LS>
+__device__ __forceinline__ void nn_put_rows(uint16_t* tile, int sl, int k0, const cx<float> w[12])
+{
+    for (int c = 0; c < 3; ++c) {
+        uint4 r;
+        r.x = (uint32_t)float_to_bf16(w[c].re) | ((uint32_t)float_to_bf16(w[c].im) << 16);
+        r.y = (uint32_t)float_to_bf16(w[3 + c].re) | ((uint32_t)float_to_bf16(w[3 + c].im) << 16);
+        r.z = (uint32_t)float_to_bf16(w[6 + c].re) | ((uint32_t)float_to_bf16(w[6 + c].im) << 16);
+        r.w = (uint32_t)float_to_bf16(w[9 + c].re) | ((uint32_t)float_to_bf16(w[9 + c].im) << 16);
+        *(uint4*)&tile[(sl * 3 + c) * LS + k0] = r;
+    }
+}
+
+template <int CIN, int COUT>
+__global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, const float* const* in,
+                                                             const void* Bt, float* const* out,
+                                                             const void* links, const void* dets)
+{
+    constexpr int PB = CIN == 1 ? kPaths : 1;          // paths per batch
+    constexpr int KB = (PB * CIN * 8 + 15) & ~15;      // columns per batch (80 or 64)
+    constexpr int LS = KB + 8;                         // LDS row stride (halves)
+    constexpr int NT = COUT * 8 >= 16 ? COUT * 8 / 16 : 1;  // 16-column tiles of N
+    static_assert(CIN == 1 || CIN == 8, "channel counts of the network");
+    // LDS: the transported tile during the batches, then the output block (COUT channels x
+    // 6 chunks x 64 sites x 4 floats, the eo-SoA order of one 64-site block)
+    constexpr int TILE_B = 192 * LS * 2, OUT_B = COUT * 6 * 64 * 16;
+    __shared__ __attribute__((aligned(16))) char lds[TILE_B > OUT_B ? TILE_B : OUT_B];
+    uint16_t* tile = (uint16_t*)lds;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int Vp = padded(g.Vh);
+    const long q0 = (long)blockIdx.x * 64;
+    // this lane's transport site
+    const int sl = lane;
+    const long qs = q0 + sl;
+    const int par = (int)(qs / Vp), i = (int)(qs - (long)par * Vp);
+    const bool real = i < g.Vh;
+    int x[4] = {0, 0, 0, 0}, lex = 0;
+    if (real) eo_coords(g, par, i, x, lex);
+    const cx<float> zero12[12] = {};
+    // Cin = 8: the inputs of the next path (two channels' neighbour spinors and the link)
+    struct Prefetch {
+        cx<float> s0[12], s1[12], u[6], d;
+        float sg;
+    } pf;
+    auto prefetch = [&](int p) {
+        if (p == 0) {
+            load_spinor<F32>(in[wave], g.Vh, par, i, pf.s0);
+            load_spinor<F32>(in[wave + 4], g.Vh, par, i, pf.s1);
+        } else {
+            int j;
+            nn_path_setup(g, par, i, x, lex, p, links, dets, j, pf.sg, pf.u, pf.d);
+            load_spinor<F32>(in[wave], g.Vh, 1 - par, j, pf.s0);
+            load_spinor<F32>(in[wave + 4], g.Vh, 1 - par, j, pf.s1);
+        }
+    };
+    if (CIN == 8 && real) prefetch(0);
+    f4 acc[3][NT];
+    for (int r = 0; r < 3; ++r)
+        for (int j = 0; j < NT; ++j) acc[r][j] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int p0 = 0; p0 < kPaths; p0 += PB) {
+        if constexpr (CIN == 8) {
+            // channels wave and wave + 4 of path p0: the loads were issued before the
+            // previous batch's mixing (below), so they overlap it
+            if (!real) {
+                nn_put_rows<LS>(tile, sl, wave * 8, zero12);
+                nn_put_rows<LS>(tile, sl, (wave + 4) * 8, zero12);
+            } else if (p0 == 0) {
+                nn_put_rows<LS>(tile, sl, wave * 8, pf.s0);
+                nn_put_rows<LS>(tile, sl, (wave + 4) * 8, pf.s1);
+            } else {
+                const bool fwd = ((p0 - 1) & 1) == 0;
+                cx<float> w[12];
+                nn_path_apply(fwd, pf.u, pf.d, pf.sg, pf.s0, w);
+                nn_put_rows<LS>(tile, sl, wave * 8, w);
+                nn_path_apply(fwd, pf.u, pf.d, pf.sg, pf.s1, w);
+                nn_put_rows<LS>(tile, sl, (wave + 4) * 8, w);
+            }
+            if (real && p0 + 1 < kPaths) prefetch(p0 + 1);
+        } else {
+            // paths wave, wave + 4, wave + 8 of the single channel
+            for (int p = wave; p < kPaths; p += 4) {
+                cx<float> w[12];
+                if (!real) {
+                    nn_put_rows<LS>(tile, sl, p * 8, zero12);
+                    continue;
+                }
+                if (p == 0) {
+                    load_spinor<F32>(in[0], g.Vh, par, i, w);
+                } else {
+                    int j;
+                    float sg;
+                    cx<float> u[6], d, sp[12];
+                    nn_path_setup(g, par, i, x, lex, p, links, dets, j, sg, u, d);
+                    load_spinor<F32>(in[0], g.Vh, 1 - par, j, sp);
+                    nn_path_apply(((p - 1) & 1) == 0, u, d, sg, sp, w);
+                }
+                nn_put_rows<LS>(tile, sl, p * 8, w);
+            }
+            // zero padding columns 72..79
+            for (int rr = threadIdx.x; rr < 192; rr += 256)
+                *(uint4*)&tile[rr * LS + kPaths * 8] = uint4{0u, 0u, 0u, 0u};
+        }
+        __syncthreads();
+        // mixing: rows 48*wave .. +48 of the tile times B[p0*CIN*8 .. +KB][0 .. 16 NT]
+        const long kglob = (long)p0 * CIN * 8;
+        for (int kk = 0; kk < KB; kk += 16) {
+            const int kl = kk + 4 * (lane >> 4);
+            s4 bf[NT];
+            for (int j = 0; j < NT; ++j)
+                bf[j] = *(const s4*)((const uint16_t*)Bt + (long)(j * 16 + (lane & 15)) * Kpad + kglob + kl);
+            for (int r = 0; r < 3; ++r) {
+                const s4 a = *(const s4*)&tile[(wave * 48 + r * 16 + (lane & 15)) * LS + kl];
+                for (int j = 0; j < NT; ++j)
+                    acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bf[j], acc[r][j], 0, 0, 0);
+            }
+        }
+        __syncthreads();  // the tile is rewritten by the next batch
+    }
+    // outputs: row m = 3 * site + c, column n = (a * 4 + s) * 2 + re/im, staged in LDS in
+    // the fields' order (the 64 sites are one aligned block of one parity), then written
+    // as contiguous 16-byte chunks
+    float* ob = (float*)lds;
+    for (int r = 0; r < 3; ++r)
+        for (int j = 0; j < NT; ++j)
+            for (int e = 0; e < 4; ++e) {
+                const int m = wave * 48 + r * 16 + 4 * (lane >> 4) + e;
+                const int n = j * 16 + (lane & 15);
+                const int ms = m / 3, c = m - ms * 3;
+                const int a = n >> 3, sp = (n >> 1) & 3, ri = n & 1;
+                if (a >= COUT) continue;
+                const int k12 = sp * 3 + c;
+                ob[((a * 6 + (k12 >> 1)) * 64 + ms) * 4 + (k12 & 1) * 2 + ri] = acc[r][j][e];
+            }
+    __syncthreads();
+    const int opar = (int)(q0 / Vp), oi0 = (int)(q0 - (long)opar * Vp);
+    for (int u = threadIdx.x; u < COUT * 6 * 64; u += 256) {
+        const int a = u / 384, rem = u - a * 384, ch = rem >> 6, site = rem & 63;
+        if (oi0 + site >= g.Vh) continue;
+        ((float4*)out[a])[chunk_at(g.Vh, 6, opar, ch, oi0 + site)] = ((const float4*)ob)[u];
+    }
 }
 
 __global__ void fill_kernel(uint32_t* p, long n)
@@ -476,16 +706,28 @@ int forward(qdw_op* op, const float* weights, NnWork& W, hipStream_t st)
         const int Cin = kCh[l], Cout = kCh[l + 1], Kp = layer_K(l), Np = layer_N(l);
         if ((rc = set_ptrs(W.ptrs, W.act[l], Cin, 0, st))) return rc;
         if ((rc = set_ptrs(W.ptrs, W.act[l + 1], Cout, 1, st))) return rc;
-        if ((rc = zero_dev(W.A, (size_t)Mp * Kp * (F32M ? 4 : 2), st))) return rc;
-        nn_transport_kernel<F32M><<<(unsigned)((nq * Cin + 255) / 256), 256, 0, st>>>(
-            g, Cin, Kp, W.ptrs, W.A, op->links[F32], op->det[F32]);
-        QDW_LAUNCH_CHECK();
         nn_embed_kernel<F32M><<<(Kp * Np + 255) / 256, 256, 0, st>>>(
             weights + 2 * layer_w_offset(l), Cin, Cout, Kp, Np, W.Bt, W.Bk);
         QDW_LAUNCH_CHECK();
-        nn_gemm_out_kernel<F32M><<<(unsigned)(Mp / 64), 256, 0, st>>>(g, Kp, Np, Cout, W.A, W.Bt,
-                                                                      W.ptrs + 8);
-        QDW_LAUNCH_CHECK();
+        if constexpr (!F32M) {
+            const unsigned nb = (unsigned)(nq / 64);
+            const void* L = op->links[F32];
+            const void* D = op->det[F32];
+            if (Cin == 1)
+                nn_layer_fused_kernel<1, 8><<<nb, 256, 0, st>>>(g, Kp, W.ptrs, W.Bt, W.ptrs + 8, L, D);
+            else if (Cout == 8)
+                nn_layer_fused_kernel<8, 8><<<nb, 256, 0, st>>>(g, Kp, W.ptrs, W.Bt, W.ptrs + 8, L, D);
+            else
+                nn_layer_fused_kernel<8, 1><<<nb, 256, 0, st>>>(g, Kp, W.ptrs, W.Bt, W.ptrs + 8, L, D);
+            QDW_LAUNCH_CHECK();
+        } else {
+            nn_transport_kernel<F32M><<<(unsigned)((nq * Cin + 255) / 256), 256, 0, st>>>(
+                g, Cin, Kp, Mp, W.ptrs, W.A, op->links[F32], op->det[F32]);
+            QDW_LAUNCH_CHECK();
+            nn_gemm_out_kernel<F32M><<<(unsigned)(Mp / 64), 256, 0, st>>>(g, Kp, Np, Cout, Mp, W.A,
+                                                                          W.Bt, W.ptrs + 8);
+            QDW_LAUNCH_CHECK();
+        }
     }
     return QDW_OK;
 }
@@ -506,23 +748,21 @@ int backward(qdw_op* op, const float* weights, float* dW, NnWork& W, float gscal
         const int Cin = kCh[l], Cout = kCh[l + 1], Kp = layer_K(l), Np = layer_N(l);
         // recompute this layer's transported input rows
         if ((rc = set_ptrs(W.ptrs, W.act[l], Cin, 0, st))) return rc;
-        if ((rc = zero_dev(W.A, (size_t)Mp * Kp * (F32M ? 4 : 2), st))) return rc;
         nn_transport_kernel<F32M><<<(unsigned)((nq * Cin + 255) / 256), 256, 0, st>>>(
-            g, Cin, Kp, W.ptrs, W.A, op->links[F32], op->det[F32]);
+            g, Cin, Kp, Mp, W.ptrs, W.A, op->links[F32], op->det[F32]);
         QDW_LAUNCH_CHECK();
         nn_embed_kernel<F32M><<<(Kp * Np + 255) / 256, 256, 0, st>>>(
             weights + 2 * layer_w_offset(l), Cin, Cout, Kp, Np, W.Bt, W.Bk);
         QDW_LAUNCH_CHECK();
         // G rows from the output gradient
         if ((rc = set_ptrs(W.ptrs, W.grad[cur], Cout, 1, st))) return rc;
-        if ((rc = zero_dev(W.G, (size_t)Mp * Np * (F32M ? 4 : 2), st))) return rc;
         nn_pack_g_kernel<F32M><<<(unsigned)((nq + 255) / 256), 256, 0, st>>>(
             g, Cout, Np, W.ptrs + 8, l == kLayers - 1 ? gscale : 1.f, W.G);
         QDW_LAUNCH_CHECK();
         // weight gradient dB = A^T G
         const long rows_per = ((M + kSplit - 1) / kSplit + 15) & ~15L;
         nn_gemm_db_kernel<F32M><<<dim3(Kp / 16, kSplit), 256, 0, st>>>(M, Kp, Np, (int)rows_per,
-                                                                      W.A, W.G, W.part);
+                                                                      Mp, W.A, W.G, W.part);
         QDW_LAUNCH_CHECK();
         nn_reduce_db_kernel<<<(Kp * Np + 255) / 256, 256, 0, st>>>(W.part, kSplit, Kp * Np, W.dB);
         QDW_LAUNCH_CHECK();
@@ -531,11 +771,11 @@ int backward(qdw_op* op, const float* weights, float* dW, NnWork& W, float gscal
                                                        dW + 2 * layer_w_offset(l));
         QDW_LAUNCH_CHECK();
         // input gradient dA = G B^T, then the adjoint transport
-        nn_gemm_da_kernel<F32M><<<(unsigned)(Mp / 64), 256, 0, st>>>(Kp, Np, W.G, W.Bk, W.dA);
+        nn_gemm_da_kernel<F32M><<<(unsigned)(Mp / 64), 256, 0, st>>>(Kp, Np, Mp, W.G, W.Bk, W.dA);
         QDW_LAUNCH_CHECK();
         if ((rc = set_ptrs(W.ptrs, W.grad[1 - cur], Cin, 2, st))) return rc;
         nn_transport_adj_kernel<<<(unsigned)((nq * Cin + 255) / 256), 256, 0, st>>>(
-            g, Cin, Kp, W.dA, W.ptrs + 16, op->links[F32], op->det[F32]);
+            g, Cin, Mp, W.dA, W.ptrs + 16, op->links[F32], op->det[F32]);
         QDW_LAUNCH_CHECK();
         cur = 1 - cur;
     }

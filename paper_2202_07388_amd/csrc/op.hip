@@ -399,15 +399,17 @@ extern "C" int qdw_create(const qdw_lattice* lat, const double* su3, const doubl
     g.Vh = (int)(V / 2);
     g.bc_t = lat->bc_t;
     g.S = L[1] * L[2] * L[3] / 2;
-    g.ts = 128;
-    g.ntile = (g.S + g.ts - 1) / g.ts;
-    g.nt = 1;
-    for (int d = 1; d <= 8; ++d)
-        if (L[0] % d == 0) g.nt = d;
+    {
+        int nt = 1;
+        for (int d = 1; d <= 8; ++d)
+            if (L[0] % d == 0) nt = d;
+        set_walk(g, 128, nt, 0);
+    }
     for (int p = 0; p < 4; ++p) {  // defaults; qdw_autotune may change them
         op->dw_shape[p].ts = g.ts;
         op->dw_shape[p].nt = g.nt;
         op->dw_shape[p].pipe = (p == F64 || p == F32) ? 1 : 0;
+        op->dw_shape[p].walk = 0;
     }
     op->m0 = m0;
     op->csw = csw;

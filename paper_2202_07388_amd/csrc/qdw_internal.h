@@ -34,9 +34,23 @@ struct Geom {
     int bc_t;      // -1 antiperiodic, +1 periodic in time
     int S;         // even-odd sites per time slice and parity (L1*L2*L3/2)
     int ts;        // sites per parity of a site-kernel workgroup (64 or 128; 2*ts lanes)
-    int ntile;     // ts-site tiles per time slice (ceil(S/ts))
-    int nt;        // time slices per chunk of the workgroup walk (a divisor of T, <= 8)
+    int ntile;     // workgroups per time slice
+    int nt;        // time slices per chunk of the workgroup walk (a divisor of T, <= 16)
+    int walk;      // workgroup order within a chunk (walk_site)
+    int slab;      // even-odd sites per parity of one x1 slab of a time slice (L2*L3/2)
+    int tps;       // ts-site tiles per slab (walk 1)
 };
+
+// set the walk of the site kernels (ts, nt, walk as in walk_site)
+inline void set_walk(Geom& g, int ts, int nt, int walk)
+{
+    g.ts = ts;
+    g.nt = nt;
+    g.walk = walk;
+    g.slab = g.L[2] * g.L[3] / 2;
+    g.tps = (g.slab + ts - 1) / ts;
+    g.ntile = walk ? g.L[1] * g.tps : (g.S + ts - 1) / ts;
+}
 
 // ---------------------------------------------------------------- scalar types
 
@@ -238,14 +252,20 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblk)
     return x * q + (x < r ? x : r) + k;
 }
 
-// Workgroup walk of the site kernels: a workgroup handles one ts-site tile of one time
-// slice in both parities (T * ntile workgroups of 2*ts lanes). Consecutive logical
-// workgroups step through the nt time slices of a chunk for one spatial tile before moving
-// to the next tile, so the sites' t +- 1 neighbours are loaded by workgroups running at
-// the same time, and the x1 +- 1 neighbours by workgroups a few dozen positions away -- on
-// the same XCD, whose L2 then serves the halo instead of HBM. ts and nt are chosen per
-// lattice by the autotuner. Returns false for the lanes of the last, ragged tile of a
-// slice; `par` and the lane come from the thread index.
+// Workgroup walk of the site kernels: a workgroup handles ts sites of one time slice in
+// both parities (2*ts lanes, T * ntile workgroups). Logical workgroups are grouped in
+// chunks of nt time slices; within a chunk:
+//   walk 0: tiles of ts consecutive even-odd indices of a slice; the nt slices of one tile
+//           are consecutive, then the next tile. The t +- 1 neighbours are loaded by
+//           workgroups running at the same time; the x1 +- 1 neighbours, L2*L3/(2 ts)
+//           tiles away, by workgroups about nt times that many positions away.
+//   walk 1: each x1 slab of a slice (L2*L3/2 sites per parity) is cut into tiles of ts
+//           sites (x2 rows); for one tile position the nt slices and then all L1 slabs
+//           are consecutive, so the t and the x1 neighbours are both loaded by workgroups
+//           a few positions away, and only the x2 neighbours across a tile edge are far.
+// Logical workgroups map XCD-contiguously (xcd_tile), so neighbours in this order share
+// an XCD and its L2. Shapes are chosen per lattice by the autotuner. Returns false for the
+// lanes of a ragged last tile; `par` and the lane come from the thread index.
 __device__ __forceinline__ bool walk_site(const Geom& g, int logical, int tid, int& par, int& i)
 {
     par = tid >= g.ts ? 1 : 0;
@@ -253,11 +273,21 @@ __device__ __forceinline__ bool walk_site(const Geom& g, int logical, int tid, i
     const int per_chunk = g.nt * g.ntile;
     const int c = logical / per_chunk;
     const int r = logical - c * per_chunk;
-    const int s = r / g.nt;
-    const int t = c * g.nt + (r - s * g.nt);
-    const int k = s * g.ts + lane;
-    i = t * g.S + k;
-    return k < g.S;
+    if (g.walk == 0) {
+        const int s = r / g.nt;
+        const int t = c * g.nt + (r - s * g.nt);
+        const int k = s * g.ts + lane;
+        i = t * g.S + k;
+        return k < g.S;
+    }
+    const int per_b = g.nt * g.L[1];
+    const int b = r / per_b;
+    const int r2 = r - b * per_b;
+    const int x1 = r2 / g.nt;
+    const int t = c * g.nt + (r2 - x1 * g.nt);
+    const int k = b * g.ts + lane;
+    i = t * g.S + x1 * g.slab + k;
+    return k < g.slab;
 }
 
 inline int walk_blocks(const Geom& g) { return g.L[0] * g.ntile; }

@@ -68,23 +68,34 @@ def solver_pairs(op: "qdw.Op", etas, steps: int, store: str = "bf16", nkv: int =
 
 
 def train(op: "qdw.Op", rhos, errs, store: str, epochs: int, batch: int, lr: float,
-          m0: float, seed: int = 0, loss: str = "dnorm", log=None):
+          m0: float, seed: int = 0, loss: str = "dnorm", log=None, groups=None):
     """Adam on the pairs; returns the weights tensor and the loss per step. The default
     loss measures N(rho) - e in the D-norm, i.e. the residual a GCR step would leave,
-    which is what the flexible GCR judges a preconditioner by."""
+    which is what the flexible GCR judges a preconditioner by.
+
+    Pairs from several gauge fields: pass groups = [(op_f, rhos_f, errs_f), ...] (op, rhos
+    and errs are then ignored); every batch is drawn from one field, since the network's
+    transports and the loss's D use that field's links."""
     import torch
+    if groups is None:
+        groups = [(op, rhos, errs)]
     w = qdw.nn_weights_tensor(init_weights(m0, seed))
     adam = torch.zeros(4 * qdw.nn_weight_count(), dtype=torch.float32, device=w.device)
     rng = np.random.Generator(np.random.PCG64(seed + 1))
     losses = []
     step = 0
     for ep in range(epochs):
-        order = rng.permutation(len(rhos))
-        for b0 in range(0, len(order) - batch + 1, batch):
-            idx = order[b0:b0 + batch]
+        batches = []
+        for gi, (_, rs, _) in enumerate(groups):
+            order = rng.permutation(len(rs))
+            batches += [(gi, order[b0:b0 + batch]) for b0 in range(0, len(order) - batch + 1, batch)]
+        nb = len(batches)
+        for j in rng.permutation(nb):
+            gi, idx = batches[j]
+            gop, rs, es = groups[gi]
             step += 1
-            losses.append(qdw.nn_train_step(op, w, adam, step, lr, [rhos[i] for i in idx],
-                                            [errs[i] for i in idx], store, loss))
+            losses.append(qdw.nn_train_step(gop, w, adam, step, lr, [rs[i] for i in idx],
+                                            [es[i] for i in idx], store, loss))
         if log:
-            log("epoch %d: mean loss %.4f" % (ep, float(np.mean(losses[-max(1, len(order) // batch):]))))
+            log("epoch %d: mean loss %.4f" % (ep, float(np.mean(losses[-max(1, nb):]))))
     return w, losses

@@ -60,9 +60,10 @@ def test_multi_rhs_rejects_aliasing(ragged):
 
 @pytest.mark.parametrize("prec,tol", [("f64", 1e-13), ("f32", 2e-6)])
 @pytest.mark.parametrize("ts", [64, 128])
-@pytest.mark.parametrize("nt", [1, 2])
+@pytest.mark.parametrize("nt", [1, 2, 3, 6])
 @pytest.mark.parametrize("pipe", [0, 1])
-def test_every_shape_gives_the_same_d(ragged, prec, tol, ts, nt, pipe):
+@pytest.mark.parametrize("walk", [0, 1])
+def test_every_shape_gives_the_same_d(ragged, prec, tol, ts, nt, pipe, walk):
     """Workgroup shape and walk change only the schedule: bit-identical results for one
     hop-loop form. The two forms are separately compiled code (the compiler may fuse
     multiply-adds differently), so across forms the bar is the oracle's."""
@@ -71,11 +72,11 @@ def test_every_shape_gives_the_same_d(ragged, prec, tol, ts, nt, pipe):
     keep = qdw.get_dw_shape(gop, prec)
     x = gop.pack(srcs[0], prec)
     try:
-        qdw.set_dw_shape(gop, prec, 128, 1, pipe)
+        qdw.set_dw_shape(gop, prec, 128, 1, pipe, 0)
         ref = gop.new_field(prec)
         qdw.dw_apply(gop, x, ref, prec)
-        qdw.set_dw_shape(gop, prec, ts, nt, pipe)
-        assert qdw.get_dw_shape(gop, prec) == (ts, nt, pipe)
+        qdw.set_dw_shape(gop, prec, ts, nt, pipe, walk)
+        assert qdw.get_dw_shape(gop, prec) == (ts, nt, pipe, walk)
         out = gop.new_field(prec)
         qdw.dw_apply(gop, x, out, prec)
         dag = gop.new_field(prec)
@@ -89,9 +90,10 @@ def test_every_shape_gives_the_same_d(ragged, prec, tol, ts, nt, pipe):
 
 def test_bad_shapes_rejected(ragged):
     gop, _, _ = ragged
-    for ts, nt, pipe in [(96, 1, 0), (128, 4, 0), (64, 1, 2), (64, 0, 1)]:
+    for ts, nt, pipe, walk in [(96, 1, 0, 0), (128, 4, 0, 0), (64, 1, 2, 0), (64, 0, 1, 0),
+                               (64, 1, 1, 2), (64, 12, 1, 0)]:
         with pytest.raises(qdw.QdwError, match="shape"):
-            qdw.set_dw_shape(gop, "f64", ts, nt, pipe)
+            qdw.set_dw_shape(gop, "f64", ts, nt, pipe, walk)
 
 
 def test_autotune_picks_a_valid_shape_and_keeps_results(ragged):
@@ -101,10 +103,11 @@ def test_autotune_picks_a_valid_shape_and_keeps_results(ragged):
     before = gop.new_field("f64")
     qdw.dw_apply(gop, x, before, "f64")
     rep = qdw.autotune(gop, "f64", nrhs=3)
-    assert "best" in rep and rep.count("[") == 2 * 2 * 2  # ts {64,128} x nt {1,2} x pipe {0,1}
-    ts, nt, pipe = qdw.get_dw_shape(gop, "f64")
-    assert ts in (64, 128) and nt in (1, 2) and pipe in (0, 1)
-    assert "ts=%d nt=%d pipe=%d" % (ts, nt, pipe) in rep
+    # ts {64,128} x nt {1,2} (the powers of two dividing T = 6) x pipe {0,1} x walk {0,1}
+    assert "best" in rep and rep.count("[") == 2 * 2 * 2 * 2
+    ts, nt, pipe, walk = qdw.get_dw_shape(gop, "f64")
+    assert ts in (64, 128) and nt in (1, 2) and pipe in (0, 1) and walk in (0, 1)
+    assert "ts=%d nt=%d pipe=%d walk=%d" % (ts, nt, pipe, walk) in rep
     after = gop.new_field("f64")
     qdw.dw_apply(gop, x, after, "f64")
     assert maxrel(gop.unpack(after, "f64").cpu().numpy(), oop.dw(srcs[1])) <= 1e-13
