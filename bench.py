@@ -45,6 +45,10 @@ M0, CSW, EPS, EPS_U1 = -0.05, 1.7, 0.3, 0.1
 SEED = 7388 + 10
 SAP_DIMS = (48, 24, 24, 24)
 SAP_M0, SAP_EPS, SAP_SEED = -0.08, 0.35, 7388 + 20
+# D-kernel shapes (ts, nt, pipe, walk, march) at 32^3 x 64, as the autotuner picks them on
+# MI355X (profiles/dw_autotune_32c64.md); pinned so that a kernel trace of this script
+# holds only the timed shape's launches (--autotune picks them live)
+PINNED_SHAPES = {"f64": (64, 16, 1, 0, 1), "f32": (128, 16, 1, 0, 1), "f16": (64, 2, 0, 0, 0)}
 # algorithmic bytes per site of one application of D (each datum read once)
 BYTES_PER_SITE = {"f64": 1376, "f32": 688, "f16": 344}
 # HBM traffic measured with rocprofv3 counters for the FP64 kernel (profiles/); reported
@@ -65,12 +69,16 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(shape):
+    """HBM bytes per launch of the FP64 D kernel from the committed counter runs, while the
+    kernel sources and the shape are the ones they were taken with."""
     try:
         t = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
-    return t.get("bytes_per_launch") if t.get("kernel_hash") == kernel_hash() else None
+    if t.get("kernel_hash") != kernel_hash() or list(t.get("shape", [])) != list(shape):
+        return None
+    return t.get("bytes_per_launch")
 
 
 def time_launches(fn, n):
@@ -271,9 +279,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solves", action="store_true")
     ap.add_argument("--no-nn", action="store_true", help="skip training the learned preconditioner")
-    ap.add_argument("--dw-shape", default=None,
-                    help="ts,nt,pipe,walk: pin the FP64 D-kernel shape instead of autotuning it "
-                         "(profiling runs pin the shape the autotuner reported)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the 32^3x64 D-kernel shapes with the autotuner instead of the "
+                         "pinned ones (its own launches then join any kernel trace)")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run a plain elementwise kernel that reads and writes 1 GiB "
                          "(3 launches), to scale hardware byte counters")
@@ -299,12 +307,17 @@ def main():
     op = qdw.Op(DIMS, su3, th, M0, CSW, -1)
     del su3, th
     V = op.V
-    if args.dw_shape:
-        qdw.set_dw_shape(op, "f64", *[int(v) for v in args.dw_shape.split(",")])
-        tuned = {"f64": "pinned ts,nt,pipe,walk = %s" % args.dw_shape}
-    else:
+    if args.autotune:
         log("autotuning the D kernel ...")
-        tuned = {p: qdw.autotune(op, p, 1).split(";")[0] for p in ("f64", "f32", "f16")}
+        tuned = {}
+        for p in ("f64", "f32", "f16"):
+            rep = qdw.autotune(op, p, 1)
+            log("  autotune %s: %s" % (p, rep))
+            tuned[p] = rep.split(";")[0]
+    else:
+        for p, shape in PINNED_SHAPES.items():
+            qdw.set_dw_shape(op, p, *shape)
+        tuned = {p: "pinned ts,nt,pipe,walk,march = %s" % (shape,) for p, shape in PINNED_SHAPES.items()}
     log("  D-kernel shapes: %s" % tuned)
     fields = {}
     for prec in ("f64", "f32", "f16"):
@@ -348,7 +361,7 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    traffic = measured_traffic()
+    traffic = measured_traffic(qdw.get_dw_shape(op, "f64"))
     out = {
         "metric": "Dw GB/s (% HBM peak) at 32^3x64; solve s to rel res 1e-10, plain vs chosen",
         "value": round(gbs, 2),

@@ -113,22 +113,25 @@ int dw_apply_multi(qdw_op* op, const void* const* in, void* const* out, int nrhs
 
 /* Autotuner of the D kernel for this operator (not from the paper): times every shape --
  * workgroup size (64 or 128 sites per parity), walk chunk (1, 2, 4, 8 or 16 time slices,
- * dividing T), hop-loop form (plain or software-pipelined) and walk order (0: tiles of a
- * time slice in index order; 1: x1 slabs innermost, so the t and x1 neighbours of a tile
- * are loaded by nearby workgroups) -- for precision prec and nrhs right-hand sides on the
- * stream, keeps the fastest in op (used by dw_apply, dw_apply_multi and the solvers from
- * then on), and writes a one-line report (best shape, then every candidate's time in ms as
- * [ts,nt,pipe,walk]=ms) to report (host, may be NULL). Times on two scratch fields per
- * right-hand side filled with a fixed non-zero pattern (allocated and freed here);
- * synchronises the stream. Results do not depend on ts, nt or
- * walk; the two hop-loop forms are separately compiled and may differ in the last bit. */
+ * dividing T), hop-loop form (plain or software-pipelined), tile order (walk 0: tiles of a
+ * time slice in index order; 1: x1 slabs innermost, so the x1 neighbours of a tile are
+ * loaded by nearby workgroups) and form (march 0: one workgroup per tile and slice; 1: a
+ * workgroup marches through the chunk's slices of its tile and hands the time hops on
+ * through LDS, so that they are read from memory once) -- for precision prec and nrhs
+ * right-hand sides on the stream, keeps the fastest in op (used by dw_apply,
+ * dw_apply_multi and the solvers from then on), and writes a one-line report (best shape,
+ * then every candidate's time in ms as [ts,nt,pipe,walk,march]=ms) to report (host, may be
+ * NULL). Times on two scratch fields per right-hand side filled with a fixed non-zero
+ * pattern (allocated and freed here); synchronises the stream. Results do not depend on
+ * ts, nt or walk; the hop-loop forms and the marching form are separately compiled and
+ * may differ in the last bit. */
 int qdw_autotune(qdw_op* op, qdw_prec prec, int nrhs, char* report, size_t report_len,
                  void* stream);
 /* Set / read the D kernel's shape for precision prec by hand (ts 64 or 128, nt in 1..16
- * dividing T, pipe 0 or 1, walk 0 or 1; shape4 = {ts, nt, pipe, walk}); QDW_EINVAL for
- * anything else. */
-int qdw_set_dw_shape(qdw_op* op, qdw_prec prec, int ts, int nt, int pipe, int walk);
-int qdw_get_dw_shape(const qdw_op* op, qdw_prec prec, int* shape4);
+ * dividing T, pipe 0 or 1, walk 0 or 1, march 0 or 1 (marching implies pipe 1);
+ * shape5 = {ts, nt, pipe, walk, march}); QDW_EINVAL for anything else. */
+int qdw_set_dw_shape(qdw_op* op, qdw_prec prec, int ts, int nt, int pipe, int walk, int march);
+int qdw_get_dw_shape(const qdw_op* op, qdw_prec prec, int* shape5);
 
 /* Fused BLAS-1 on eo-SoA fields of one precision (device), every reduction accumulated in
  * binary64 (Sec. 2.1: reduction variables in binary64 whatever the working type) in a

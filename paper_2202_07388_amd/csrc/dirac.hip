@@ -166,6 +166,148 @@ __global__ __launch_bounds__(256) void dw_kernel(Geom g, RhsTable tab, int nrhs,
     store_spinor<P>(out, g.Vh, par, i, acc);
 }
 
+// Marching form: a workgroup owns one spatial tile (both parities) and walks the nt time
+// slices of its chunk in order. The time hops then never go to memory twice:
+//   * +t: at step t every lane loads the spinor its own lane will need at t+1; projected
+//     with the +t projector it is exactly the +t neighbour of the partner lane (the other
+//     parity, same even-odd index: the same spatial point one slice down), so it goes to
+//     the partner through LDS;
+//   * -t: at the end of step t each lane has its own spinor and its own forward t link in
+//     hand; it forms U_0^+ (1 -+ gamma_0) psi, the -t hop of the partner's site at t+1,
+//     and hands it over through LDS.
+// Only the spatial hops read neighbours from memory; the neighbouring tiles' workgroups
+// march through the same slices at the same time, so those come from L2. One barrier per
+// step: the LDS buffers are double-buffered by slice parity (see the step comments).
+template <int P, bool DAG>
+__device__ __forceinline__ void march_site_hops(const Geom& g, const void* in, const void* links,
+                                                const void* dets, int par, int i, const int x[4],
+                                                int lex, cx<typename Traits<P>::real> hop[12])
+{
+    // the six spatial hops (loop steps 2..7 of dw_kernel), two register buffers
+    HopIn<P> A, B;
+    load_k<P>(2, g, in, links, dets, par, i, x, lex, A);
+#pragma unroll 1
+    for (int k = 2; k < 8; k += 2) {
+        int ii = i, ll = lex, xx[4] = {x[0], x[1], x[2], x[3]};
+        asm volatile("" : "+v"(ii), "+v"(ll), "+v"(xx[0]), "+v"(xx[1]), "+v"(xx[2]), "+v"(xx[3]));
+        load_k<P>(k + 1, g, in, links, dets, par, ii, xx, ll, B);
+        compute_k<P, DAG>(k, g, xx, A, hop);
+        if (k + 2 < 8) load_k<P>(k + 2, g, in, links, dets, par, ii, xx, ll, A);
+        compute_k<P, DAG>(k + 1, g, xx, B, hop);
+    }
+}
+
+template <int P, bool DAG>
+__global__ __launch_bounds__(256) void dw_march_kernel(Geom g, RhsTable tab, int nrhs,
+                                                       const void* __restrict__ links,
+                                                       const void* __restrict__ dets,
+                                                       const void* __restrict__ clover)
+{
+    using R = typename Traits<P>::real;
+    constexpr int SGF = DAG ? +1 : -1;  // projector of the +t hop: 1 + SGF gamma_0
+    constexpr int SGB = -SGF;           // of the -t hop
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    const int nl = blockDim.x;  // 2 ts lanes
+    R* hp = (R*)smem;           // [2 slots][12 reals][nl]: projected +t neighbours
+    R* pw = hp + 2 * 12 * nl;   // [2 slots][12 reals][nl]: transported -t neighbours
+    const int logical = xcd_tile(blockIdx.x, gridDim.x);
+    const int wg = logical / nrhs;
+    const int rhs = logical - wg * nrhs;
+    if (tab.gate && !tab.gate[(long)rhs * tab.gstride]) return;  // the whole workgroup
+    const void* __restrict__ in = tab.in[rhs];
+    void* __restrict__ out = tab.out[rhs];
+    const int c = wg / g.ntile, s = wg - c * g.ntile;
+    const int t0 = c * g.nt;
+    const int tid = threadIdx.x;
+    const int par = tid >= g.ts ? 1 : 0;
+    const int lane = tid - par * g.ts;
+    const int partner = tid + (par ? -g.ts : g.ts);
+    int k;
+    bool valid;
+    if (g.walk == 0) {
+        k = s * g.ts + lane;
+        valid = k < g.S;
+    } else {
+        const int b = s / g.L[1], x1 = s - b * g.L[1];
+        k = x1 * g.slab + b * g.ts + lane;
+        valid = b * g.ts + lane < g.slab;
+    }
+    auto put6 = [&](R* buf, int slot, int who, const cx<R> v[6]) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            buf[(slot * 12 + 2 * q) * nl + who] = v[q].re;
+            buf[(slot * 12 + 2 * q + 1) * nl + who] = v[q].im;
+        }
+    };
+    auto get6 = [&](const R* buf, int slot, cx<R> v[6]) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q)
+            v[q] = {buf[(slot * 12 + 2 * q) * nl + tid], buf[(slot * 12 + 2 * q + 1) * nl + tid]};
+    };
+    // U_0(y)^+ (1 + SGB gamma_0) psi(y) for the partner's site one slice up (sign when the
+    // hop wraps from T-1 to 0)
+    auto push = [&](int t, int slot) {
+        const int i = t * g.S + k;
+        cx<R> sp[12], h[6], w[6], u[6], d;
+        load_spinor<P>(in, g.Vh, par, i, sp);
+        load_link<P>(links, dets, g.Vh, par, i, 0, u, d);
+        project<R, 0, SGB>(sp, h);
+        if (g.bc_t < 0 && t == g.L[0] - 1) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) h[q] = {-h[q].re, -h[q].im};
+        }
+        su3_mul<R, true>(u, d, h, w);
+        put6(pw, slot, partner, w);
+    };
+    if (valid) push(t0 == 0 ? g.L[0] - 1 : t0 - 1, t0 & 1);
+    for (int step = 0; step < g.nt; ++step) {
+        const int t = t0 + step;
+        const int tn = t + 1 == g.L[0] ? 0 : t + 1;
+        // (1) the spinor this lane owns at t+1, projected for the partner's +t hop; slot
+        //     (t+1)&1 was last read two steps ago, before the previous barrier
+        if (valid) {
+            cx<R> sp[12], h[6];
+            load_spinor<P>(in, g.Vh, par, tn * g.S + k, sp);
+            project<R, 0, SGF>(sp, h);
+            put6(hp, (t + 1) & 1, partner, h);
+        }
+        __syncthreads();
+        if (valid) {
+            const int i = t * g.S + k;
+            int x[4], lex;
+            eo_coords(g, par, i, x, lex);
+            cx<R> hop[12];
+#pragma unroll
+            for (int q = 0; q < 12; ++q) hop[q] = {(R)0, (R)0};
+            {
+                // +t: U_0(x) times the projected neighbour from the partner
+                cx<R> h[6], w[6], u[6], d;
+                get6(hp, (t + 1) & 1, h);
+                if (g.bc_t < 0 && x[0] == g.L[0] - 1) {
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) h[q] = {-h[q].re, -h[q].im};
+                }
+                load_link<P>(links, dets, g.Vh, par, i, 0, u, d);
+                su3_mul<R, false>(u, d, h, w);
+                expand_add<R, 0, SGF>(w, hop);
+                // -t: already transported by the partner
+                get6(pw, t & 1, w);
+                expand_add<R, 0, SGB>(w, hop);
+            }
+            march_site_hops<P, DAG>(g, in, links, dets, par, i, x, lex, hop);
+            cx<R> sp[12], acc[12];
+            load_spinor<P>(in, g.Vh, par, i, sp);
+            clover_apply<P>(clover, g.Vh, par, i, sp, acc);
+#pragma unroll
+            for (int q = 0; q < 12; ++q) acc[q] = acc[q] - scale(hop[q], (R)0.5);
+            store_spinor<P>(out, g.Vh, par, i, acc);
+            // (2) the partner's -t hop at t+1; slot (t+1)&1 was read one step ago, before
+            //     this step's barrier
+            if (step + 1 < g.nt) push(t, (t + 1) & 1);
+        }
+    }
+}
+
 // the operator's geometry with the D kernel's own shape for precision P
 inline Geom shaped(const qdw_op* op, int P)
 {
@@ -178,6 +320,16 @@ template <int P, bool DAG>
 int launch(qdw_op* op, const RhsTable& tab, int nrhs, hipStream_t st)
 {
     const Geom g = shaped(op, P);
+    if (op->dw_shape[P].march) {
+        using R = typename Traits<P>::real;
+        const int nblk = (g.L[0] / g.nt) * g.ntile * nrhs;
+        const size_t lds = (size_t)2 * 2 * 12 * (2 * g.ts) * sizeof(R);
+        static_assert(sizeof(R) == 8 || sizeof(R) == 4, "real type");
+        dw_march_kernel<P, DAG><<<nblk, 2 * g.ts, lds, st>>>(g, tab, nrhs, op->links[P],
+                                                             op->det[P], op->clover[P]);
+        QDW_LAUNCH_CHECK();
+        return QDW_OK;
+    }
     const int nblk = walk_blocks(g) * nrhs;
     if (op->dw_shape[P].pipe)
         dw_kernel<P, DAG, true><<<nblk, 2 * g.ts, 0, st>>>(g, tab, nrhs, op->links[P], op->det[P],
@@ -290,8 +442,16 @@ int fill_pattern(void* buf, size_t bytes, int prec, hipStream_t st)
     return QDW_OK;
 }
 
-int check_shape(const qdw_op* op, int ts, int nt, int pipe, int walk)
+// LDS of a marching workgroup: two double-buffered hand-over arrays of 12 reals per lane
+inline size_t march_lds(int prec, int ts) { return (size_t)96 * ts * (prec == F64 ? 8 : 4); }
+
+int check_shape(const qdw_op* op, int prec, int ts, int nt, int pipe, int walk, int march)
 {
+    QDW_CHECK(!march || march_lds(prec, ts) <= 65536, QDW_EINVAL,
+              "D kernel shape: a marching FP64 workgroup of 128 sites per parity needs more "
+              "than 64 KB of LDS");
+    QDW_CHECK(march == 0 || march == 1, QDW_EINVAL, "D kernel shape: march must be 0 or 1");
+    QDW_CHECK(!march || pipe == 1, QDW_EINVAL, "D kernel shape: the marching form is pipelined");
     QDW_CHECK(ts == 64 || ts == 128, QDW_EINVAL, "D kernel shape: ts must be 64 or 128");
     QDW_CHECK(nt >= 1 && nt <= 16 && op->g.L[0] % nt == 0, QDW_EINVAL,
               "D kernel shape: nt must divide T and lie in 1..16");
@@ -301,24 +461,26 @@ int check_shape(const qdw_op* op, int ts, int nt, int pipe, int walk)
 }
 }  // namespace
 
-extern "C" int qdw_set_dw_shape(qdw_op* op, qdw_prec prec, int ts, int nt, int pipe, int walk)
+extern "C" int qdw_set_dw_shape(qdw_op* op, qdw_prec prec, int ts, int nt, int pipe, int walk,
+                                int march)
 {
     QDW_CHECK(op, QDW_EINVAL, "qdw_set_dw_shape: null operator");
     QDW_CHECK(prec >= QDW_F64 && prec <= QDW_BF16S, QDW_EINVAL, "qdw_set_dw_shape: bad precision");
-    const int rc = check_shape(op, ts, nt, pipe, walk);
+    const int rc = check_shape(op, prec, ts, nt, pipe, walk, march);
     if (rc) return rc;
-    op->dw_shape[prec] = {ts, nt, pipe, walk};
+    op->dw_shape[prec] = {ts, nt, pipe, walk, march};
     return QDW_OK;
 }
 
-extern "C" int qdw_get_dw_shape(const qdw_op* op, qdw_prec prec, int* shape4)
+extern "C" int qdw_get_dw_shape(const qdw_op* op, qdw_prec prec, int* shape5)
 {
-    QDW_CHECK(op && shape4, QDW_EINVAL, "qdw_get_dw_shape: null argument");
+    QDW_CHECK(op && shape5, QDW_EINVAL, "qdw_get_dw_shape: null argument");
     QDW_CHECK(prec >= QDW_F64 && prec <= QDW_BF16S, QDW_EINVAL, "qdw_get_dw_shape: bad precision");
-    shape4[0] = op->dw_shape[prec].ts;
-    shape4[1] = op->dw_shape[prec].nt;
-    shape4[2] = op->dw_shape[prec].pipe;
-    shape4[3] = op->dw_shape[prec].walk;
+    shape5[0] = op->dw_shape[prec].ts;
+    shape5[1] = op->dw_shape[prec].nt;
+    shape5[2] = op->dw_shape[prec].pipe;
+    shape5[3] = op->dw_shape[prec].walk;
+    shape5[4] = op->dw_shape[prec].march;
     return QDW_OK;
 }
 
@@ -340,14 +502,18 @@ extern "C" int qdw_autotune(qdw_op* op, qdw_prec prec, int nrhs, char* report, s
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const auto keep = op->dw_shape[prec];
-    struct Cand { int ts, nt, pipe, walk; float ms; };
+    struct Cand { int ts, nt, pipe, walk, march; float ms; };
     std::vector<Cand> cands;
-    for (int walk = 0; walk < 2; ++walk)
-        for (int ts : {64, 128})
-            for (int nt = 1; nt <= 16; nt *= 2) {
-                if (g.L[0] % nt) continue;
-                for (int pipe = 0; pipe < 2; ++pipe) cands.push_back({ts, nt, pipe, walk, 0.f});
-            }
+    for (int march = 0; march < 2; ++march)
+        for (int walk = 0; walk < 2; ++walk)
+            for (int ts : {64, 128})
+                for (int nt = 1; nt <= 16; nt *= 2) {
+                    if (g.L[0] % nt) continue;
+                    // the marching form pipelines its spatial hops always
+                    if (march && march_lds(prec, ts) > 65536) continue;
+                    for (int pipe = march; pipe < 2; ++pipe)
+                        cands.push_back({ts, nt, pipe, walk, march, 0.f});
+                }
     int rc = QDW_OK;
     auto run = [&]() -> int {
         int r0 = fill_pattern(buf, 2 * fb * nrhs, prec, st);
@@ -355,7 +521,7 @@ extern "C" int qdw_autotune(qdw_op* op, qdw_prec prec, int nrhs, char* report, s
         QDW_HIP(hipEventCreate(&e0));
         QDW_HIP(hipEventCreate(&e1));
         for (Cand& c : cands) {
-            op->dw_shape[prec] = {c.ts, c.nt, c.pipe, c.walk};
+            op->dw_shape[prec] = {c.ts, c.nt, c.pipe, c.walk, c.march};
             int r;
             for (int w = 0; w < 2; ++w)
                 if ((r = dispatch(op, tab, nrhs, prec, false, st))) return r;
@@ -383,18 +549,18 @@ extern "C" int qdw_autotune(qdw_op* op, qdw_prec prec, int nrhs, char* report, s
     const Cand* best = &cands[0];
     for (const Cand& c : cands)
         if (c.ms < best->ms) best = &c;
-    op->dw_shape[prec] = {best->ts, best->nt, best->pipe, best->walk};
+    op->dw_shape[prec] = {best->ts, best->nt, best->pipe, best->walk, best->march};
     if (report && report_len) {
         std::string s;
         char line[200];
         std::snprintf(line, sizeof line,
-                      "lattice %dx%dx%dx%d prec %d nrhs %d: best ts=%d nt=%d pipe=%d walk=%d %.4f ms;",
+                      "lattice %dx%dx%dx%d prec %d nrhs %d: best ts=%d nt=%d pipe=%d walk=%d march=%d %.4f ms;",
                       g.L[0], g.L[1], g.L[2], g.L[3], (int)prec, nrhs, best->ts, best->nt,
-                      best->pipe, best->walk, best->ms);
+                      best->pipe, best->walk, best->march, best->ms);
         s += line;
         for (const Cand& c : cands) {
-            std::snprintf(line, sizeof line, " [%d,%d,%d,%d]=%.4f", c.ts, c.nt, c.pipe, c.walk,
-                          c.ms);
+            std::snprintf(line, sizeof line, " [%d,%d,%d,%d,%d]=%.4f", c.ts, c.nt, c.pipe, c.walk,
+                          c.march, c.ms);
             s += line;
         }
         std::snprintf(report, report_len, "%s", s.c_str());

@@ -410,6 +410,7 @@ extern "C" int qdw_create(const qdw_lattice* lat, const double* su3, const doubl
         op->dw_shape[p].nt = g.nt;
         op->dw_shape[p].pipe = (p == F64 || p == F32) ? 1 : 0;
         op->dw_shape[p].walk = 0;
+        op->dw_shape[p].march = 0;
     }
     op->m0 = m0;
     op->csw = csw;

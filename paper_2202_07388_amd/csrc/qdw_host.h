@@ -19,8 +19,9 @@ struct qdw_op {
     void* det[4];
     void* clover[4];
     // per precision: shape of the D kernel (sites per parity of a workgroup, time slices
-    // per walk chunk, software-pipelined hop loop, walk order); other site kernels use g
-    struct { int ts, nt, pipe, walk; } dw_shape[4];
+    // per walk chunk, software-pipelined hop loop, walk order, marching form); other site
+    // kernels use g
+    struct { int ts, nt, pipe, walk, march; } dw_shape[4];
     // reduction scratch: per-workgroup partial sums and the final scalars
     double* partials;      // device, kMaxPartials * kMaxScalars doubles
     double* scalars;       // device, kMaxScalars doubles

@@ -99,3 +99,31 @@ def train(op: "qdw.Op", rhos, errs, store: str, epochs: int, batch: int, lr: flo
         if log:
             log("epoch %d: mean loss %.4f" % (ep, float(np.mean(losses[-max(1, nb):]))))
     return w, losses
+
+
+def _time_forward(dims, reps: int = 5):
+    """Time the network's forward pass (bf16 matrix-core mixing) on a random field of the
+    given extents, with the identity-path initial weights plus noise."""
+    import time
+    import torch
+    from . import synthetic as syn
+    su3, th = syn.gauge_field(dims, 0.3, 0.1, 7388)
+    op = qdw.Op(dims, su3, th, -0.05, 1.7)
+    del su3, th
+    w = qdw.nn_weights_tensor(init_weights(-0.05, 0, noise=0.1))
+    x = op.pack(syn.gaussian_spinor(dims, 3))
+    y = op.new_field()
+    qdw.nn_forward(op, w, x, y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        qdw.nn_forward(op, w, x, y)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / reps * 1e3
+    print("nn_forward %s: %.3f ms per application" % ("x".join(map(str, dims)), ms), flush=True)
+    op.close()
+
+
+if __name__ == "__main__":
+    import sys
+    _time_forward(tuple(int(v) for v in (sys.argv[1] if len(sys.argv) > 1 else "64,32,32,32").split(",")))

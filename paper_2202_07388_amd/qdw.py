@@ -118,8 +118,8 @@ _OPTIONAL: list = [
     ("qdw_autotune", [_P, ctypes.c_int, ctypes.c_int, ctypes.c_char_p, ctypes.c_size_t, _P],
      ctypes.c_int),
     ("qdw_set_dw_shape", [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                          ctypes.c_int], ctypes.c_int),
-    ("qdw_get_dw_shape", [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int * 4)], ctypes.c_int),
+                          ctypes.c_int, ctypes.c_int], ctypes.c_int),
+    ("qdw_get_dw_shape", [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int * 5)], ctypes.c_int),
     ("qdw_sap_gcr_batched_workspace_bytes", [_P, ctypes.c_int, ctypes.POINTER(SapGcrParams)],
      ctypes.c_size_t),
     ("sap_gcr_solve_batched", [_P, _P, _P, ctypes.c_int, ctypes.POINTER(SapGcrParams), _P,
@@ -328,15 +328,15 @@ def autotune(op: Op, prec: str = "f64", nrhs: int = 1) -> str:
     return buf.value.decode()
 
 
-def set_dw_shape(op: Op, prec: str, ts: int, nt: int, pipe: int, walk: int = 0):
+def set_dw_shape(op: Op, prec: str, ts: int, nt: int, pipe: int, walk: int = 0, march: int = 0):
     """Pin the D kernel's shape for one precision (what the autotuner would choose)."""
-    _check(load().qdw_set_dw_shape(op.handle, PREC[prec], ts, nt, pipe, walk),
+    _check(load().qdw_set_dw_shape(op.handle, PREC[prec], ts, nt, pipe, walk, march),
            "qdw_set_dw_shape")
 
 
 def get_dw_shape(op: Op, prec: str = "f64"):
-    """(ts, nt, pipe, walk) of the D kernel for one precision."""
-    out = (ctypes.c_int * 4)()
+    """(ts, nt, pipe, walk, march) of the D kernel for one precision."""
+    out = (ctypes.c_int * 5)()
     _check(load().qdw_get_dw_shape(op.handle, PREC[prec], ctypes.byref(out)), "qdw_get_dw_shape")
     return tuple(out)
 

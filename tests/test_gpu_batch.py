@@ -58,25 +58,31 @@ def test_multi_rhs_rejects_aliasing(ragged):
         qdw.dw_apply_multi(gop, xs, [xs[1], gop.new_field("f64")], "f64")
 
 
-@pytest.mark.parametrize("prec,tol", [("f64", 1e-13), ("f32", 2e-6)])
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-13), ("f32", 2e-6), ("f16", 2e-2)])
 @pytest.mark.parametrize("ts", [64, 128])
 @pytest.mark.parametrize("nt", [1, 2, 3, 6])
-@pytest.mark.parametrize("pipe", [0, 1])
+@pytest.mark.parametrize("pipe,march", [(0, 0), (1, 0), (1, 1)])
 @pytest.mark.parametrize("walk", [0, 1])
-def test_every_shape_gives_the_same_d(ragged, prec, tol, ts, nt, pipe, walk):
-    """Workgroup shape and walk change only the schedule: bit-identical results for one
-    hop-loop form. The two forms are separately compiled code (the compiler may fuse
-    multiply-adds differently), so across forms the bar is the oracle's."""
+def test_every_shape_gives_the_same_d(ragged, prec, tol, ts, nt, pipe, march, walk):
+    """Workgroup size, walk chunk and tile order change only the schedule: bit-identical
+    results within one kernel form. The forms (plain, pipelined, marching) are separately
+    compiled code (the compiler may fuse multiply-adds differently), so across forms the
+    bar is the oracle's. The marching form hands the time hops over through LDS; nt = 1
+    and 6 (= T) are its edge cases (no hand-over; the whole time extent, wrapping)."""
     import torch
     gop, oop, srcs = ragged
+    if march and prec == "f64" and ts == 128:
+        with pytest.raises(qdw.QdwError, match="LDS"):
+            qdw.set_dw_shape(gop, prec, ts, nt, pipe, walk, march)
+        return
     keep = qdw.get_dw_shape(gop, prec)
     x = gop.pack(srcs[0], prec)
     try:
-        qdw.set_dw_shape(gop, prec, 128, 1, pipe, 0)
+        qdw.set_dw_shape(gop, prec, 64, 1, pipe, 0, march)
         ref = gop.new_field(prec)
         qdw.dw_apply(gop, x, ref, prec)
-        qdw.set_dw_shape(gop, prec, ts, nt, pipe, walk)
-        assert qdw.get_dw_shape(gop, prec) == (ts, nt, pipe, walk)
+        qdw.set_dw_shape(gop, prec, ts, nt, pipe, walk, march)
+        assert qdw.get_dw_shape(gop, prec) == (ts, nt, pipe, walk, march)
         out = gop.new_field(prec)
         qdw.dw_apply(gop, x, out, prec)
         dag = gop.new_field(prec)
@@ -88,12 +94,33 @@ def test_every_shape_gives_the_same_d(ragged, prec, tol, ts, nt, pipe, walk):
     assert maxrel(gop.unpack(dag, prec).cpu().numpy(), oop.dw_dag(srcs[0])) <= tol
 
 
+@pytest.mark.parametrize("march", [0, 1])
+def test_multi_rhs_in_every_form(ragged, march):
+    """Several right-hand sides in one launch of either form equal the single launches."""
+    import torch
+    gop, oop, srcs = ragged
+    keep = qdw.get_dw_shape(gop, "f64")
+    try:
+        qdw.set_dw_shape(gop, "f64", 64, 2, 1, 1, march)
+        xs = [gop.pack(s, "f64") for s in srcs]
+        outs = [gop.new_field("f64") for _ in srcs]
+        qdw.dw_apply_multi(gop, xs, outs, "f64")
+        for s_, x, o in zip(srcs, xs, outs):
+            one = gop.new_field("f64")
+            qdw.dw_apply(gop, x, one, "f64")
+            assert torch.equal(one, o)
+            assert maxrel(gop.unpack(o, "f64").cpu().numpy(), oop.dw(s_)) <= 1e-13
+    finally:
+        qdw.set_dw_shape(gop, "f64", *keep)
+
+
 def test_bad_shapes_rejected(ragged):
     gop, _, _ = ragged
-    for ts, nt, pipe, walk in [(96, 1, 0, 0), (128, 4, 0, 0), (64, 1, 2, 0), (64, 0, 1, 0),
-                               (64, 1, 1, 2), (64, 12, 1, 0)]:
+    for ts, nt, pipe, walk, march in [(96, 1, 0, 0, 0), (128, 4, 0, 0, 0), (64, 1, 2, 0, 0),
+                                      (64, 0, 1, 0, 0), (64, 1, 1, 2, 0), (64, 12, 1, 0, 0),
+                                      (64, 1, 1, 0, 2), (64, 1, 0, 0, 1)]:
         with pytest.raises(qdw.QdwError, match="shape"):
-            qdw.set_dw_shape(gop, "f64", ts, nt, pipe, walk)
+            qdw.set_dw_shape(gop, "f64", ts, nt, pipe, walk, march)
 
 
 def test_autotune_picks_a_valid_shape_and_keeps_results(ragged):
@@ -103,11 +130,12 @@ def test_autotune_picks_a_valid_shape_and_keeps_results(ragged):
     before = gop.new_field("f64")
     qdw.dw_apply(gop, x, before, "f64")
     rep = qdw.autotune(gop, "f64", nrhs=3)
-    # ts {64,128} x nt {1,2} (the powers of two dividing T = 6) x pipe {0,1} x walk {0,1}
-    assert "best" in rep and rep.count("[") == 2 * 2 * 2 * 2
-    ts, nt, pipe, walk = qdw.get_dw_shape(gop, "f64")
+    # plain and pipelined: ts {64,128} x nt {1,2} (the powers of two dividing T = 6) x
+    # pipe {0,1} x walk {0,1}; marching (FP64 at ts 64 only): nt {1,2} x walk {0,1}
+    assert "best" in rep and rep.count("[") == 2 * 2 * 2 * 2 + 2 * 2
+    ts, nt, pipe, walk, march = qdw.get_dw_shape(gop, "f64")
     assert ts in (64, 128) and nt in (1, 2) and pipe in (0, 1) and walk in (0, 1)
-    assert "ts=%d nt=%d pipe=%d walk=%d" % (ts, nt, pipe, walk) in rep
+    assert "ts=%d nt=%d pipe=%d walk=%d march=%d" % (ts, nt, pipe, walk, march) in rep
     after = gop.new_field("f64")
     qdw.dw_apply(gop, x, after, "f64")
     assert maxrel(gop.unpack(after, "f64").cpu().numpy(), oop.dw(srcs[1])) <= 1e-13
