@@ -11,7 +11,8 @@ Also reported, each timed on its own outside the K steps:
   * the 32^3 x 64 normal-equation solve to FP64 true residual 1e-10: plain FP64 CG
     against FP32 and FP16 regular steps with FP64 reset steps;
   * the 24^3 x 48 solve of D psi = eta to 1e-10 (eps = 0.35, m0 = -0.08): plain FP64 GCR
-    against SAP-preconditioned GCR (4^4 blocks, 5 cycles, 4 MR steps, FP16 and FP32);
+    against SAP-preconditioned GCR (4^4 blocks, 5 cycles, 4 MR steps, FP16 and FP32) and
+    adaptive SAP (at most 20 cycles and 20 MR steps, alpha 0.9 and 0.7, FP16);
   * the learned preconditioner: trained on the GPU on 2000 residual/error pairs from
     plain FP64 GCR solves on four 16^3 x 32 fields (eps = 0.3, m0 = -0.05), then used as
     the flexible-GCR preconditioner on the 32^3 x 64 field against SAP-GCR and plain GCR,
@@ -142,12 +143,15 @@ def gcr_solves(qdw, syn):
     del su3, th
     eta = op.pack(syn.gaussian_spinor(SAP_DIMS, SAP_SEED + 1000), "f64")
     out = {}
-    for name, kw in (("plain_fp64", dict(precond="none")),
-                     ("sap_fp16", dict(precond="sap", sdtype="f16")),
-                     ("sap_fp32", dict(precond="sap", sdtype="f32"))):
+    base = dict(ncy=5, nmr=4)
+    adaptive = dict(precond="sap_adaptive", sdtype="f16", ncy=20, nmr=20)
+    for name, kw in (("plain_fp64", dict(base, precond="none")),
+                     ("sap_fp16", dict(base, precond="sap", sdtype="f16")),
+                     ("sap_fp32", dict(base, precond="sap", sdtype="f32")),
+                     ("sap_adaptive_fp16_alpha0.9", dict(adaptive, alpha=0.9)),
+                     ("sap_adaptive_fp16_alpha0.7", dict(adaptive, alpha=0.7))):
         x = op.new_field("f64")
-        info = qdw.sap_gcr_solve(op, eta, x, res=1e-10, nmx=5000, nkv=16, ncy=5, nmr=4,
-                                 bs=(4, 4, 4, 4), **kw)
+        info = qdw.sap_gcr_solve(op, eta, x, res=1e-10, nmx=5000, nkv=16, bs=(4, 4, 4, 4), **kw)
         out[name] = solve_record(info)
         log("  gcr %s: %s" % (name, out[name]))
     op.close()

@@ -198,7 +198,12 @@ enum {
     QDW_PRECOND_NONE = 0,  /* identity: plain GCR, the paper's (ncy, nmr) = (0, 0)          */
     QDW_PRECOND_SAP = 1,   /* Schwarz alternating procedure (Sec. 3)                          */
     QDW_PRECOND_NN = 2,    /* learned gauge-covariant network (not from the paper)            */
-    QDW_PRECOND_NN_SAP = 3 /* network while it reduces the GCR residual, then SAP             */
+    QDW_PRECOND_NN_SAP = 3, /* network while it reduces the GCR residual, then SAP            */
+    QDW_PRECOND_SAP_ADAPTIVE = 4 /* adaptive SAP (Sec. 3.2): ncy and nmr are maxima; a cycle
+                                    stops the application when it did not lower |rho|; a
+                                    block's MR stops after >= 4 steps when |r_b| > sap_alpha
+                                    times its previous value, when |r_b| grew, or when
+                                    |r_b| < res |eta| / (number of blocks)                    */
 };
 
 /* Settings of the SAP-preconditioned flexible GCR (Sec. 3.1, Table 2). The large and the
@@ -216,6 +221,8 @@ typedef struct {
     qdw_prec sdtype;     /* QDW_F32, QDW_F16S or QDW_BF16S storage for the SAP fields      */
     int precond;         /* QDW_PRECOND_*                                                  */
     const void* nn_weights; /* (device) network weights for QDW_PRECOND_NN / _NN_SAP        */
+    double sap_alpha;    /* QDW_PRECOND_SAP_ADAPTIVE: the MR exit factor alpha (0.9 in
+                            Sec. 3.2); ignored otherwise                                    */
 } qdw_sap_gcr_params;
 
 /* Device workspace (bytes) sap_gcr_solve needs (2 nkv + 2 FP64 fields plus the
@@ -283,6 +290,20 @@ int nn_backward(qdw_op* op, const float* weights, const void* in, const void* go
 int nn_train_step(qdw_op* op, float* weights, float* adam, int step, double lr,
                   const void* const* rho, const void* const* err, int nbatch, qdw_prec pair_prec,
                   int loss_kind, double* loss, void* work, size_t work_bytes, void* stream);
+
+/* Adaptive SAP (Sec. 3.2) as one preconditioner application phi = M rho: at most ncy_max
+ * cycles, stopping after the first cycle that did not lower |r| (r = rho - D phi, the
+ * residual the cycles maintain); every block's MR loop runs at most nmr_max steps and
+ * stops after the step that (1) makes >= 4 steps and leaves |r_b| > alpha times its value
+ * one step before, (2) increases |r_b|, or (3) brings |r_b| below tol (absolute, in the
+ * units of rho); blocks with |r_b| < tol at the start take no step. *cycles (host, may be
+ * NULL) receives the cycles run (synchronises the stream); mr_steps (device, may be NULL)
+ * receives the MR steps of every block, int[ncy_max][2][number of blocks / 2] (colour-0
+ * blocks, then colour-1 blocks, each in block-index order); entries of cycles not run are
+ * left as they were. Workspace as for sap_apply. */
+int sap_adaptive_apply(qdw_op* op, const void* rho, void* phi, int ncy_max, int nmr_max,
+                       double alpha, double tol, const int bs[4], qdw_prec sdtype, void* work,
+                       size_t work_bytes, int* cycles, int* mr_steps, void* stream);
 
 /* Device workspace (bytes) of sap_apply for storage precision sdtype. */
 size_t qdw_sap_workspace_bytes(const qdw_op* op, qdw_prec sdtype);

@@ -162,7 +162,8 @@ struct GcrLayout {
 size_t precond_bytes(const qdw_op* op, const qdw_sap_gcr_params& p)
 {
     size_t b = 0;
-    if (p.precond == QDW_PRECOND_SAP || p.precond == QDW_PRECOND_NN_SAP)
+    if (p.precond == QDW_PRECOND_SAP || p.precond == QDW_PRECOND_NN_SAP ||
+        p.precond == QDW_PRECOND_SAP_ADAPTIVE)
         b = sap_workspace(op, p.sdtype);
     if (p.precond == QDW_PRECOND_NN || p.precond == QDW_PRECOND_NN_SAP)
         b = std::max(b, nn_precond_workspace(op));
@@ -196,7 +197,8 @@ int gcr_impl(qdw_op* op, const void* eta, void* psi, const qdw_sap_gcr_params& p
     layout(op, p, work, &L);
     BlockGeom B{};
     int rc;
-    if (p.precond == QDW_PRECOND_SAP || p.precond == QDW_PRECOND_NN_SAP)
+    const bool adaptive = p.precond == QDW_PRECOND_SAP_ADAPTIVE;
+    if (p.precond == QDW_PRECOND_SAP || p.precond == QDW_PRECOND_NN_SAP || adaptive)
         if ((rc = make_block_geom(g, p.bs, &B))) return rc;
 #define TRY(x) do { if ((rc = (x)) != QDW_OK) return rc; } while (0)
     info->status = 0;
@@ -206,6 +208,7 @@ int gcr_impl(qdw_op* op, const void* eta, void* psi, const qdw_sap_gcr_params& p
     info->rel_res_true = 0.0;
     TRY(run_map(op, Zero<F64>{psi, Vh}, st));
     TRY(run_map(op, Axpby<F64, F64>{eta, L.rho, 1.0, 0.0, Vh}, st));
+    if (adaptive) TRY(sap_ctrl_reset_total(sap_ctrl(op, p.sdtype, L.pre), st));
     double eta2;
     TRY(run_map(op, Norm2<F64>{eta, Vh}, st, op->scalars + S_TMP));
     TRY(read_scalars(op, S_TMP, 1, &eta2, st));
@@ -230,6 +233,10 @@ int gcr_impl(qdw_op* op, const void* eta, void* psi, const qdw_sap_gcr_params& p
             } else if (p.precond == QDW_PRECOND_SAP || p.precond == QDW_PRECOND_NN_SAP) {
                 TRY(sap_run(op, L.rho, L.phi[k], rn, p.ncy, p.nmr, B, p.sdtype, L.pre, st));
                 info->n_dw_lo += p.ncy * p.nmr;
+            } else if (adaptive) {
+                // block tolerance: the solve's absolute target shared among the blocks
+                TRY(sap_adaptive_run(op, L.rho, L.phi[k], rn, p.ncy, p.nmr, p.sap_alpha,
+                                     p.res * neta / B.nblk, B, p.sdtype, L.pre, nullptr, st));
             } else {
                 TRY(run_map(op, Axpby<F64, F64>{L.rho, L.phi[k], 1.0, 0.0, Vh}, st));
             }
@@ -310,6 +317,16 @@ int gcr_impl(qdw_op* op, const void* eta, void* psi, const qdw_sap_gcr_params& p
             break;
         }
     }
+    if (adaptive) {
+        // SAP work: cycles run, each counted as nmr block sweeps (an upper bound: blocks
+        // may leave their MR loop early)
+        int total = 0;
+        QDW_HIP(hipMemcpyAsync(op->host_scalars, sap_ctrl(op, p.sdtype, L.pre) + 2, sizeof(int),
+                               hipMemcpyDeviceToHost, st));
+        QDW_HIP(hipStreamSynchronize(st));
+        total = *(const int*)op->host_scalars;
+        info->n_dw_lo = total * p.nmr;
+    }
 #undef TRY
     info->status = status;
     info->n_steps = steps;
@@ -336,9 +353,12 @@ extern "C" int sap_gcr_solve(qdw_op* op, const void* eta, void* psi, const qdw_s
     QDW_CHECK(eta != psi, QDW_EINVAL, "sap_gcr_solve: eta and psi must be distinct");
     QDW_CHECK(p->nkv >= 1 && p->nkv <= kMaxKv, QDW_EINVAL, "sap_gcr_solve: need 1 <= nkv <= 16");
     QDW_CHECK(p->nmx >= 1 && p->res > 0.0, QDW_EINVAL, "sap_gcr_solve: need nmx >= 1, res > 0");
-    QDW_CHECK(p->precond >= QDW_PRECOND_NONE && p->precond <= QDW_PRECOND_NN_SAP, QDW_EINVAL,
+    QDW_CHECK(p->precond >= QDW_PRECOND_NONE && p->precond <= QDW_PRECOND_SAP_ADAPTIVE, QDW_EINVAL,
               "sap_gcr_solve: bad preconditioner");
-    const bool sap = p->precond == QDW_PRECOND_SAP || p->precond == QDW_PRECOND_NN_SAP;
+    const bool sap = p->precond == QDW_PRECOND_SAP || p->precond == QDW_PRECOND_NN_SAP ||
+                     p->precond == QDW_PRECOND_SAP_ADAPTIVE;
+    if (p->precond == QDW_PRECOND_SAP_ADAPTIVE)
+        QDW_CHECK(p->sap_alpha > 0.0, QDW_EINVAL, "sap_gcr_solve: adaptive SAP needs sap_alpha > 0");
     if (sap) {
         QDW_CHECK(p->ncy >= 0 && p->nmr >= 0, QDW_EINVAL, "sap_gcr_solve: ncy, nmr must be >= 0");
         QDW_CHECK(p->sdtype >= QDW_F32 && p->sdtype <= QDW_BF16S, QDW_EINVAL,

@@ -95,6 +95,19 @@ __device__ __forceinline__ void hop_backward(float (*hb)[12][kBMax], const int l
     }
 }
 
+// sum over the block of a per-lane value (one FP64 result, the same in every lane);
+// `slots` must not be read by any lane between the barrier inside and the next barrier
+__device__ __forceinline__ double block_sum(double v, double* slots, int t, int nw)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((t & 63) == 0) slots[t >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += slots[w];
+    return s;
+}
+
 template <int SP>
 __global__ __launch_bounds__(256) void sap_mr_kernel(Geom g, BlockGeom B, int colour, int nmr,
                                                      void* __restrict__ rs, void* __restrict__ psis,
@@ -102,11 +115,12 @@ __global__ __launch_bounds__(256) void sap_mr_kernel(Geom g, BlockGeom B, int co
                                                      const void* __restrict__ links,
                                                      const void* __restrict__ dets,
                                                      const void* __restrict__ clover,
-                                                     RhsStride bat)
+                                                     RhsStride bat, SapAdapt ad)
 {
     __shared__ float rl[24][kBMax];
     __shared__ float hb[4][12][kBMax];
     __shared__ double red[4][3];
+    __shared__ double red2[2][4];
     // right-hand side blockIdx.y of a batch (fields at a fixed byte stride)
     if (bat.gate && !bat.gate[(long)blockIdx.y * bat.gstride]) return;
     rs = (char*)rs + blockIdx.y * bat.fstride;
@@ -152,7 +166,19 @@ __global__ __launch_bounds__(256) void sap_mr_kernel(Geom g, BlockGeom B, int co
         rl[2 * c][t] = r[c].re;
         rl[2 * c + 1][t] = r[c].im;
     }
-    for (int k = 0; k < nmr; ++k) {
+    // adaptive exits (Sec. 3.2): the block residual norm before the first step and after
+    // every step decides, uniformly in the workgroup, whether the MR loop goes on
+    double prev = 0.0;
+    int nsteps = 0;
+    bool go = true;
+    if (ad.on) {
+        float l2 = 0.f;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) l2 += r[c].re * r[c].re + r[c].im * r[c].im;
+        prev = sqrt(block_sum((double)l2, red2[0], t, nw));
+        go = !(prev < (double)ad.tol);
+    }
+    for (int k = 0; k < nmr && go; ++k) {
         __syncthreads();  // rl holds the current block residual
         push_backward<SP, 0>(hb, B, l, t, r, u[0], d[0]);
         push_backward<SP, 1>(hb, B, l, t, r, u[1], d[1]);
@@ -210,13 +236,34 @@ __global__ __launch_bounds__(256) void sap_mr_kernel(Geom g, BlockGeom B, int co
             chi[c] = chi[c] + om * r[c];
             r[c] = r[c] - om * v[c];
         }
+        if (ad.on) {
+            float l2 = 0.f;
+#pragma unroll
+            for (int c = 0; c < 12; ++c) l2 += r[c].re * r[c].re + r[c].im * r[c].im;
+            double v2 = l2;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) v2 += __shfl_xor(v2, o, 64);
+            if ((t & 63) == 0) red2[(k + 1) & 1][t >> 6] = v2;
+        }
         __syncthreads();  // all lanes have read red and rl of this step
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
             rl[2 * c][t] = r[c].re;
             rl[2 * c + 1][t] = r[c].im;
         }
+        ++nsteps;
+        if (ad.on) {
+            double c2 = 0.0;
+            for (int w = 0; w < nw; ++w) c2 += red2[(k + 1) & 1][w];
+            const double cur = sqrt(c2);
+            if ((nsteps >= 4 && cur > (double)ad.alpha * prev) || cur > prev ||
+                cur < (double)ad.tol)
+                go = false;
+            else
+                prev = cur;
+        }
     }
+    if (ad.steps && t == 0) ad.steps[blockIdx.x] = nsteps;
     cx<float> p[12];
     load_spinor<SP>(psis, g.Vh, par, i, p);
 #pragma unroll
@@ -301,7 +348,7 @@ int cycles_impl(qdw_op* op, const BlockGeom& B, int ncy, int nmr, void* rs, void
     for (int cy = 0; cy < ncy; ++cy)
         for (int c = 0; c < 2; ++c) {
             sap_mr_kernel<SP><<<gmr, B.bvol, 0, st>>>(g, B, c, nmr, rs, psis, delta, op->links[SP],
-                                                      op->det[SP], op->clover[SP], bat);
+                                                      op->det[SP], op->clover[SP], bat, SapAdapt{});
             QDW_LAUNCH_CHECK();
             sap_boundary_kernel<SP><<<gbd, 2 * g.ts, 0, st>>>(g, B, c, rs, delta, op->links[SP],
                                                               op->det[SP], bat);
@@ -331,7 +378,94 @@ int sap_impl(qdw_op* op, const void* rho, void* phi, double rho_norm, int ncy, i
     return run_map(op, Axpby<SP, F64>{psis, phi, 1.0 / s, 0.0, g.Vh}, st);
 }
 
+// adaptive cycles: ctrl = {go, cycles done, cycles done over all applications}
+__global__ void sap_ctrl_init_kernel(int* ctrl, int reset_total)
+{
+    ctrl[0] = 1;
+    ctrl[1] = 0;
+    if (reset_total) ctrl[2] = 0;
+}
+
+// after a cycle: count it; go on only while the cycle lowered |r| (sc[S_SAP] holds |r|^2
+// before the cycle, sc[S_SAP_NEW] after it)
+__global__ void sap_ctrl_cycle_kernel(int* ctrl, double* sc)
+{
+    if (!ctrl[0]) return;
+    ctrl[1] += 1;
+    ctrl[2] += 1;
+    if (!(sc[S_SAP_NEW] < sc[S_SAP])) ctrl[0] = 0;
+    else sc[S_SAP] = sc[S_SAP_NEW];
+}
+
+template <int SP>
+int adaptive_impl(qdw_op* op, const void* rho, void* phi, double rho_norm, int ncy_max,
+                  int nmr_max, double alpha, double tol, const BlockGeom& B, char* work,
+                  int* steps, hipStream_t st)
+{
+    const Geom& g = op->g;
+    const size_t fb = spinor_bytes(g, SP);
+    void* rs = work;
+    void* psis = work + fb;
+    void* delta = work + 2 * fb;
+    int* ctrl = (int*)(work + 3 * fb);
+    int rc;
+    if (ncy_max == 0 || !(rho_norm > 0.0))
+        return run_map(op, Axpby<F64, F64>{rho, phi, ncy_max == 0 ? 1.0 : 0.0, 0.0, g.Vh}, st);
+    const double s = std::sqrt(24.0 * g.V) / rho_norm;
+    if ((rc = run_map(op, ScaleNorm<F64, SP>{rho, rs, s, g.Vh}, st, op->scalars + S_SAP))) return rc;
+    if ((rc = run_map(op, Zero<SP>{psis, g.Vh}, st))) return rc;
+    sap_ctrl_init_kernel<<<1, 1, 0, st>>>(ctrl, 0);
+    QDW_LAUNCH_CHECK();
+    RhsStride gate;
+    gate.gate = ctrl;  // every kernel of a cycle returns at once after the stop
+    SapAdapt ad;
+    ad.alpha = (float)alpha;
+    ad.tol = (float)(tol * s);
+    ad.on = 1;
+    const dim3 gmr(B.nblk / 2, 1), gbd(walk_blocks(g), 1);
+    for (int cy = 0; cy < ncy_max; ++cy) {
+        for (int c = 0; c < 2; ++c) {
+            ad.steps = steps ? steps + (long)(2 * cy + c) * (B.nblk / 2) : nullptr;
+            sap_mr_kernel<SP><<<gmr, B.bvol, 0, st>>>(g, B, c, nmr_max, rs, psis, delta,
+                                                      op->links[SP], op->det[SP], op->clover[SP],
+                                                      gate, ad);
+            QDW_LAUNCH_CHECK();
+            sap_boundary_kernel<SP><<<gbd, 2 * g.ts, 0, st>>>(g, B, c, rs, delta, op->links[SP],
+                                                              op->det[SP], gate);
+            QDW_LAUNCH_CHECK();
+        }
+        if ((rc = run_map(op, Norm2<SP>{rs, g.Vh}, st, op->scalars + S_SAP_NEW))) return rc;
+        sap_ctrl_cycle_kernel<<<1, 1, 0, st>>>(ctrl, op->scalars);
+        QDW_LAUNCH_CHECK();
+    }
+    return run_map(op, Axpby<SP, F64>{psis, phi, 1.0 / s, 0.0, g.Vh}, st);
+}
+
 }  // namespace
+
+int sap_adaptive_run(qdw_op* op, const void* rho, void* phi, double rho_norm, int ncy_max,
+                     int nmr_max, double alpha, double tol, const BlockGeom& B, int sdtype,
+                     char* work, int* steps, hipStream_t st)
+{
+    switch (sdtype) {
+    case F32: return adaptive_impl<F32>(op, rho, phi, rho_norm, ncy_max, nmr_max, alpha, tol, B, work, steps, st);
+    case F16S: return adaptive_impl<F16S>(op, rho, phi, rho_norm, ncy_max, nmr_max, alpha, tol, B, work, steps, st);
+    case BF16S: return adaptive_impl<BF16S>(op, rho, phi, rho_norm, ncy_max, nmr_max, alpha, tol, B, work, steps, st);
+    default: QDW_CHECK(false, QDW_EINVAL, "SAP: sdtype must be QDW_F32, QDW_F16S or QDW_BF16S");
+    }
+}
+
+int* sap_ctrl(const qdw_op* op, int sdtype, char* work)
+{
+    return (int*)(work + 3 * spinor_bytes(op->g, sdtype));
+}
+
+int sap_ctrl_reset_total(int* ctrl, hipStream_t st)
+{
+    sap_ctrl_init_kernel<<<1, 1, 0, st>>>(ctrl, 1);
+    QDW_LAUNCH_CHECK();
+    return QDW_OK;
+}
 
 int sap_cycles(qdw_op* op, const BlockGeom& B, int sdtype, int ncy, int nmr, void* rs,
                void* psis, void* delta, const RhsStride& bat, int nrhs, hipStream_t st)
@@ -386,4 +520,39 @@ extern "C" int sap_apply(qdw_op* op, const void* rho, void* phi, int ncy, int nm
     if ((rc = read_scalars(op, S_TMP, 1, &n2, st))) return rc;
     char* wk = (char*)(((uintptr_t)work + 255) & ~(uintptr_t)255);
     return sap_run(op, rho, phi, std::sqrt(n2), ncy, nmr, B, sdtype, wk, st);
+}
+
+extern "C" int sap_adaptive_apply(qdw_op* op, const void* rho, void* phi, int ncy_max, int nmr_max,
+                                  double alpha, double tol, const int bs[4], qdw_prec sdtype,
+                                  void* work, size_t work_bytes, int* cycles, int* mr_steps,
+                                  void* stream)
+{
+    QDW_CHECK(op && rho && phi && bs && work, QDW_EINVAL, "sap_adaptive_apply: null argument");
+    QDW_CHECK(rho != phi, QDW_EINVAL, "sap_adaptive_apply: rho and phi must be distinct");
+    QDW_CHECK(ncy_max >= 0 && nmr_max >= 0, QDW_EINVAL,
+              "sap_adaptive_apply: ncy_max and nmr_max must be >= 0");
+    QDW_CHECK(alpha > 0.0 && tol >= 0.0, QDW_EINVAL, "sap_adaptive_apply: need alpha > 0, tol >= 0");
+    QDW_CHECK(sdtype >= QDW_F32 && sdtype <= QDW_BF16S, QDW_EINVAL,
+              "sap_adaptive_apply: sdtype must be QDW_F32, QDW_F16S or QDW_BF16S");
+    QDW_CHECK(work_bytes >= sap_workspace(op, sdtype), QDW_EWORKSPACE,
+              "sap_adaptive_apply: workspace smaller than qdw_sap_workspace_bytes()");
+    BlockGeom B;
+    int rc = make_block_geom(op->g, bs, &B);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = run_map(op, Norm2<F64>{rho, op->g.Vh}, st, op->scalars + S_TMP))) return rc;
+    double n2;
+    if ((rc = read_scalars(op, S_TMP, 1, &n2, st))) return rc;
+    char* wk = (char*)(((uintptr_t)work + 255) & ~(uintptr_t)255);
+    int* ctrl = sap_ctrl(op, sdtype, wk);
+    if ((rc = sap_ctrl_reset_total(ctrl, st))) return rc;
+    if ((rc = sap_adaptive_run(op, rho, phi, std::sqrt(n2), ncy_max, nmr_max, alpha, tol, B,
+                               sdtype, wk, mr_steps, st)))
+        return rc;
+    if (cycles) {
+        QDW_HIP(hipMemcpyAsync(op->host_scalars, ctrl + 2, sizeof(int), hipMemcpyDeviceToHost, st));
+        QDW_HIP(hipStreamSynchronize(st));
+        *cycles = *(const int*)op->host_scalars;
+    }
+    return QDW_OK;
 }

@@ -88,16 +88,19 @@ class SapGcrParams(ctypes.Structure):
     _fields_ = [("res", ctypes.c_double), ("nmx", ctypes.c_int), ("nkv", ctypes.c_int),
                 ("ncy", ctypes.c_int), ("nmr", ctypes.c_int), ("bs", ctypes.c_int * 4),
                 ("sdtype", ctypes.c_int), ("precond", ctypes.c_int),
-                ("nn_weights", ctypes.c_void_p)]
+                ("nn_weights", ctypes.c_void_p), ("sap_alpha", ctypes.c_double)]
 
 
-PRECOND = {"none": 0, "sap": 1, "nn": 2, "nn_sap": 3}
+PRECOND = {"none": 0, "sap": 1, "nn": 2, "nn_sap": 3, "sap_adaptive": 4}
 
 _OPTIONAL: list = [
     ("qdw_sap_gcr_workspace_bytes", [_P, ctypes.POINTER(SapGcrParams)], ctypes.c_size_t),
     ("sap_gcr_solve", [_P, _P, _P, ctypes.POINTER(SapGcrParams), _P, ctypes.c_size_t,
                        ctypes.POINTER(Info), _P], ctypes.c_int),
     ("qdw_sap_workspace_bytes", [_P, ctypes.c_int], ctypes.c_size_t),
+    ("sap_adaptive_apply", [_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                            ctypes.c_double, ctypes.POINTER(ctypes.c_int * 4), ctypes.c_int, _P,
+                            ctypes.c_size_t, ctypes.POINTER(ctypes.c_int), _P, _P], ctypes.c_int),
     ("sap_apply", [_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int * 4),
                    ctypes.c_int, _P, ctypes.c_size_t, _P], ctypes.c_int),
     ("qdw_axpby", [_P, ctypes.c_double, _P, ctypes.c_double, _P, ctypes.c_int, _P], ctypes.c_int),
@@ -291,12 +294,13 @@ def cgne_solve(op: Op, eta, psi, res: float = 1e-10, nmx: int = 20000, inner: st
 
 def sap_gcr_solve(op: Op, eta, psi, res: float = 1e-10, nmx: int = 2000, nkv: int = 16,
                   ncy: int = 5, nmr: int = 4, bs=(4, 4, 4, 4), sdtype: str = "f16",
-                  precond: str = "sap", nn_weights=None) -> dict:
-    """Solve D psi = eta (FP64 eo-SoA fields) with (SAP-preconditioned) flexible GCR."""
+                  precond: str = "sap", nn_weights=None, alpha: float = 0.9) -> dict:
+    """Solve D psi = eta (FP64 eo-SoA fields) with (SAP-preconditioned) flexible GCR.
+    precond "sap_adaptive": ncy and nmr are maxima, alpha the MR exit factor."""
     L = load()
     w = ctypes.c_void_p(nn_weights.data_ptr()) if nn_weights is not None else None
     prm = SapGcrParams(res, nmx, nkv, ncy, nmr, (ctypes.c_int * 4)(*bs), PREC[sdtype],
-                       PRECOND[precond], w)
+                       PRECOND[precond], w, alpha)
     nb = int(L.qdw_sap_gcr_workspace_bytes(op.handle, ctypes.byref(prm)))
     if nb == 0:
         raise QdwError("bad SAP-GCR settings")
@@ -352,7 +356,7 @@ def sap_gcr_solve_batched(ops, etas, psis, res: float = 1e-10, nmx: int = 2000, 
     if not (len(etas) == n and len(psis) == n):
         raise QdwError("sap_gcr_solve_batched: one source and one solution per operator")
     prm = SapGcrParams(res, nmx, nkv, ncy, nmr, (ctypes.c_int * 4)(*bs), PREC[sdtype],
-                       PRECOND[precond], None)
+                       PRECOND[precond], None, 0.9)
     hs = (ctypes.c_void_p * n)(*[o.handle for o in ops])
     nb = int(L.qdw_sap_gcr_batched_workspace_bytes(hs, n, ctypes.byref(prm)))
     if nb == 0:
@@ -365,6 +369,24 @@ def sap_gcr_solve_batched(ops, etas, psis, res: float = 1e-10, nmx: int = 2000, 
                                    _ptr(work), work.numel(), infos, ctypes.byref(gms),
                                    _stream()), "sap_gcr_solve_batched")
     return [i.as_dict() for i in infos], gms.value
+
+
+def sap_adaptive_apply(op: Op, rho, phi, ncy_max: int = 20, nmr_max: int = 20,
+                       alpha: float = 0.9, tol: float = 0.0, bs=(4, 4, 4, 4),
+                       sdtype: str = "f16", steps=None) -> int:
+    """phi = adaptive SAP applied to rho (FP64 fields); returns the cycles run. steps: an
+    optional device int32 tensor of ncy_max * 2 * (blocks / 2) entries for the per-block MR
+    step counts."""
+    L = load()
+    nb = int(L.qdw_sap_workspace_bytes(op.handle, PREC[sdtype]))
+    ws = _workspace(op, nb)
+    cyc = ctypes.c_int(0)
+    sp = _ptr(steps) if steps is not None else None
+    _check(L.sap_adaptive_apply(op.handle, _ptr(rho), _ptr(phi), ncy_max, nmr_max, alpha, tol,
+                                ctypes.byref((ctypes.c_int * 4)(*bs)), PREC[sdtype], _ptr(ws),
+                                ws.numel(), ctypes.byref(cyc), sp, _stream()),
+           "sap_adaptive_apply")
+    return cyc.value
 
 
 def sap_apply(op: Op, rho, phi, ncy: int = 5, nmr: int = 4, bs=(4, 4, 4, 4),

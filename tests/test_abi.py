@@ -77,3 +77,11 @@ def test_batched_and_tuning_entry_points_reject_bad_arguments_without_gpu(lib):
     # the learned preconditioner is not offered in batched form
     prm.precond = qdw.PRECOND["nn"]
     assert lib.qdw_sap_gcr_batched_workspace_bytes(None, 1, ctypes.byref(prm)) == 0
+
+
+def test_adaptive_sap_rejects_bad_arguments_without_gpu(lib):
+    import ctypes
+    bs = (ctypes.c_int * 4)(4, 4, 4, 4)
+    rc = lib.sap_adaptive_apply(None, None, None, 20, 20, 0.9, 0.0, ctypes.byref(bs), 2, None, 0,
+                                None, None, None)
+    assert rc == -1 and b"null" in lib.qdw_last_error()

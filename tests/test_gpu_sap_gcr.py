@@ -130,3 +130,60 @@ def test_gcr_nmx_and_restarts(lat8):
     dims, gop, oop, eta = lat8
     _, info, _ = _gcr(gop, eta, res=1e-10, nmx=5, nkv=2, precond="none")
     assert info["status"] == -1 and info["n_steps"] == 5 and info["nreset"] == 3
+
+
+# ---------------------------------------------------------------- adaptive SAP (Sec. 3.2)
+
+def _adaptive_gpu(gop, rho, bs, ncy, nmr, alpha, tol, sdtype):
+    import torch
+    nblk = int(np.prod([d // b for d, b in zip(gop.dims, bs)]))
+    steps = torch.full((ncy * 2 * (nblk // 2),), -1, dtype=torch.int32, device=gop.device)
+    r = gop.pack(rho, "f64")
+    phi = gop.new_field("f64")
+    cyc = qdw.sap_adaptive_apply(gop, r, phi, ncy, nmr, alpha, tol, bs, sdtype, steps)
+    st = steps.cpu().numpy().reshape(ncy, 2, nblk // 2)
+    return gop.unpack(phi, "f64").cpu().numpy(), cyc, st
+
+
+@pytest.mark.parametrize("alpha", [0.9, 0.7])
+def test_adaptive_sap_matches_oracle(lat8, alpha):
+    """Cycles, per-block MR step counts and the result of the adaptive exits, against the
+    oracle's adaptive SAP. FP32 storage: a norm comparison can only flip when two norms
+    agree to ~1e-6; then the counts differ in a few blocks and the results move apart by
+    about one MR step, hence the two bars."""
+    dims, gop, oop, rho = lat8
+    bs = (4, 4, 4, 4)
+    tol = 1e-3 * np.linalg.norm(rho) / 16
+    got, cyc, st = _adaptive_gpu(gop, rho, bs, 20, 20, alpha, tol, "f32")
+    want, ocyc, osteps = oracle.sap_adaptive(oop, rho, bs, 20, 20, alpha, tol)
+    assert cyc == ocyc, (cyc, ocyc)
+    ost = np.array(osteps).reshape(ocyc, 2, -1)
+    same = np.mean(st[:cyc] == ost)
+    assert (st[cyc:] == -1).all()
+    if same == 1.0:
+        assert rel(got, want) <= 1e-4, rel(got, want)
+    else:
+        assert same >= 0.95 and rel(got, want) <= 5e-2, (same, rel(got, want))
+    assert ost.max() > 4  # the exits were exercised beyond the minimum of 4 steps
+
+
+def test_adaptive_sap_tol_exit(lat8):
+    """Every block already below the tolerance: no MR step anywhere, phi = 0, one cycle
+    (which did not lower |r|)."""
+    dims, gop, oop, rho = lat8
+    got, cyc, st = _adaptive_gpu(gop, rho, (4, 4, 4, 4), 5, 20, 0.9,
+                                 10.0 * np.linalg.norm(rho), "f16")
+    assert cyc == 1 and (st[0] == 0).all() and (st[1:] == -1).all()
+    assert np.abs(got).max() == 0.0
+
+
+@pytest.mark.parametrize("alpha,sdtype", [(0.9, "f16"), (0.7, "f16"), (0.9, "f32")])
+def test_gcr_adaptive_sap_reaches_fp64_residual(lat8, solved, alpha, sdtype):
+    dims, gop, oop, eta = lat8
+    x, info, _ = _gcr(gop, eta, res=1e-10, nkv=16, ncy=20, nmr=20, bs=(4, 4, 4, 4),
+                      sdtype=sdtype, precond="sap_adaptive", alpha=alpha)
+    assert info["status"] > 0 and info["rel_res_true"] <= 1e-10, info
+    assert info["n_dw_lo"] > 0
+    r = eta - oop.dw(x)
+    assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(eta)
+    assert rel(x, solved) <= 1e-7
