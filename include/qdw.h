@@ -178,6 +178,16 @@ typedef struct {
     int keep_p;      /* 1: a reset keeps the search direction (reliable update) as long as
                         the recursive residual stayed within 30 % of the true one, else
                         restarts; 0: every reset restarts CG from the new residual          */
+    int cascade;     /* 1: precision cascade (Sec. 2.1: start in a 16-bit type until the
+                        residual falls below a constant times its epsilon, continue in a
+                        32-bit type until that is exhausted, finish in binary64): `inner` is
+                        ignored; phases BF16 storage -> FP32 -> FP64, each a CG on the
+                        current FP64 residual D^+ D delta = eta - D^+ D psi, psi += delta,
+                        until |eta - D^+ D psi| / |eta| <= cascade_c eps(type) (Table 1
+                        epsilons) or the phase stagnates; the FP64 phase finishes to res.
+                        n_dw_hi then counts every FP64 application, n_dw_lo the BF16 and
+                        FP32 ones; nreset counts resets and phase switches. 0: off           */
+    double cascade_c;  /* the constant of the phase switch (default 1 when <= 0)           */
 } qdw_cgne_params;
 
 /* Device workspace (bytes) cgne_solve needs for these settings. 0 on bad arguments. */

@@ -16,6 +16,7 @@
 // keeps FP16-stored components near unit size (Table 1: binary16 has no normal numbers
 // below 6.1e-5). By default the search direction is kept (rescaled) -- a reliable update;
 // keep_p = 0 restarts it from r instead.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 
@@ -253,11 +254,111 @@ size_t workspace(const qdw_op* op, int inner)
     return b + 256;
 }
 
+
+size_t cascade_workspace(const qdw_op* op)
+{
+    const size_t f = spinor_bytes(op->g, F64);
+    size_t sub = std::max(workspace(op, F64), std::max(workspace(op, F32), workspace(op, BF16S)));
+    return 4 * f + sub + 256;
+}
+
+int run_phase(qdw_op* op, int prec, const void* eta, void* psi, const qdw_cgne_params& prm,
+              char* work, qdw_info* info, hipStream_t st)
+{
+    switch (prec) {
+    case F64: return cgne_impl<F64, F64>(op, eta, psi, prm, work, info, st);
+    case F32: return cgne_impl<F32, F32>(op, eta, psi, prm, work, info, st);
+    default: return cgne_impl<BF16S, F32>(op, eta, psi, prm, work, info, st);
+    }
+}
+
+// The precision cascade: defect correction with an inner CG whose storage precision rises
+// BF16 -> FP32 -> FP64 as the residual passes c eps of each type.
+int cascade_impl(qdw_op* op, const void* eta, void* psi, const qdw_cgne_params& prm, char* work,
+                 qdw_info* info, hipStream_t st)
+{
+    const Geom& g = op->g;
+    const int Vh = g.Vh;
+    const size_t f = spinor_bytes(g, F64);
+    void* rres = work;
+    void* dlt = work + f;
+    void* t1 = work + 2 * f;
+    void* t2 = work + 3 * f;
+    char* sub = work + 4 * f;
+    int rc;
+#define TRY(x) do { if ((rc = (x)) != QDW_OK) return rc; } while (0)
+    info->status = 0;
+    info->nreset = 0;
+    info->n_dw_hi = info->n_dw_lo = 0;
+    info->n_steps = 0;
+    info->rel_res_true = 0.0;
+    TRY(run_map(op, Zero<F64>{psi, Vh}, st));
+    TRY(run_map(op, Axpby<F64, F64>{eta, rres, 1.0, 0.0, Vh}, st));
+    double eta2;
+    TRY(run_map(op, Norm2<F64>{eta, Vh}, st, op->scalars + S_TMP));
+    TRY(read_scalars(op, S_TMP, 1, &eta2, st));
+    if (!(eta2 > 0.0)) {
+        info->status = std::isfinite(eta2) ? 0 : -3;
+        return QDW_OK;
+    }
+    const double neta = std::sqrt(eta2);
+    const double c = prm.cascade_c > 0.0 ? prm.cascade_c : 1.0;
+    const struct { int prec; double tau; } phases[3] = {
+        {BF16S, c * std::ldexp(1.0, -7)}, {F32, c * std::ldexp(1.0, -23)}, {F64, 0.0}};
+    double rel = 1.0;
+    int status = 0;
+    for (const auto& ph : phases) {
+        const double target = std::max(prm.res, ph.tau);
+        if (rel <= target) continue;
+        if (info->n_steps >= prm.nmx) {
+            status = -1;
+            break;
+        }
+        qdw_cgne_params sp = prm;
+        sp.cascade = 0;
+        sp.inner = (qdw_prec)ph.prec;
+        sp.res = target / rel;  // relative to the current residual, the phase's source
+        sp.nmx = prm.nmx - info->n_steps;
+        qdw_info si{};
+        TRY(run_phase(op, ph.prec, rres, dlt, sp, sub, &si, st));
+        info->n_steps += si.n_steps;
+        info->nreset += si.nreset;
+        info->n_dw_hi += si.n_dw_hi;
+        (ph.prec == F64 ? info->n_dw_hi : info->n_dw_lo) += si.n_dw_lo;
+        if (si.status == -3) {
+            status = -3;
+            break;
+        }
+        // psi += delta ; residual of the whole system in FP64
+        TRY(run_map(op, Axpby<F64, F64>{dlt, psi, 1.0, 1.0, Vh}, st));
+        TRY(dw_launch(op, psi, t1, F64, false, st));
+        TRY(dw_launch(op, t1, t2, F64, true, st));
+        info->n_dw_hi += 2;
+        double r2;
+        TRY(run_map(op, Residual{eta, t2, rres, Vh}, st, op->scalars + S_TMP));
+        TRY(read_scalars(op, S_TMP, 1, &r2, st));
+        rel = std::sqrt(r2) / neta;
+        ++info->nreset;  // the phase switch is a reset step too
+        if (!std::isfinite(rel)) {
+            status = -3;
+            break;
+        }
+        // a phase that stagnated (-2) or ran out of steps (-1) hands over to the next type
+    }
+#undef TRY
+    if (status == 0) status = rel <= prm.res ? info->n_steps : (info->n_steps >= prm.nmx ? -1 : -2);
+    info->status = status;
+    info->rel_res_true = rel;
+    return QDW_OK;
+}
+
 }  // namespace
 
 extern "C" size_t qdw_cgne_workspace_bytes(const qdw_op* op, const qdw_cgne_params* prm)
 {
-    if (!op || !prm || prm->inner < QDW_F64 || prm->inner > QDW_BF16S) return 0;
+    if (!op || !prm) return 0;
+    if (prm->cascade) return cascade_workspace(op);
+    if (prm->inner < QDW_F64 || prm->inner > QDW_BF16S) return 0;
     return workspace(op, prm->inner);
 }
 
@@ -265,16 +366,21 @@ extern "C" int cgne_solve(qdw_op* op, const void* eta, void* psi, const qdw_cgne
                           void* work, size_t work_bytes, qdw_info* info, void* stream)
 {
     QDW_CHECK(op && eta && psi && prm && work && info, QDW_EINVAL, "cgne_solve: null argument");
-    QDW_CHECK(prm->inner >= QDW_F64 && prm->inner <= QDW_BF16S, QDW_EINVAL,
+    QDW_CHECK(prm->cascade || (prm->inner >= QDW_F64 && prm->inner <= QDW_BF16S), QDW_EINVAL,
               "cgne_solve: bad inner precision");
     QDW_CHECK(prm->nmx >= 1 && prm->res > 0.0, QDW_EINVAL, "cgne_solve: need nmx >= 1, res > 0");
     QDW_CHECK(eta != psi, QDW_EINVAL, "cgne_solve: eta and psi must be distinct");
-    QDW_CHECK(work_bytes >= workspace(op, prm->inner), QDW_EWORKSPACE,
-              "cgne_solve: workspace smaller than qdw_cgne_workspace_bytes()");
+    QDW_CHECK(work_bytes >= (prm->cascade ? cascade_workspace(op) : workspace(op, prm->inner)),
+              QDW_EWORKSPACE, "cgne_solve: workspace smaller than qdw_cgne_workspace_bytes()");
     hipStream_t st = (hipStream_t)stream;
     char* wk = (char*)(((uintptr_t)work + 255) & ~(uintptr_t)255);
     const auto t0 = std::chrono::steady_clock::now();
     int rc;
+    if (prm->cascade) {
+        rc = cascade_impl(op, eta, psi, *prm, wk, info, st);
+        info->t_sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        return rc;
+    }
     switch (prm->inner) {
     case QDW_F64: rc = cgne_impl<F64, F64>(op, eta, psi, *prm, wk, info, st); break;
     case QDW_F32: rc = cgne_impl<F32, F32>(op, eta, psi, *prm, wk, info, st); break;

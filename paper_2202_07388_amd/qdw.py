@@ -81,7 +81,8 @@ class Info(ctypes.Structure):
 
 class CgneParams(ctypes.Structure):
     _fields_ = [("res", ctypes.c_double), ("nmx", ctypes.c_int), ("inner", ctypes.c_int),
-                ("delta", ctypes.c_double), ("keep_p", ctypes.c_int)]
+                ("delta", ctypes.c_double), ("keep_p", ctypes.c_int), ("cascade", ctypes.c_int),
+                ("cascade_c", ctypes.c_double)]
 
 
 class SapGcrParams(ctypes.Structure):
@@ -280,10 +281,13 @@ def _workspace(op: Op, nbytes: int):
 
 
 def cgne_solve(op: Op, eta, psi, res: float = 1e-10, nmx: int = 20000, inner: str = "f64",
-               delta: float = -1.0, keep_p: bool = True) -> dict:
-    """Solve D^+ D psi = eta (FP64 eo-SoA fields) with the normal-equation CG."""
+               delta: float = -1.0, keep_p: bool = True, cascade: bool = False,
+               cascade_c: float = 0.0) -> dict:
+    """Solve D^+ D psi = eta (FP64 eo-SoA fields) with the normal-equation CG; cascade=True
+    runs the BF16 -> FP32 -> FP64 precision cascade (inner is then ignored)."""
     L = load()
-    prm = CgneParams(res, nmx, PREC[inner], delta, 1 if keep_p else 0)
+    prm = CgneParams(res, nmx, PREC[inner], delta, 1 if keep_p else 0, 1 if cascade else 0,
+                     cascade_c)
     nb = int(L.qdw_cgne_workspace_bytes(op.handle, ctypes.byref(prm)))
     ws = _workspace(op, nb)
     info = Info()

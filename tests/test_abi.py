@@ -85,3 +85,11 @@ def test_adaptive_sap_rejects_bad_arguments_without_gpu(lib):
     rc = lib.sap_adaptive_apply(None, None, None, 20, 20, 0.9, 0.0, ctypes.byref(bs), 2, None, 0,
                                 None, None, None)
     assert rc == -1 and b"null" in lib.qdw_last_error()
+
+
+def test_cascade_workspace_without_gpu(lib):
+    import ctypes
+    prm = qdw.CgneParams(1e-10, 100, 99, -1.0, 1, 1, 1.0)  # inner ignored by the cascade
+    assert lib.qdw_cgne_workspace_bytes(None, ctypes.byref(prm)) == 0
+    prm.cascade = 0
+    assert lib.qdw_cgne_workspace_bytes(None, ctypes.byref(prm)) == 0

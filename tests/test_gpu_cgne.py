@@ -113,3 +113,42 @@ def test_zero_source(small):
     dims, gop, oop, eta = small
     x, info = _solve(gop, np.zeros_like(eta), res=1e-10)
     assert info["status"] == 0 and np.abs(x).max() == 0
+
+
+# ---------------------------------------------------------------- precision cascade
+
+@pytest.mark.parametrize("c", [1.0, 10.0])
+def test_cascade_reaches_fp64_residual(mid, c):
+    """BF16 -> FP32 -> FP64 (Sec. 2.1): the FP64 true residual 1e-10 is reached, the
+    solution agrees with the oracle's, and the FP64 phase takes only the last few digits:
+    far fewer FP64 operator applications than plain FP64 CG."""
+    dims, gop, oop, eta, xo = mid
+    x, info = _solve(gop, eta, res=1e-10, cascade=True, cascade_c=c)
+    assert info["status"] > 0 and info["rel_res_true"] <= 1e-10, info
+    r = eta - oop.normal(x)
+    assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(eta)
+    assert rel(x, xo) <= 1e-7
+    _, plain = _solve(gop, eta, res=1e-10, inner="f64")
+    # all of plain FP64 CG's applications are FP64 (its regular steps count as n_dw_lo)
+    assert info["n_dw_lo"] > 0 and info["n_dw_hi"] < 0.5 * (plain["n_dw_hi"] + plain["n_dw_lo"])
+
+
+def test_cascade_phases_follow_the_thresholds(mid):
+    """A target above the BF16 switch point is met by the BF16 phase alone (no FP64
+    operator applications beyond the residual checks); one between the switch points
+    needs BF16 and FP32 only."""
+    dims, gop, oop, eta, xo = mid
+    _, a = _solve(gop, eta, res=2e-2, cascade=True, cascade_c=1.0)
+    assert a["status"] > 0 and a["rel_res_true"] <= 2e-2
+    # FP64 applications: 2 per reset of the BF16 phase, 2 for its final check and 2 for
+    # the cascade's residual after the phase (counted as one more reset)
+    assert a["n_dw_hi"] == 2 * a["nreset"] + 2
+    _, b = _solve(gop, eta, res=1e-5, cascade=True, cascade_c=1.0)
+    assert b["status"] > 0 and b["rel_res_true"] <= 1e-5
+    assert b["n_steps"] > a["n_steps"]
+
+
+def test_cascade_zero_source(mid):
+    dims, gop, oop, eta, xo = mid
+    x, info = _solve(gop, np.zeros_like(eta), res=1e-10, cascade=True)
+    assert info["status"] == 0 and np.abs(x).max() == 0.0
