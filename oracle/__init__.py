@@ -15,6 +15,8 @@ Contents, each written from its definition (stencil loops live in ``oracle.c``):
 * ``sap`` / ``mr_blocks``: Schwarz alternating procedure (Sec. 3, Fig. 2 and 3): chessboard
   blocks, grey then white, ``nmr`` minimal-residual steps per block, ``ncy`` cycles;
 * ``sap_adaptive``: the adaptive variant of Sec. 3.2;
+* ``Schur`` / ``cgne_schur``: the even-odd reduced operator A_ee - D_eo A_oo^-1 D_oe and
+  CG on its normal equations;
 * ``nn_*``: a gauge-covariant linear network of parallel-transport layers, forward and
   analytic adjoint (not from the paper).
 
@@ -227,6 +229,101 @@ def cgne(op: Operator, eta, res: float, nmx: int, history: bool = False):
         p = r + beta * p
         rr = rr_new
     return (x, status, hist) if history else (x, status)
+
+
+# --------------------------------------------------------------------------- even-odd
+
+def site_parity(dims) -> np.ndarray:
+    """(x0 + x1 + x2 + x3) mod 2 per lexicographic site."""
+    return np.indices(tuple(dims)).reshape(4, -1).sum(axis=0) % 2
+
+
+class Schur:
+    """The even-odd reduced operator D^ = A_ee - D_eo A_oo^-1 D_oe on even-site fields
+    (the matrix of the paper's Sec. 3 is even-odd ordered, Fig. 3 left; its even-even
+    Schur complement), written from the blocks of D itself:
+
+    * (D (psi_e, 0))_even = A_ee psi_e and (D (psi_e, 0))_odd = D_oe psi_e, since no hop
+      joins two sites of one parity;
+    * (D (0, t))_even = D_eo t;
+    * A_oo^-1 is the inverse of each odd site's 12 x 12 clover matrix.
+
+    Fields are full-size [V, 4, 3] arrays; odd components of the input are ignored and
+    those of the output are zero. D^+ is built the same way from D^+ (A is Hermitian).
+    """
+
+    def __init__(self, op: Operator):
+        self.op = op
+        par = site_parity(op.dims)
+        self.even = (par == 0)[:, None, None]
+        self.odd = (par == 1)[:, None, None]
+        self.Ainv = np.linalg.inv(op.A)
+
+    def _ainv(self, y):
+        return np.einsum("sab,sb->sa", self.Ainv, y.reshape(-1, 12)).reshape(y.shape)
+
+    def _apply(self, fwd, psi):
+        psi = np.asarray(psi, dtype=np.complex128).reshape(self.op.V, 4, 3)
+        y = fwd(np.where(self.even, psi, 0))
+        t = np.where(self.odd, self._ainv(np.where(self.odd, y, 0)), 0)
+        z = fwd(t)
+        return np.where(self.even, y - z, 0)
+
+    def apply(self, psi):
+        return self._apply(self.op.dw, psi)
+
+    def apply_dag(self, psi):
+        return self._apply(self.op.dw_dag, psi)
+
+    def normal(self, psi):
+        return self.apply_dag(self.apply(psi))
+
+    def solve_full(self, eta, x_even):
+        """Given the even part x_e of the solution of D x = eta, the odd part follows
+        from the odd rows: x_o = A_oo^-1 (eta_o - D_oe x_e)."""
+        eta = np.asarray(eta, dtype=np.complex128).reshape(self.op.V, 4, 3)
+        xe = np.where(self.even, np.asarray(x_even).reshape(self.op.V, 4, 3), 0)
+        y = self.op.dw(xe)
+        xo = np.where(self.odd, self._ainv(np.where(self.odd, eta - y, 0)), 0)
+        return xe + xo
+
+    def source(self, eta):
+        """eta^_e = eta_e - D_eo A_oo^-1 eta_o: D^ x_e = eta^_e for the even part of the
+        solution of D x = eta."""
+        eta = np.asarray(eta, dtype=np.complex128).reshape(self.op.V, 4, 3)
+        t = np.where(self.odd, self._ainv(np.where(self.odd, eta, 0)), 0)
+        return np.where(self.even, eta - self.op.dw(t), 0)
+
+
+def cgne_schur(sc: Schur, eta, res: float, nmx: int):
+    """Textbook CG on D^+ D^ over even-site fields from x = 0, stopping when the true
+    residual |eta_e - D^+ D^ x| <= res |eta_e| (checked when the recursive one is)."""
+    eta = np.where(sc.even, np.asarray(eta, dtype=np.complex128).reshape(sc.op.V, 4, 3), 0)
+    neta = _norm(eta)
+    x = np.zeros_like(eta)
+    r = eta.copy()
+    p = r.copy()
+    rr = _norm(r) ** 2
+    status = 0
+    while True:
+        q = sc.apply(p)
+        alpha = rr / _norm(q) ** 2
+        x = x + alpha * p
+        r = r - alpha * sc.apply_dag(q)
+        rr_new = _norm(r) ** 2
+        status += 1
+        if np.sqrt(rr_new) <= res * neta:
+            rt = eta - sc.normal(x)
+            if _norm(rt) <= res * neta:
+                break
+            r = rt
+            rr_new = _norm(r) ** 2
+        if status >= nmx:
+            status = -1
+            break
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+    return x, status
 
 
 # --------------------------------------------------------------------------- FGCR

@@ -482,3 +482,95 @@ def test_nn_gradients_finite_differences(opn):
         rm[j] -= h
         fd = (oracle.nn_loss(opn, W, rp, e)[0] - oracle.nn_loss(opn, W, rm, e)[0]) / (2 * h)
         assert abs(fd - 2 * gin[j].real) <= 1e-6 * max(1.0, abs(fd))
+
+
+# ---------------------------------------------------------------- even-odd reduction
+
+def _eo_index(dims):
+    par = np.repeat(oracle.site_parity(dims), 12)
+    return np.flatnonzero(par == 0), np.flatnonzero(par == 1)
+
+
+def test_schur_equals_dense_schur_complement(op44, dense44):
+    """Column by column, the oracle's D^ equals D_EE - D_EO D_OO^-1 D_OE formed from the
+    brute-force dense matrix."""
+    E, O = _eo_index(D44)
+    S = dense44[np.ix_(E, E)] - dense44[np.ix_(E, O)] @ np.linalg.solve(
+        dense44[np.ix_(O, O)], dense44[np.ix_(O, E)])
+    sc = oracle.Schur(op44)
+    e = np.zeros(op44.V * 12, dtype=np.complex128)
+    rng = np.random.default_rng(5)
+    for j in rng.choice(len(E), 48, replace=False):
+        e[E[j]] = 1.0
+        col = sc.apply(e).reshape(-1)
+        e[E[j]] = 0.0
+        assert np.abs(col[E] - S[:, j]).max() < 1e-13
+        assert np.abs(col[O]).max() == 0.0
+    # a random even field at once
+    v = rng.standard_normal(len(E)) + 1j * rng.standard_normal(len(E))
+    f = np.zeros(op44.V * 12, dtype=np.complex128)
+    f[E] = v
+    assert np.abs(sc.apply(f).reshape(-1)[E] - S @ v).max() < 1e-12
+
+
+def test_schur_determinant_identity():
+    """det D = det D_OO det D^ (block LU); a swapped or mis-signed coupling breaks it."""
+    dims = (4, 2, 2, 2)
+    op = _op(dims, m0=-0.1, csw=1.7, eps=0.4, seed=21)
+    M = oracle.dense_matrix(op)
+    E, O = _eo_index(dims)
+    sc = oracle.Schur(op)
+    n = len(E)
+    S = np.zeros((n, n), dtype=np.complex128)
+    e = np.zeros(op.V * 12, dtype=np.complex128)
+    for j in range(n):
+        e[E[j]] = 1.0
+        S[:, j] = sc.apply(e).reshape(-1)[E]
+        e[E[j]] = 0.0
+    s_full, l_full = np.linalg.slogdet(M)
+    s_oo, l_oo = np.linalg.slogdet(M[np.ix_(O, O)])
+    s_s, l_s = np.linalg.slogdet(S)
+    assert abs(l_full - (l_oo + l_s)) < 1e-10
+    assert abs(s_full - s_oo * s_s) < 1e-10
+
+
+def test_schur_reconstructs_the_full_solution(op44, dense44):
+    """For x = D^-1 eta: D^ x_e = eta^_e, and the odd rows give back x_o."""
+    eta = syn.gaussian_spinor(D44, 77)
+    x = np.linalg.solve(dense44, eta.reshape(-1)).reshape(eta.shape)
+    sc = oracle.Schur(op44)
+    lhs = sc.apply(x)
+    rhs = sc.source(eta)
+    assert np.abs(lhs - rhs).max() < 1e-12 * np.abs(rhs).max()
+    back = sc.solve_full(eta, x)
+    assert np.abs(back - x).max() < 1e-12 * np.abs(x).max()
+
+
+def test_schur_gamma5_hermitian(op44):
+    sc = oracle.Schur(op44)
+    g5 = np.diag([1.0, 1.0, -1.0, -1.0])
+    v = syn.gaussian_spinor(D44, 78)
+    lhs = spin(g5, sc.apply(spin(g5, v)))
+    assert np.abs(lhs - sc.apply_dag(v)).max() < 1e-13
+    w = syn.gaussian_spinor(D44, 79)
+    ev = np.where(sc.even, w, 0)
+    assert abs(np.vdot(ev, sc.apply(v)) - np.vdot(sc.apply_dag(ev), v)) < 1e-11
+
+
+def test_cgne_schur_solves_the_reduced_normal_equations(op44, dense44):
+    E, _ = _eo_index(D44)
+    sc = oracle.Schur(op44)
+    eta = syn.gaussian_spinor(D44, 80)
+    x, st = oracle.cgne_schur(sc, eta, 1e-10, 2000)
+    assert st > 0
+    r = np.where(sc.even, eta, 0) - sc.normal(x)
+    assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(np.where(sc.even, eta, 0))
+    # against the dense normal equations of the dense Schur complement
+    O = np.setdiff1d(np.arange(op44.V * 12), E)
+    S = dense44[np.ix_(E, E)] - dense44[np.ix_(E, O)] @ np.linalg.solve(
+        dense44[np.ix_(O, O)], dense44[np.ix_(O, E)])
+    xd = np.linalg.solve(S.conj().T @ S, eta.reshape(-1)[E])
+    assert np.linalg.norm(x.reshape(-1)[E] - xd) <= 1e-7 * np.linalg.norm(xd)
+    # the reduced system needs fewer CG steps than the full normal equations
+    _, st_full = oracle.cgne(op44, eta, 1e-10, 2000)
+    assert st < st_full, (st, st_full)
