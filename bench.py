@@ -10,7 +10,8 @@ Also reported, each timed on its own outside the K steps:
   * D in FP32 and FP16 storage, D^+ in FP64;
   * the 32^3 x 64 normal-equation solve to FP64 true residual 1e-10: plain FP64 CG
     against FP32, FP16 and BF16 regular steps with FP64 reset steps, and the BF16 -> FP32
-    -> FP64 precision cascade;
+    -> FP64 precision cascade; and the even-odd reduced normal equations D^+ D^ psi_e =
+    eta_e (FP64 and FP32 inner), which the solver of the full equations is compared with;
   * the 24^3 x 48 solve of D psi = eta to 1e-10 (eps = 0.35, m0 = -0.08): plain FP64 GCR
     against SAP-preconditioned GCR (4^4 blocks, 5 cycles, 4 MR steps, FP16 and FP32) and
     adaptive SAP (at most 20 cycles and 20 MR steps, alpha 0.9 and 0.7, FP16);
@@ -131,7 +132,9 @@ def cgne_solves(op, qdw, psi):
     out = {}
     for name, kw in (("f64", dict(inner="f64")), ("f32", dict(inner="f32")),
                      ("f16", dict(inner="f16")), ("bf16", dict(inner="bf16")),
-                     ("cascade_bf16_f32_f64", dict(cascade=True))):
+                     ("cascade_bf16_f32_f64", dict(cascade=True)),
+                     ("schur_f64", dict(inner="f64", schur=True)),
+                     ("schur_f32", dict(inner="f32", schur=True))):
         x = op.new_field("f64")
         info = qdw.cgne_solve(op, eta, x, res=1e-10, nmx=20000, **kw)
         out[name] = solve_record(info)

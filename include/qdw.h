@@ -102,6 +102,15 @@ int qdw_unpack(const qdw_op* op, const void* eo, double* canonical, qdw_prec pre
 int dw_apply(qdw_op* op, const void* in, void* out, qdw_prec prec, void* stream);
 int dw_dag_apply(qdw_op* op, const void* in, void* out, qdw_prec prec, void* stream);
 
+/* Even-odd reduced operator (the matrix of Sec. 3 is stored even sites first, Fig. 3
+ * left; its Schur complement on the even sites): out_e = D^ in_e with
+ * D^ = A_ee - D_eo A_oo^-1 D_oe, and D^+ = gamma_5 D^ gamma_5. Only the even half of `in`
+ * is read; the even half of `out` receives the result and its odd half is overwritten
+ * with A_oo^-1 D_oe in_e (scratch). The inverses of the odd-site clover blocks are formed
+ * at qdw_create in FP64 (Gauss-Jordan with pivoting) and stored in every precision. */
+int dw_schur_apply(qdw_op* op, const void* in, void* out, qdw_prec prec, void* stream);
+int dw_schur_dag_apply(qdw_op* op, const void* in, void* out, qdw_prec prec, void* stream);
+
 /* out[r] = D in[r] for r < nrhs (1 <= nrhs <= 64) in one launch: several right-hand sides
  * on one gauge field (Sec. 2 and 3 solve one system per source; the batch shares the
  * operator). in, out: host arrays of device eo-SoA fields of precision prec; no output may
@@ -188,6 +197,12 @@ typedef struct {
                         n_dw_hi then counts every FP64 application, n_dw_lo the BF16 and
                         FP32 ones; nreset counts resets and phase switches. 0: off           */
     double cascade_c;  /* the constant of the phase switch (default 1 when <= 0)           */
+    int schur;       /* 1: solve the even-odd reduced normal equations D^+ D^ psi_e = eta_e
+                        (D^ = A_ee - D_eo A_oo^-1 D_oe, see dw_schur_apply) instead of
+                        D^+ D psi = eta: only the even halves of eta and psi are used, the
+                        odd half of psi is set to zero, and rel_res_true refers to the
+                        reduced system. Works with every inner precision and the cascade.
+                        0: the full operator                                                */
 } qdw_cgne_params;
 
 /* Device workspace (bytes) cgne_solve needs for these settings. 0 on bad arguments. */

@@ -186,12 +186,13 @@ inline int map_blocks(long nunits)
     return (int)b;
 }
 
-// launch F over all 3V units of op's lattice and (if F::NS > 0) finalise into scalars
+// launch F over all 3V units of op's lattice, or over the first nu units when nu > 0
+// (3 Vh: the even half), and (if F::NS > 0) finalise into scalars
 template <class F>
 int run_map(const qdw_op* op, const F& f, hipStream_t st, double* out = nullptr,
-            int fin = FIN_STORE, int k = 0)
+            int fin = FIN_STORE, int k = 0, long nu = 0)
 {
-    const long nunits = 3L * op->g.V;
+    const long nunits = nu > 0 ? nu : 3L * op->g.V;
     const int nb = map_blocks(nunits);
     map_kernel<F><<<nb, 256, 0, st>>>(nunits, op->g.Vh, f, op->partials);
     QDW_LAUNCH_CHECK();
@@ -381,6 +382,8 @@ struct Zero {
 // ---------------------------------------------------------------- host helpers
 
 int dw_launch(qdw_op* op, const void* in, void* out, int prec, bool dag, hipStream_t st);
+// the even-odd reduced operator on the even half of in (odd half of out: scratch)
+int schur_launch(qdw_op* op, const void* in, void* out, int prec, bool dag, hipStream_t st);
 
 // read `n` device doubles at `src` (synchronises the stream)
 inline int read_device(const qdw_op* op, const double* src, int n, double* out, hipStream_t st)

@@ -88,13 +88,19 @@ int cgne_impl(qdw_op* op, const void* eta, void* psi, const qdw_cgne_params& prm
     double delta = prm.delta >= 0 ? prm.delta : prm.keep_p ? 0.1 : 10.0 * eps_inner;
     if (PL == F64 && prm.delta < 0) delta = 0.0;  // FP64: check only at convergence
 
+    // the even-odd reduced system lives on the even half of every field
+    const bool schur = prm.schur != 0;
+    const long nu = schur ? 3L * Vh : 0;
+    auto apply = [&](const void* in, void* out, int prec, bool dag) {
+        return schur ? schur_launch(op, in, out, prec, dag, st) : dw_launch(op, in, out, prec, dag, st);
+    };
     CgState S;
     int rc;
 #define TRY(x) do { if ((rc = (x)) != QDW_OK) return rc; } while (0)
     TRY(run_map(op, Zero<F64>{psi, Vh}, st));
-    if (PL != F64) TRY(run_map(op, Zero<PX>{xlo, Vh}, st));
+    if (PL != F64) TRY(run_map(op, Zero<PX>{xlo, Vh}, st, nullptr, FIN_STORE, 0, nu));
     double eta2;
-    TRY(run_map(op, Norm2<F64>{eta, Vh}, st, op->scalars + S_TMP, FIN_STORE));
+    TRY(run_map(op, Norm2<F64>{eta, Vh}, st, op->scalars + S_TMP, FIN_STORE, 0, nu));
     TRY(read_scalars(op, S_TMP, 1, &eta2, st));
     info->status = 0;
     info->nreset = 0;
@@ -106,8 +112,8 @@ int cgne_impl(qdw_op* op, const void* eta, void* psi, const qdw_cgne_params& prm
     }
     const double neta = std::sqrt(eta2);
     double s = PL == F64 ? 1.0 : sqrt24v / neta;
-    TRY(run_map(op, ScaleNorm<F64, PL>{eta, r, s, Vh}, st, op->scalars + S_RR, FIN_STORE));
-    TRY(run_map(op, Axpby<PL, PL>{r, p, 1.0, 0.0, Vh}, st));
+    TRY(run_map(op, ScaleNorm<F64, PL>{eta, r, s, Vh}, st, op->scalars + S_RR, FIN_STORE, 0, nu));
+    TRY(run_map(op, Axpby<PL, PL>{r, p, 1.0, 0.0, Vh}, st, nullptr, FIN_STORE, 0, nu));
     double rr_reset;
     TRY(read_scalars(op, S_RR, 1, &rr_reset, st));
     double best = rr_reset, prev_true = 1.0;
@@ -121,12 +127,12 @@ int cgne_impl(qdw_op* op, const void* eta, void* psi, const qdw_cgne_params& prm
 
     auto iterate = [&]() -> int {
         int e;
-        if ((e = dw_launch(op, p, q, PL, false, st))) return e;
-        if ((e = dw_launch(op, q, w, PL, true, st))) return e;
+        if ((e = apply(p, q, PL, false))) return e;
+        if ((e = apply(q, w, PL, true))) return e;
         S.ndw_lo += 2;
-        if ((e = run_map(op, Norm2<PL>{q, Vh}, st, op->scalars, FIN_CG_ALPHA))) return e;
-        if ((e = run_map(op, CgStep<PX, PL>{xlo, p, r, w, sc, Vh}, st, op->scalars, FIN_CG_BETA))) return e;
-        if ((e = run_map(op, CgDirection<PL>{r, p, sc, Vh}, st))) return e;
+        if ((e = run_map(op, Norm2<PL>{q, Vh}, st, op->scalars, FIN_CG_ALPHA, 0, nu))) return e;
+        if ((e = run_map(op, CgStep<PX, PL>{xlo, p, r, w, sc, Vh}, st, op->scalars, FIN_CG_BETA, 0, nu))) return e;
+        if ((e = run_map(op, CgDirection<PL>{r, p, sc, Vh}, st, nullptr, FIN_STORE, 0, nu))) return e;
         ++S.steps;
         const int k = S.steps & 1;
         QDW_HIP(hipMemcpyAsync(slot + k, sc + S_RR, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -138,11 +144,11 @@ int cgne_impl(qdw_op* op, const void* eta, void* psi, const qdw_cgne_params& prm
     auto true_residual = [&](double* rel) -> int {
         int e;
         if (PL != F64)
-            if ((e = run_map(op, Accumulate<PX>{psi, xlo, 1.0 / s, Vh}, st))) return e;
-        if ((e = dw_launch(op, psi, t1, F64, false, st))) return e;
-        if ((e = dw_launch(op, t1, t2, F64, true, st))) return e;
+            if ((e = run_map(op, Accumulate<PX>{psi, xlo, 1.0 / s, Vh}, st, nullptr, FIN_STORE, 0, nu))) return e;
+        if ((e = apply(psi, t1, F64, false))) return e;
+        if ((e = apply(t1, t2, F64, true))) return e;
         S.ndw_hi += 2;
-        if ((e = run_map(op, Residual{eta, t2, rhi, Vh}, st, op->scalars + S_TMP, FIN_STORE))) return e;
+        if ((e = run_map(op, Residual{eta, t2, rhi, Vh}, st, op->scalars + S_TMP, FIN_STORE, 0, nu))) return e;
         double rt2;
         if ((e = read_scalars(op, S_TMP, 1, &rt2, st))) return e;
         *rel = std::sqrt(rt2) / neta;
@@ -154,7 +160,7 @@ int cgne_impl(qdw_op* op, const void* eta, void* psi, const qdw_cgne_params& prm
         int e;
         const double snew = PL == F64 ? 1.0 : sqrt24v / (rel * neta);
         // r = snew r_hi, with |r|^2 into S_RR and the drift |r_hi - r_old/s|^2 next to it
-        if ((e = run_map(op, ResetResidual<PL>{rhi, r, s, snew, Vh}, st, op->scalars + S_RR))) return e;
+        if ((e = run_map(op, ResetResidual<PL>{rhi, r, s, snew, Vh}, st, op->scalars + S_RR, FIN_STORE, 0, nu))) return e;
         double d2[2];
         if ((e = read_scalars(op, S_RR, 2, d2, st))) return e;
         // keep the direction only while the recursive residual had not drifted far from
@@ -162,9 +168,9 @@ int cgne_impl(qdw_op* op, const void* eta, void* psi, const qdw_cgne_params& prm
         const bool keep = prm.keep_p && std::sqrt(d2[1]) <= 0.3 * rel * neta;
         S.kept += keep;
         if (keep) {
-            if ((e = run_map(op, Axpby<PL, PL>{p, p, snew / s, 0.0, Vh}, st))) return e;
+            if ((e = run_map(op, Axpby<PL, PL>{p, p, snew / s, 0.0, Vh}, st, nullptr, FIN_STORE, 0, nu))) return e;
         } else {
-            if ((e = run_map(op, Axpby<PL, PL>{r, p, 1.0, 0.0, Vh}, st))) return e;
+            if ((e = run_map(op, Axpby<PL, PL>{r, p, 1.0, 0.0, Vh}, st, nullptr, FIN_STORE, 0, nu))) return e;
         }
         s = snew;
         rr_reset = d2[0];
@@ -285,6 +291,11 @@ int cascade_impl(qdw_op* op, const void* eta, void* psi, const qdw_cgne_params& 
     void* t1 = work + 2 * f;
     void* t2 = work + 3 * f;
     char* sub = work + 4 * f;
+    const bool schur = prm.schur != 0;
+    const long nu = schur ? 3L * Vh : 0;
+    auto apply = [&](const void* in, void* out, int prec, bool dag) {
+        return schur ? schur_launch(op, in, out, prec, dag, st) : dw_launch(op, in, out, prec, dag, st);
+    };
     int rc;
 #define TRY(x) do { if ((rc = (x)) != QDW_OK) return rc; } while (0)
     info->status = 0;
@@ -293,9 +304,9 @@ int cascade_impl(qdw_op* op, const void* eta, void* psi, const qdw_cgne_params& 
     info->n_steps = 0;
     info->rel_res_true = 0.0;
     TRY(run_map(op, Zero<F64>{psi, Vh}, st));
-    TRY(run_map(op, Axpby<F64, F64>{eta, rres, 1.0, 0.0, Vh}, st));
+    TRY(run_map(op, Axpby<F64, F64>{eta, rres, 1.0, 0.0, Vh}, st, nullptr, FIN_STORE, 0, nu));
     double eta2;
-    TRY(run_map(op, Norm2<F64>{eta, Vh}, st, op->scalars + S_TMP));
+    TRY(run_map(op, Norm2<F64>{eta, Vh}, st, op->scalars + S_TMP, FIN_STORE, 0, nu));
     TRY(read_scalars(op, S_TMP, 1, &eta2, st));
     if (!(eta2 > 0.0)) {
         info->status = std::isfinite(eta2) ? 0 : -3;
@@ -330,12 +341,12 @@ int cascade_impl(qdw_op* op, const void* eta, void* psi, const qdw_cgne_params& 
             break;
         }
         // psi += delta ; residual of the whole system in FP64
-        TRY(run_map(op, Axpby<F64, F64>{dlt, psi, 1.0, 1.0, Vh}, st));
-        TRY(dw_launch(op, psi, t1, F64, false, st));
-        TRY(dw_launch(op, t1, t2, F64, true, st));
+        TRY(run_map(op, Axpby<F64, F64>{dlt, psi, 1.0, 1.0, Vh}, st, nullptr, FIN_STORE, 0, nu));
+        TRY(apply(psi, t1, F64, false));
+        TRY(apply(t1, t2, F64, true));
         info->n_dw_hi += 2;
         double r2;
-        TRY(run_map(op, Residual{eta, t2, rres, Vh}, st, op->scalars + S_TMP));
+        TRY(run_map(op, Residual{eta, t2, rres, Vh}, st, op->scalars + S_TMP, FIN_STORE, 0, nu));
         TRY(read_scalars(op, S_TMP, 1, &r2, st));
         rel = std::sqrt(r2) / neta;
         ++info->nreset;  // the phase switch is a reset step too

@@ -308,6 +308,64 @@ __global__ __launch_bounds__(256) void dw_march_kernel(Geom g, RhsTable tab, int
     }
 }
 
+// Even-odd reduced operator D^ = A_ee - D_eo A_oo^-1 D_oe on the even half of a field, in
+// two passes over one parity each (one lane per site):
+//   stage 1, odd sites:  t = A_oo^-1 (D_oe psi_e) = A_oo^-1 (-1/2 sum of the hops of psi_e)
+//   stage 2, even sites: out = A_ee psi_e - D_eo t = A_ee psi_e + 1/2 sum of the hops of t
+// t lives in the odd half of the output field. D^+ = gamma_5 D^ gamma_5 flips the
+// projector signs as for D (A and A^-1 commute with gamma_5).
+template <int P, bool DAG, int STAGE>
+__global__ __launch_bounds__(256) void schur_kernel(Geom g, const void* hsrc, const void* dsrc,
+                                                    void* out, const void* __restrict__ links,
+                                                    const void* __restrict__ dets,
+                                                    const void* __restrict__ diag)
+{
+    using R = typename Traits<P>::real;
+    constexpr int par = STAGE == 1 ? 1 : 0;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.Vh) return;
+    int x[4], lex;
+    eo_coords(g, par, i, x, lex);
+    cx<R> hop[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) hop[c] = {(R)0, (R)0};
+    HopIn<P> A;
+#pragma unroll 1
+    for (int k = 0; k < 8; ++k) {
+        int ii = i, ll = lex, xx[4] = {x[0], x[1], x[2], x[3]};
+        asm volatile("" : "+v"(ii), "+v"(ll), "+v"(xx[0]), "+v"(xx[1]), "+v"(xx[2]), "+v"(xx[3]));
+        load_k<P>(k, g, hsrc, links, dets, par, ii, xx, ll, A);
+        compute_k<P, DAG>(k, g, xx, A, hop);
+    }
+    cx<R> acc[12];
+    if constexpr (STAGE == 1) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) hop[c] = scale(hop[c], (R)-0.5);
+        clover_apply<P>(diag, g.Vh, par, i, hop, acc);
+    } else {
+        cx<R> sp[12];
+        load_spinor<P>(dsrc, g.Vh, par, i, sp);
+        clover_apply<P>(diag, g.Vh, par, i, sp, acc);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) acc[c] = acc[c] + scale(hop[c], (R)0.5);
+    }
+    store_spinor<P>(out, g.Vh, par, i, acc);
+}
+
+template <int P, bool DAG>
+int schur_launch_t(qdw_op* op, const void* in, void* out, hipStream_t st)
+{
+    const Geom& g = op->g;
+    const int nb = (g.Vh + 255) / 256;
+    schur_kernel<P, DAG, 1><<<nb, 256, 0, st>>>(g, in, nullptr, out, op->links[P], op->det[P],
+                                                op->cloverinv[P]);
+    QDW_LAUNCH_CHECK();
+    schur_kernel<P, DAG, 2><<<nb, 256, 0, st>>>(g, out, in, out, op->links[P], op->det[P],
+                                                op->clover[P]);
+    QDW_LAUNCH_CHECK();
+    return QDW_OK;
+}
+
 // the operator's geometry with the D kernel's own shape for precision P
 inline Geom shaped(const qdw_op* op, int P)
 {
@@ -374,6 +432,17 @@ int dw_launch(qdw_op* op, const void* in, void* out, int prec, bool dag, hipStre
     return dispatch(op, tab, 1, prec, dag, st);
 }
 
+int schur_launch(qdw_op* op, const void* in, void* out, int prec, bool dag, hipStream_t st)
+{
+    switch (prec) {
+    case F64: return dag ? schur_launch_t<F64, true>(op, in, out, st) : schur_launch_t<F64, false>(op, in, out, st);
+    case F32: return dag ? schur_launch_t<F32, true>(op, in, out, st) : schur_launch_t<F32, false>(op, in, out, st);
+    case F16S: return dag ? schur_launch_t<F16S, true>(op, in, out, st) : schur_launch_t<F16S, false>(op, in, out, st);
+    case BF16S: return dag ? schur_launch_t<BF16S, true>(op, in, out, st) : schur_launch_t<BF16S, false>(op, in, out, st);
+    default: QDW_CHECK(false, QDW_EINVAL, "schur: bad precision");
+    }
+}
+
 int dw_launch_multi(qdw_op* op, const void* const* in, void* const* out, int nrhs, int prec,
                     bool dag, const int* gate, int gstride, hipStream_t st)
 {
@@ -396,6 +465,21 @@ extern "C" int dw_apply(qdw_op* op, const void* in, void* out, qdw_prec prec, vo
 extern "C" int dw_dag_apply(qdw_op* op, const void* in, void* out, qdw_prec prec, void* stream)
 {
     return apply_checked(op, in, out, prec, true, stream);
+}
+
+extern "C" int dw_schur_apply(qdw_op* op, const void* in, void* out, qdw_prec prec, void* stream)
+{
+    QDW_CHECK(op && in && out, QDW_EINVAL, "dw_schur_apply: null argument");
+    QDW_CHECK(in != out, QDW_EINVAL, "dw_schur_apply: in and out must be distinct fields");
+    return qdw::schur_launch(op, in, out, prec, false, (hipStream_t)stream);
+}
+
+extern "C" int dw_schur_dag_apply(qdw_op* op, const void* in, void* out, qdw_prec prec,
+                                  void* stream)
+{
+    QDW_CHECK(op && in && out, QDW_EINVAL, "dw_schur_dag_apply: null argument");
+    QDW_CHECK(in != out, QDW_EINVAL, "dw_schur_dag_apply: in and out must be distinct fields");
+    return qdw::schur_launch(op, in, out, prec, true, (hipStream_t)stream);
 }
 
 extern "C" int dw_apply_multi(qdw_op* op, const void* const* in, void* const* out, int nrhs,

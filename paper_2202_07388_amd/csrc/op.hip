@@ -278,6 +278,83 @@ __global__ void clover_kernel(Geom g, const double* su3, const double* theta, do
         out[chunk_at(g.Vh, 36, par, k, i)] = double2{reals[2 * k], reals[2 * k + 1]};
 }
 
+// The inverse of each 6x6 Hermitian chirality block of the clover term (for the even-odd
+// reduced operator): Gauss-Jordan elimination with partial pivoting in FP64, stored in the
+// clover term's packed Hermitian format (6 diagonal reals, then the upper triangle row by
+// row). A singular block leaves non-finite entries, which a solve reports as status -3.
+__global__ void clover_inv_kernel(Geom g, const double2* clov, double2* inv)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int par = blockIdx.y;
+    if (i >= g.Vh) return;
+    double in[72], outr[72];
+    for (int k = 0; k < 36; ++k) {
+        const double2 v = clov[chunk_at(g.Vh, 36, par, k, i)];
+        in[2 * k] = v.x;
+        in[2 * k + 1] = v.y;
+    }
+    for (int blk = 0; blk < 2; ++blk) {
+        const double* a = in + 36 * blk;
+        cx<double> m[6][6], r[6][6];
+        int n = 0;
+        for (int u = 0; u < 6; ++u) {
+            m[u][u] = {a[u], 0.0};
+            for (int v = u + 1; v < 6; ++v) {
+                m[u][v] = {a[6 + 2 * n], a[6 + 2 * n + 1]};
+                m[v][u] = {a[6 + 2 * n], -a[6 + 2 * n + 1]};
+                ++n;
+            }
+        }
+        for (int u = 0; u < 6; ++u)
+            for (int v = 0; v < 6; ++v) r[u][v] = {u == v ? 1.0 : 0.0, 0.0};
+        for (int c = 0; c < 6; ++c) {
+            int pv = c;
+            double best = m[c][c].re * m[c][c].re + m[c][c].im * m[c][c].im;
+            for (int u = c + 1; u < 6; ++u) {
+                const double mag = m[u][c].re * m[u][c].re + m[u][c].im * m[u][c].im;
+                if (mag > best) {
+                    best = mag;
+                    pv = u;
+                }
+            }
+            if (pv != c)
+                for (int v = 0; v < 6; ++v) {
+                    const cx<double> t = m[c][v];
+                    m[c][v] = m[pv][v];
+                    m[pv][v] = t;
+                    const cx<double> w = r[c][v];
+                    r[c][v] = r[pv][v];
+                    r[pv][v] = w;
+                }
+            const double n2 = m[c][c].re * m[c][c].re + m[c][c].im * m[c][c].im;
+            const cx<double> piv = {m[c][c].re / n2, -m[c][c].im / n2};  // 1 / m_cc
+            for (int v = 0; v < 6; ++v) {
+                m[c][v] = m[c][v] * piv;
+                r[c][v] = r[c][v] * piv;
+            }
+            for (int u = 0; u < 6; ++u) {
+                if (u == c) continue;
+                const cx<double> f = m[u][c];
+                for (int v = 0; v < 6; ++v) {
+                    m[u][v] = m[u][v] - f * m[c][v];
+                    r[u][v] = r[u][v] - f * r[c][v];
+                }
+            }
+        }
+        double* o = outr + 36 * blk;
+        for (int u = 0; u < 6; ++u) o[u] = r[u][u].re;
+        n = 0;
+        for (int u = 0; u < 6; ++u)
+            for (int v = u + 1; v < 6; ++v) {
+                o[6 + 2 * n] = r[u][v].re;
+                o[6 + 2 * n + 1] = r[u][v].im;
+                ++n;
+            }
+    }
+    for (int k = 0; k < 36; ++k)
+        inv[chunk_at(g.Vh, 36, par, k, i)] = double2{outr[2 * k], outr[2 * k + 1]};
+}
+
 // FP64 eo-SoA array of `nr` reals per site -> lower precision copies
 __global__ void convert_site_reals(Geom g, int nr, const double* src, float* f32, _Float16* f16,
                                    uint16_t* b16)
@@ -364,6 +441,7 @@ void free_op(qdw_op* op)
         if (op->links[p]) (void)hipFree(op->links[p]);
         if (op->det[p]) (void)hipFree(op->det[p]);
         if (op->clover[p]) (void)hipFree(op->clover[p]);
+        if (op->cloverinv[p]) (void)hipFree(op->cloverinv[p]);
     }
     if (op->partials) (void)hipFree(op->partials);
     if (op->scalars) (void)hipFree(op->scalars);
@@ -472,6 +550,19 @@ extern "C" int qdw_create(const qdw_lattice* lat, const double* su3, const doubl
     convert_site_reals<<<gs, 128, 0, st>>>(g, 72, (const double*)op->clover[F64],
                                            (float*)op->clover[F32], (_Float16*)op->clover[F16S],
                                            (uint16_t*)op->clover[BF16S]);
+    CREATE_HIP(hipGetLastError());
+    // their inverses (the even-odd reduced operator divides by the odd-site blocks)
+    CREATE_HIP(hipMalloc(&op->cloverinv[F64], ns * 72 * 8));
+    CREATE_HIP(hipMalloc(&op->cloverinv[F32], ns * 72 * 4));
+    CREATE_HIP(hipMalloc(&op->cloverinv[F16S], ns * 72 * 2));
+    CREATE_HIP(hipMalloc(&op->cloverinv[BF16S], ns * 72 * 2));
+    clover_inv_kernel<<<gs, 128, 0, st>>>(g, (const double2*)op->clover[F64],
+                                          (double2*)op->cloverinv[F64]);
+    CREATE_HIP(hipGetLastError());
+    convert_site_reals<<<gs, 128, 0, st>>>(g, 72, (const double*)op->cloverinv[F64],
+                                           (float*)op->cloverinv[F32],
+                                           (_Float16*)op->cloverinv[F16S],
+                                           (uint16_t*)op->cloverinv[BF16S]);
     CREATE_HIP(hipGetLastError());
 
     // 4. reduction scratch

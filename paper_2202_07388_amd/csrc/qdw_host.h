@@ -18,6 +18,7 @@ struct qdw_op {
     void* links[4];
     void* det[4];
     void* clover[4];
+    void* cloverinv[4];    // per precision: inverses of the clover blocks (same format)
     // per precision: shape of the D kernel (sites per parity of a workgroup, time slices
     // per walk chunk, software-pipelined hop loop, walk order, marching form); other site
     // kernels use g

@@ -56,6 +56,9 @@ def load():
         f.argtypes = [_P, _P, _P, ctypes.c_int, _P]
     for f in (L.dw_apply, L.dw_dag_apply):
         f.argtypes = [_P, _P, _P, ctypes.c_int, _P]
+    for name in ("dw_schur_apply", "dw_schur_dag_apply"):
+        if hasattr(L, name):
+            getattr(L, name).argtypes = [_P, _P, _P, ctypes.c_int, _P]
     _declare_solvers(L)
     _lib = L
     return L
@@ -82,7 +85,7 @@ class Info(ctypes.Structure):
 class CgneParams(ctypes.Structure):
     _fields_ = [("res", ctypes.c_double), ("nmx", ctypes.c_int), ("inner", ctypes.c_int),
                 ("delta", ctypes.c_double), ("keep_p", ctypes.c_int), ("cascade", ctypes.c_int),
-                ("cascade_c", ctypes.c_double)]
+                ("cascade_c", ctypes.c_double), ("schur", ctypes.c_int)]
 
 
 class SapGcrParams(ctypes.Structure):
@@ -242,6 +245,19 @@ def dw_dag_apply(op: Op, x, out, prec: str = "f64"):
     return out
 
 
+def dw_schur_apply(op: Op, x, out, prec: str = "f64"):
+    """Even half of out = D^ (even half of x); the odd half of out is scratch."""
+    _check(load().dw_schur_apply(op.handle, _ptr(x), _ptr(out), PREC[prec], _stream()),
+           "dw_schur_apply")
+    return out
+
+
+def dw_schur_dag_apply(op: Op, x, out, prec: str = "f64"):
+    _check(load().dw_schur_dag_apply(op.handle, _ptr(x), _ptr(out), PREC[prec], _stream()),
+           "dw_schur_dag_apply")
+    return out
+
+
 def axpby(op: Op, a: float, x, b: float, y, prec: str = "f64"):
     """y = a x + b y."""
     _check(load().qdw_axpby(op.handle, a, _ptr(x), b, _ptr(y), PREC[prec], _stream()),
@@ -282,12 +298,13 @@ def _workspace(op: Op, nbytes: int):
 
 def cgne_solve(op: Op, eta, psi, res: float = 1e-10, nmx: int = 20000, inner: str = "f64",
                delta: float = -1.0, keep_p: bool = True, cascade: bool = False,
-               cascade_c: float = 0.0) -> dict:
+               cascade_c: float = 0.0, schur: bool = False) -> dict:
     """Solve D^+ D psi = eta (FP64 eo-SoA fields) with the normal-equation CG; cascade=True
-    runs the BF16 -> FP32 -> FP64 precision cascade (inner is then ignored)."""
+    runs the BF16 -> FP32 -> FP64 precision cascade (inner is then ignored); schur=True
+    solves the even-odd reduced system D^+ D^ psi_e = eta_e on the even halves."""
     L = load()
     prm = CgneParams(res, nmx, PREC[inner], delta, 1 if keep_p else 0, 1 if cascade else 0,
-                     cascade_c)
+                     cascade_c, 1 if schur else 0)
     nb = int(L.qdw_cgne_workspace_bytes(op.handle, ctypes.byref(prm)))
     ws = _workspace(op, nb)
     info = Info()

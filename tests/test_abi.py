@@ -93,3 +93,8 @@ def test_cascade_workspace_without_gpu(lib):
     assert lib.qdw_cgne_workspace_bytes(None, ctypes.byref(prm)) == 0
     prm.cascade = 0
     assert lib.qdw_cgne_workspace_bytes(None, ctypes.byref(prm)) == 0
+
+
+def test_schur_entry_points_reject_null_without_gpu(lib):
+    assert lib.dw_schur_apply(None, None, None, 0, None) == -1
+    assert lib.dw_schur_dag_apply(None, None, None, 0, None) == -1
