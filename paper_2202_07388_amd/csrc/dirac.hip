@@ -175,6 +175,9 @@ __global__ __launch_bounds__(256) void dw_kernel(Geom g, RhsTable tab, int nrhs,
 //   * -t: at the end of step t each lane has its own spinor and its own forward t link in
 //     hand; it forms U_0^+ (1 -+ gamma_0) psi, the -t hop of the partner's site at t+1,
 //     and hands it over through LDS.
+// The lane's own spinor of a slice is loaded once, as the +t neighbour one step earlier,
+// and kept in registers for the clover term and the hand-over (a reload a step later
+// would find it evicted from L2); the t link likewise within a step.
 // Only the spatial hops read neighbours from memory; the neighbouring tiles' workgroups
 // march through the same slices at the same time, so those come from L2. One barrier per
 // step: the LDS buffers are double-buffered by slice parity (see the step comments).
@@ -246,11 +249,8 @@ __global__ __launch_bounds__(256) void dw_march_kernel(Geom g, RhsTable tab, int
     };
     // U_0(y)^+ (1 + SGB gamma_0) psi(y) for the partner's site one slice up (sign when the
     // hop wraps from T-1 to 0)
-    auto push = [&](int t, int slot) {
-        const int i = t * g.S + k;
-        cx<R> sp[12], h[6], w[6], u[6], d;
-        load_spinor<P>(in, g.Vh, par, i, sp);
-        load_link<P>(links, dets, g.Vh, par, i, 0, u, d);
+    auto push = [&](int t, int slot, const cx<R> sp[12], const cx<R> u[6], cx<R> d) {
+        cx<R> h[6], w[6];
         project<R, 0, SGB>(sp, h);
         if (g.bc_t < 0 && t == g.L[0] - 1) {
 #pragma unroll
@@ -259,16 +259,27 @@ __global__ __launch_bounds__(256) void dw_march_kernel(Geom g, RhsTable tab, int
         su3_mul<R, true>(u, d, h, w);
         put6(pw, slot, partner, w);
     };
-    if (valid) push(t0 == 0 ? g.L[0] - 1 : t0 - 1, t0 & 1);
+    // the lane's own spinor of the current slice stays in registers from the step that
+    // loaded it for the partner (a reload one step later would come from HBM again)
+    cx<R> own[12];
+    if (valid) {
+        const int tp = t0 == 0 ? g.L[0] - 1 : t0 - 1;
+        cx<R> u[6], d;
+        load_spinor<P>(in, g.Vh, par, tp * g.S + k, own);
+        load_link<P>(links, dets, g.Vh, par, tp * g.S + k, 0, u, d);
+        push(tp, t0 & 1, own, u, d);
+        load_spinor<P>(in, g.Vh, par, t0 * g.S + k, own);
+    }
     for (int step = 0; step < g.nt; ++step) {
         const int t = t0 + step;
         const int tn = t + 1 == g.L[0] ? 0 : t + 1;
         // (1) the spinor this lane owns at t+1, projected for the partner's +t hop; slot
         //     (t+1)&1 was last read two steps ago, before the previous barrier
+        cx<R> nxt[12];
         if (valid) {
-            cx<R> sp[12], h[6];
-            load_spinor<P>(in, g.Vh, par, tn * g.S + k, sp);
-            project<R, 0, SGF>(sp, h);
+            cx<R> h[6];
+            load_spinor<P>(in, g.Vh, par, tn * g.S + k, nxt);
+            project<R, 0, SGF>(nxt, h);
             put6(hp, (t + 1) & 1, partner, h);
         }
         __syncthreads();
@@ -279,31 +290,33 @@ __global__ __launch_bounds__(256) void dw_march_kernel(Geom g, RhsTable tab, int
             cx<R> hop[12];
 #pragma unroll
             for (int q = 0; q < 12; ++q) hop[q] = {(R)0, (R)0};
+            cx<R> u0[6], d0;  // the site's forward t link, also used for the push below
             {
                 // +t: U_0(x) times the projected neighbour from the partner
-                cx<R> h[6], w[6], u[6], d;
+                cx<R> h[6], w[6];
                 get6(hp, (t + 1) & 1, h);
                 if (g.bc_t < 0 && x[0] == g.L[0] - 1) {
 #pragma unroll
                     for (int q = 0; q < 6; ++q) h[q] = {-h[q].re, -h[q].im};
                 }
-                load_link<P>(links, dets, g.Vh, par, i, 0, u, d);
-                su3_mul<R, false>(u, d, h, w);
+                load_link<P>(links, dets, g.Vh, par, i, 0, u0, d0);
+                su3_mul<R, false>(u0, d0, h, w);
                 expand_add<R, 0, SGF>(w, hop);
                 // -t: already transported by the partner
                 get6(pw, t & 1, w);
                 expand_add<R, 0, SGB>(w, hop);
             }
             march_site_hops<P, DAG>(g, in, links, dets, par, i, x, lex, hop);
-            cx<R> sp[12], acc[12];
-            load_spinor<P>(in, g.Vh, par, i, sp);
-            clover_apply<P>(clover, g.Vh, par, i, sp, acc);
+            cx<R> acc[12];
+            clover_apply<P>(clover, g.Vh, par, i, own, acc);
 #pragma unroll
             for (int q = 0; q < 12; ++q) acc[q] = acc[q] - scale(hop[q], (R)0.5);
             store_spinor<P>(out, g.Vh, par, i, acc);
             // (2) the partner's -t hop at t+1; slot (t+1)&1 was read one step ago, before
             //     this step's barrier
-            if (step + 1 < g.nt) push(t, (t + 1) & 1);
+            if (step + 1 < g.nt) push(t, (t + 1) & 1, own, u0, d0);
+#pragma unroll
+            for (int q = 0; q < 12; ++q) own[q] = nxt[q];
         }
     }
 }
