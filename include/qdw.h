@@ -137,8 +137,8 @@ int dw_apply_multi(qdw_op* op, const void* const* in, void* const* out, int nrhs
 int qdw_autotune(qdw_op* op, qdw_prec prec, int nrhs, char* report, size_t report_len,
                  void* stream);
 /* Set / read the D kernel's shape for precision prec by hand (ts 64 or 128, nt in 1..16
- * dividing T, pipe 0 or 1, walk 0 or 1, march 0 or 1 (marching implies pipe 1);
- * shape5 = {ts, nt, pipe, walk, march}); QDW_EINVAL for anything else. */
+ * dividing T, pipe 0 or 1, walk 0 or 1, march 0 or 1; shape5 = {ts, nt, pipe, walk,
+ * march}); QDW_EINVAL for anything else. */
 int qdw_set_dw_shape(qdw_op* op, qdw_prec prec, int ts, int nt, int pipe, int walk, int march);
 int qdw_get_dw_shape(const qdw_op* op, qdw_prec prec, int* shape5);
 

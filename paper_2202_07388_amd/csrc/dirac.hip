@@ -181,11 +181,23 @@ __global__ __launch_bounds__(256) void dw_kernel(Geom g, RhsTable tab, int nrhs,
 // Only the spatial hops read neighbours from memory; the neighbouring tiles' workgroups
 // march through the same slices at the same time, so those come from L2. One barrier per
 // step: the LDS buffers are double-buffered by slice parity (see the step comments).
-template <int P, bool DAG>
+template <int P, bool DAG, bool PIPE>
 __device__ __forceinline__ void march_site_hops(const Geom& g, const void* in, const void* links,
                                                 const void* dets, int par, int i, const int x[4],
                                                 int lex, cx<typename Traits<P>::real> hop[12])
 {
+    if constexpr (!PIPE) {
+        // the six spatial hops (loop steps 2..7 of dw_kernel), one register buffer
+        HopIn<P> A;
+#pragma unroll 1
+        for (int k = 2; k < 8; ++k) {
+            int ii = i, ll = lex, xx[4] = {x[0], x[1], x[2], x[3]};
+            asm volatile("" : "+v"(ii), "+v"(ll), "+v"(xx[0]), "+v"(xx[1]), "+v"(xx[2]), "+v"(xx[3]));
+            load_k<P>(k, g, in, links, dets, par, ii, xx, ll, A);
+            compute_k<P, DAG>(k, g, xx, A, hop);
+        }
+        return;
+    }
     // the six spatial hops (loop steps 2..7 of dw_kernel), two register buffers
     HopIn<P> A, B;
     load_k<P>(2, g, in, links, dets, par, i, x, lex, A);
@@ -200,7 +212,7 @@ __device__ __forceinline__ void march_site_hops(const Geom& g, const void* in, c
     }
 }
 
-template <int P, bool DAG>
+template <int P, bool DAG, bool PIPE>
 __global__ __launch_bounds__(256) void dw_march_kernel(Geom g, RhsTable tab, int nrhs,
                                                        const void* __restrict__ links,
                                                        const void* __restrict__ dets,
@@ -306,7 +318,7 @@ __global__ __launch_bounds__(256) void dw_march_kernel(Geom g, RhsTable tab, int
                 get6(pw, t & 1, w);
                 expand_add<R, 0, SGB>(w, hop);
             }
-            march_site_hops<P, DAG>(g, in, links, dets, par, i, x, lex, hop);
+            march_site_hops<P, DAG, PIPE>(g, in, links, dets, par, i, x, lex, hop);
             cx<R> acc[12];
             clover_apply<P>(clover, g.Vh, par, i, own, acc);
 #pragma unroll
@@ -396,8 +408,12 @@ int launch(qdw_op* op, const RhsTable& tab, int nrhs, hipStream_t st)
         const int nblk = (g.L[0] / g.nt) * g.ntile * nrhs;
         const size_t lds = (size_t)2 * 2 * 12 * (2 * g.ts) * sizeof(R);
         static_assert(sizeof(R) == 8 || sizeof(R) == 4, "real type");
-        dw_march_kernel<P, DAG><<<nblk, 2 * g.ts, lds, st>>>(g, tab, nrhs, op->links[P],
-                                                             op->det[P], op->clover[P]);
+        if (op->dw_shape[P].pipe)
+            dw_march_kernel<P, DAG, true><<<nblk, 2 * g.ts, lds, st>>>(g, tab, nrhs, op->links[P],
+                                                                       op->det[P], op->clover[P]);
+        else
+            dw_march_kernel<P, DAG, false><<<nblk, 2 * g.ts, lds, st>>>(g, tab, nrhs, op->links[P],
+                                                                        op->det[P], op->clover[P]);
         QDW_LAUNCH_CHECK();
         return QDW_OK;
     }
@@ -548,7 +564,6 @@ int check_shape(const qdw_op* op, int prec, int ts, int nt, int pipe, int walk, 
               "D kernel shape: a marching FP64 workgroup of 128 sites per parity needs more "
               "than 64 KB of LDS");
     QDW_CHECK(march == 0 || march == 1, QDW_EINVAL, "D kernel shape: march must be 0 or 1");
-    QDW_CHECK(!march || pipe == 1, QDW_EINVAL, "D kernel shape: the marching form is pipelined");
     QDW_CHECK(ts == 64 || ts == 128, QDW_EINVAL, "D kernel shape: ts must be 64 or 128");
     QDW_CHECK(nt >= 1 && nt <= 16 && op->g.L[0] % nt == 0, QDW_EINVAL,
               "D kernel shape: nt must divide T and lie in 1..16");
@@ -606,9 +621,8 @@ extern "C" int qdw_autotune(qdw_op* op, qdw_prec prec, int nrhs, char* report, s
             for (int ts : {64, 128})
                 for (int nt = 1; nt <= 16; nt *= 2) {
                     if (g.L[0] % nt) continue;
-                    // the marching form pipelines its spatial hops always
                     if (march && march_lds(prec, ts) > 65536) continue;
-                    for (int pipe = march; pipe < 2; ++pipe)
+                    for (int pipe = 0; pipe < 2; ++pipe)
                         cands.push_back({ts, nt, pipe, walk, march, 0.f});
                 }
     int rc = QDW_OK;
