@@ -95,9 +95,9 @@ __device__ __forceinline__ long f32_addr(int Vh, int par, int i, int s, int c)
 // A[(q, c)][((p*Cin + b)*4 + t)*2 + re/im] = (T_p in_b)(q)[t][c], q = par*Vp + i. Rows of
 // padded sites and the padding columns K..Kpad-1 are written as zeros, so the matrix holds
 // no stale values from earlier use of the workspace.
-template <bool F32M>
+template <bool F32M, int PIN>
 __global__ __launch_bounds__(256) void nn_transport_kernel(Geom g, int Cin, int Kpad, long Mp,
-                                                           const float* const* in, void* A,
+                                                           const void* const* in, void* A,
                                                            const void* links, const void* dets)
 {
     const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -118,17 +118,17 @@ __global__ __launch_bounds__(256) void nn_transport_kernel(Geom g, int Cin, int 
     }
     int x[4], lex;
     eo_coords(g, par, i, x, lex);
-    const float* v = in[b];
+    const void* v = in[b];
     for (int p = 0; p < kPaths; ++p) {
         cx<float> s[12], w[12];
         if (p == 0) {
-            load_spinor<F32>(v, g.Vh, par, i, s);
+            load_spinor<PIN>(v, g.Vh, par, i, s);
             for (int k = 0; k < 12; ++k) w[k] = s[k];
         } else {
             const int mu = (p - 1) >> 1;
             const bool fwd = ((p - 1) & 1) == 0;
             const int j = (fwd ? lex_fwd(g, x, lex, mu) : lex_bwd(g, x, lex, mu)) >> 1;
-            load_spinor<F32>(v, g.Vh, 1 - par, j, s);
+            load_spinor<PIN>(v, g.Vh, 1 - par, j, s);
             cx<float> u[6], d;
             float sg = 1.f;
             if (fwd) {
@@ -468,9 +468,9 @@ __device__ __forceinline__ void nn_put_rows(uint16_t* tile, int sl, int k0, cons
     }
 }
 
-template <int CIN, int COUT>
-__global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, const float* const* in,
-                                                             const void* Bt, float* const* out,
+template <int CIN, int COUT, int PIN, int POUT>
+__global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, const void* const* in,
+                                                             const void* Bt, void* const* out,
                                                              const void* links, const void* dets)
 {
     constexpr int PB = CIN == 1 ? kPaths : 1;          // paths per batch
@@ -479,8 +479,8 @@ __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, c
     constexpr int NT = COUT * 8 >= 16 ? COUT * 8 / 16 : 1;  // 16-column tiles of N
     static_assert(CIN == 1 || CIN == 8, "channel counts of the network");
     // LDS: the transported tile during the batches, then the output block (COUT channels x
-    // 6 chunks x 64 sites x 4 floats, the eo-SoA order of one 64-site block)
-    constexpr int TILE_B = 192 * LS * 2, OUT_B = COUT * 6 * 64 * 16;
+    // 24 reals x 64 sites, FP32)
+    constexpr int TILE_B = 192 * LS * 2, OUT_B = COUT * 24 * 64 * 4;
     __shared__ __attribute__((aligned(16))) char lds[TILE_B > OUT_B ? TILE_B : OUT_B];
     uint16_t* tile = (uint16_t*)lds;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -501,13 +501,13 @@ __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, c
     } pf;
     auto prefetch = [&](int p) {
         if (p == 0) {
-            load_spinor<F32>(in[wave], g.Vh, par, i, pf.s0);
-            load_spinor<F32>(in[wave + 4], g.Vh, par, i, pf.s1);
+            load_spinor<PIN>(in[wave], g.Vh, par, i, pf.s0);
+            load_spinor<PIN>(in[wave + 4], g.Vh, par, i, pf.s1);
         } else {
             int j;
             nn_path_setup(g, par, i, x, lex, p, links, dets, j, pf.sg, pf.u, pf.d);
-            load_spinor<F32>(in[wave], g.Vh, 1 - par, j, pf.s0);
-            load_spinor<F32>(in[wave + 4], g.Vh, 1 - par, j, pf.s1);
+            load_spinor<PIN>(in[wave], g.Vh, 1 - par, j, pf.s0);
+            load_spinor<PIN>(in[wave + 4], g.Vh, 1 - par, j, pf.s1);
         }
     };
     if (CIN == 8 && real) prefetch(0);
@@ -542,13 +542,13 @@ __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, c
                     continue;
                 }
                 if (p == 0) {
-                    load_spinor<F32>(in[0], g.Vh, par, i, w);
+                    load_spinor<PIN>(in[0], g.Vh, par, i, w);
                 } else {
                     int j;
                     float sg;
                     cx<float> u[6], d, sp[12];
                     nn_path_setup(g, par, i, x, lex, p, links, dets, j, sg, u, d);
-                    load_spinor<F32>(in[0], g.Vh, 1 - par, j, sp);
+                    load_spinor<PIN>(in[0], g.Vh, 1 - par, j, sp);
                     nn_path_apply(((p - 1) & 1) == 0, u, d, sg, sp, w);
                 }
                 nn_put_rows<LS>(tile, sl, p * 8, w);
@@ -573,9 +573,9 @@ __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, c
         }
         __syncthreads();  // the tile is rewritten by the next batch
     }
-    // outputs: row m = 3 * site + c, column n = (a * 4 + s) * 2 + re/im, staged in LDS in
-    // the fields' order (the 64 sites are one aligned block of one parity), then written
-    // as contiguous 16-byte chunks
+    // outputs: row m = 3 * site + c, column n = (a * 4 + s) * 2 + re/im, staged in LDS as
+    // [channel][real][site] (the 64 sites are one aligned block of one parity), then
+    // written in the output precision as contiguous 16-byte chunks
     float* ob = (float*)lds;
     for (int r = 0; r < 3; ++r)
         for (int j = 0; j < NT; ++j)
@@ -585,15 +585,22 @@ __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, c
                 const int ms = m / 3, c = m - ms * 3;
                 const int a = n >> 3, sp = (n >> 1) & 3, ri = n & 1;
                 if (a >= COUT) continue;
-                const int k12 = sp * 3 + c;
-                ob[((a * 6 + (k12 >> 1)) * 64 + ms) * 4 + (k12 & 1) * 2 + ri] = acc[r][j][e];
+                ob[(a * 24 + (sp * 3 + c) * 2 + ri) * 64 + ms] = acc[r][j][e];
             }
     __syncthreads();
+    using T = Traits<POUT>;
+    constexpr int NC = T::SPIN_CHUNKS, PC = T::PER_CHUNK;
     const int opar = (int)(q0 / Vp), oi0 = (int)(q0 - (long)opar * Vp);
-    for (int u = threadIdx.x; u < COUT * 6 * 64; u += 256) {
-        const int a = u / 384, rem = u - a * 384, ch = rem >> 6, site = rem & 63;
+    for (int u = threadIdx.x; u < COUT * NC * 64; u += 256) {
+        const int a = u / (NC * 64), rem = u - a * (NC * 64), ch = rem >> 6, site = rem & 63;
         if (oi0 + site >= g.Vh) continue;
-        ((float4*)out[a])[chunk_at(g.Vh, 6, opar, ch, oi0 + site)] = ((const float4*)ob)[u];
+        Chunk<POUT> cval;
+#pragma unroll
+        for (int j = 0; j < PC; ++j)
+            cval.v[j] = to_store<POUT>((typename T::real)ob[(a * 24 + ch * PC + j) * 64 + site]);
+        uint4 raw;
+        __builtin_memcpy(&raw, &cval, 16);
+        ((uint4*)out[a])[chunk_at(g.Vh, NC, opar, ch, oi0 + site)] = raw;
     }
 }
 
@@ -637,7 +644,8 @@ struct LossDiff {
 // ------------------------------------------------------------------ host side
 
 struct NnWork {
-    float* act[kLayers + 1][8];  // channel fields per layer boundary (FP32)
+    float* act[kLayers + 1][8];  // channel fields per layer boundary (FP32 space; the hidden
+                                 // ones hold bf16 fields in the bf16 forward pass)
     float* grad[2][8];           // gradient channel fields (ping-pong)
     float* efield;               // target (FP32)
     void* A;                     // transported rows, [Mpad][Kmax]
@@ -710,19 +718,23 @@ int forward(qdw_op* op, const float* weights, NnWork& W, hipStream_t st)
             weights + 2 * layer_w_offset(l), Cin, Cout, Kp, Np, W.Bt, W.Bk);
         QDW_LAUNCH_CHECK();
         if constexpr (!F32M) {
+            // hidden activations (between the layers) are stored in bf16, the network's
+            // input and output in FP32
             const unsigned nb = (unsigned)(nq / 64);
             const void* L = op->links[F32];
             const void* D = op->det[F32];
+            const void* const* pin = (const void* const*)W.ptrs;
+            void* const* pout = (void* const*)(W.ptrs + 8);
             if (Cin == 1)
-                nn_layer_fused_kernel<1, 8><<<nb, 256, 0, st>>>(g, Kp, W.ptrs, W.Bt, W.ptrs + 8, L, D);
+                nn_layer_fused_kernel<1, 8, F32, BF16S><<<nb, 256, 0, st>>>(g, Kp, pin, W.Bt, pout, L, D);
             else if (Cout == 8)
-                nn_layer_fused_kernel<8, 8><<<nb, 256, 0, st>>>(g, Kp, W.ptrs, W.Bt, W.ptrs + 8, L, D);
+                nn_layer_fused_kernel<8, 8, BF16S, BF16S><<<nb, 256, 0, st>>>(g, Kp, pin, W.Bt, pout, L, D);
             else
-                nn_layer_fused_kernel<8, 1><<<nb, 256, 0, st>>>(g, Kp, W.ptrs, W.Bt, W.ptrs + 8, L, D);
+                nn_layer_fused_kernel<8, 1, BF16S, F32><<<nb, 256, 0, st>>>(g, Kp, pin, W.Bt, pout, L, D);
             QDW_LAUNCH_CHECK();
         } else {
-            nn_transport_kernel<F32M><<<(unsigned)((nq * Cin + 255) / 256), 256, 0, st>>>(
-                g, Cin, Kp, Mp, W.ptrs, W.A, op->links[F32], op->det[F32]);
+            nn_transport_kernel<F32M, F32><<<(unsigned)((nq * Cin + 255) / 256), 256, 0, st>>>(
+                g, Cin, Kp, Mp, (const void* const*)W.ptrs, W.A, op->links[F32], op->det[F32]);
             QDW_LAUNCH_CHECK();
             nn_gemm_out_kernel<F32M><<<(unsigned)(Mp / 64), 256, 0, st>>>(g, Kp, Np, Cout, Mp, W.A,
                                                                           W.Bt, W.ptrs + 8);
@@ -746,10 +758,16 @@ int backward(qdw_op* op, const float* weights, float* dW, NnWork& W, float gscal
     int cur = 0;  // grad[cur] holds the gradient of layer l's output
     for (int l = kLayers - 1; l >= 0; --l) {
         const int Cin = kCh[l], Cout = kCh[l + 1], Kp = layer_K(l), Np = layer_N(l);
-        // recompute this layer's transported input rows
+        // recompute this layer's transported input rows (hidden activations are bf16 in
+        // the bf16 forward pass)
         if ((rc = set_ptrs(W.ptrs, W.act[l], Cin, 0, st))) return rc;
-        nn_transport_kernel<F32M><<<(unsigned)((nq * Cin + 255) / 256), 256, 0, st>>>(
-            g, Cin, Kp, Mp, W.ptrs, W.A, op->links[F32], op->det[F32]);
+        const unsigned ntb = (unsigned)((nq * Cin + 255) / 256);
+        if (F32M || l == 0)
+            nn_transport_kernel<F32M, F32><<<ntb, 256, 0, st>>>(
+                g, Cin, Kp, Mp, (const void* const*)W.ptrs, W.A, op->links[F32], op->det[F32]);
+        else
+            nn_transport_kernel<F32M, BF16S><<<ntb, 256, 0, st>>>(
+                g, Cin, Kp, Mp, (const void* const*)W.ptrs, W.A, op->links[F32], op->det[F32]);
         QDW_LAUNCH_CHECK();
         nn_embed_kernel<F32M><<<(Kp * Np + 255) / 256, 256, 0, st>>>(
             weights + 2 * layer_w_offset(l), Cin, Cout, Kp, Np, W.Bt, W.Bk);
