@@ -110,8 +110,9 @@ def test_rejects_odd_extent():
 
 
 def test_full_size_sampled_sites():
-    """32^3 x 64 in the launch configuration the benchmark times, checked on sampled
-    sites that the oracle computes one by one (FP64 to 1e-13, FP32 to 2e-6)."""
+    """32^3 x 64 in the launch configurations the benchmark times (its pinned shapes) and
+    in the one-workgroup-per-slice form, D and D^+, checked on sampled sites that the
+    oracle computes one by one (FP64 to 1e-13, FP32 to 2e-6, FP16 storage to 2e-2)."""
     dims = (64, 32, 32, 32)
     su3, th = syn.gauge_field(dims, 0.3, 0.1, 7388 + 10)
     m0, csw = -0.05, 1.7
@@ -126,9 +127,20 @@ def test_full_size_sampled_sites():
     lex = list(((x[:, 0] * 32 + x[:, 1]) * 32 + x[:, 2]) * 32 + x[:, 3])
     sites = np.array(lex + list(rng.integers(0, V, 251)))
     want = oracle.dw_at_sites(dims, -1, u, m0, csw, psi, sites)
-    for prec, tol in (("f64", 1e-13), ("f32", 2e-6)):
+    # D^+ = gamma_5 D gamma_5 (pinned in the oracle tests), sampled the same way
+    g5 = np.array([1.0, 1.0, -1.0, -1.0])[None, :, None]
+    want_dag = g5 * oracle.dw_at_sites(dims, -1, u, m0, csw, g5[0] * psi, sites)
+    from bench import PINNED_SHAPES  # the shapes the benchmark times
+    for prec, tol in (("f64", 1e-13), ("f32", 2e-6), ("f16", 2e-2)):
         xf = gop.pack(psi, prec)
-        y = gop.new_field(prec)
-        qdw.dw_apply(gop, xf, y, prec)
-        got = gop.unpack(y, prec)[sites].cpu().numpy()
-        assert rel(got, want) <= tol, (prec, rel(got, want))
+        for shape in (PINNED_SHAPES[prec], None):
+            if shape is not None:
+                qdw.set_dw_shape(gop, prec, *shape)
+            else:
+                qdw.set_dw_shape(gop, prec, 128, 8, 1, 0, 0)  # the one-workgroup-per-slice form
+            for dag in (False, True):
+                y = gop.new_field(prec)
+                (qdw.dw_dag_apply if dag else qdw.dw_apply)(gop, xf, y, prec)
+                got = gop.unpack(y, prec)[sites].cpu().numpy()
+                ref = want_dag if dag else want
+                assert rel(got, ref) <= tol, (prec, shape, dag, rel(got, ref))
