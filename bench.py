@@ -27,6 +27,7 @@ Also reported, each timed on its own outside the K steps:
   * the FP64 oracle timed on the host on a bounded sample (cpu_baseline).
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-solves]
+                       [--legs cgne,nn,gcr,batch] [--autotune] [--calibrate]
 """
 from __future__ import annotations
 
@@ -289,6 +290,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solves", action="store_true")
     ap.add_argument("--no-nn", action="store_true", help="skip training the learned preconditioner")
+    ap.add_argument("--legs", default="cgne,nn,gcr,batch",
+                    help="comma-separated solve legs to run after the D timing "
+                         "(cgne, nn, gcr, batch); kernel traces of one leg use this")
     ap.add_argument("--autotune", action="store_true",
                     help="pick the 32^3x64 D-kernel shapes with the autotuner instead of the "
                          "pinned ones (its own launches then join any kernel trace)")
@@ -396,13 +400,19 @@ def main():
         "autotune": tuned,
         "wall_s_timed_region": round(wall, 4),
     }
-    if not args.no_solves:
-        log("solves ...")
+    legs = set() if args.no_solves else set(args.legs.split(","))
+    if args.no_nn:
+        legs.discard("nn")
+    if legs:
+        log("solves: %s ..." % sorted(legs))
+    if "cgne" in legs:
         out["cgne_32c64"] = cgne_solves(op, qdw, psi)
-        if not args.no_nn:
-            out["learned_precond_32c64"] = learned_preconditioner(qdw, syn, op, psi)
-        op.close()
+    if "nn" in legs:
+        out["learned_precond_32c64"] = learned_preconditioner(qdw, syn, op, psi)
+    op.close()
+    if "gcr" in legs:
         out["sap_gcr_24c48"] = gcr_solves(qdw, syn)
+    if "batch" in legs:
         out["batched_40rhs"] = batched_solves(qdw, syn)
     if not args.no_cpu_baseline:
         log("timing the oracle on the host (bounded sample) ...")

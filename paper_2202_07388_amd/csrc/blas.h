@@ -293,9 +293,14 @@ struct CgStep {
         }
         st4<PX, R>(x, Vh, u.par, u.g, u.i, vx);
         st4<P, R>(r, Vh, u.par, u.g, u.i, vr);
-        // reduce what is stored (rounded), in FP64
+        // reduce what is stored (rounded to P), in FP64; FP64 stores the values as they are
         cx<double> back[4];
-        ld4<P, double>(r, Vh, u.par, u.g, u.i, back);
+        if constexpr (P == F64) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) back[k] = {(double)vr[k].re, (double)vr[k].im};
+        } else {
+            ld4<P, double>(r, Vh, u.par, u.g, u.i, back);
+        }
 #pragma unroll
         for (int k = 0; k < 4; ++k) acc[0] += back[k].re * back[k].re + back[k].im * back[k].im;
     }

@@ -339,40 +339,64 @@ __global__ __launch_bounds__(256) void dw_march_kernel(Geom g, RhsTable tab, int
 //   stage 2, even sites: out = A_ee psi_e - D_eo t = A_ee psi_e + 1/2 sum of the hops of t
 // t lives in the odd half of the output field. D^+ = gamma_5 D^ gamma_5 flips the
 // projector signs as for D (A and A^-1 commute with gamma_5).
-template <int P, bool DAG, int STAGE>
-__global__ __launch_bounds__(256) void schur_kernel(Geom g, const void* hsrc, const void* dsrc,
-                                                    void* out, const void* __restrict__ links,
+template <int P, bool DAG, int STAGE, bool PIPE>
+__global__ __launch_bounds__(256) void schur_kernel(Geom g, int ntile1, const void* hsrc,
+                                                    const void* dsrc, void* out,
+                                                    const void* __restrict__ links,
                                                     const void* __restrict__ dets,
                                                     const void* __restrict__ diag)
 {
     using R = typename Traits<P>::real;
     constexpr int par = STAGE == 1 ? 1 : 0;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= g.Vh) return;
+    // one parity: tiles of 256 consecutive even-odd indices of a slice, nt slices of one
+    // tile in a row, XCD-contiguous (as the one-workgroup-per-slice D kernel, walk 0)
+    const int logical = xcd_tile(blockIdx.x, gridDim.x);
+    const int per_chunk = g.nt * ntile1;
+    const int c = logical / per_chunk;
+    const int r = logical - c * per_chunk;
+    const int sidx = r / g.nt;
+    const int t = c * g.nt + (r - sidx * g.nt);
+    const int k = sidx * 256 + (int)threadIdx.x;
+    if (k >= g.S) return;
+    const int i = t * g.S + k;
     int x[4], lex;
     eo_coords(g, par, i, x, lex);
     cx<R> hop[12];
 #pragma unroll
-    for (int c = 0; c < 12; ++c) hop[c] = {(R)0, (R)0};
-    HopIn<P> A;
+    for (int q = 0; q < 12; ++q) hop[q] = {(R)0, (R)0};
+    if constexpr (PIPE) {
+        HopIn<P> A, B;
+        load_k<P>(0, g, hsrc, links, dets, par, i, x, lex, A);
 #pragma unroll 1
-    for (int k = 0; k < 8; ++k) {
-        int ii = i, ll = lex, xx[4] = {x[0], x[1], x[2], x[3]};
-        asm volatile("" : "+v"(ii), "+v"(ll), "+v"(xx[0]), "+v"(xx[1]), "+v"(xx[2]), "+v"(xx[3]));
-        load_k<P>(k, g, hsrc, links, dets, par, ii, xx, ll, A);
-        compute_k<P, DAG>(k, g, xx, A, hop);
+        for (int kk = 0; kk < 8; kk += 2) {
+            int ii = i, ll = lex, xx[4] = {x[0], x[1], x[2], x[3]};
+            asm volatile("" : "+v"(ii), "+v"(ll), "+v"(xx[0]), "+v"(xx[1]), "+v"(xx[2]), "+v"(xx[3]));
+            load_k<P>(kk + 1, g, hsrc, links, dets, par, ii, xx, ll, B);
+            compute_k<P, DAG>(kk, g, xx, A, hop);
+            if (kk + 2 < 8) load_k<P>(kk + 2, g, hsrc, links, dets, par, ii, xx, ll, A);
+            compute_k<P, DAG>(kk + 1, g, xx, B, hop);
+        }
+    } else {
+        HopIn<P> A;
+#pragma unroll 1
+        for (int kk = 0; kk < 8; ++kk) {
+            int ii = i, ll = lex, xx[4] = {x[0], x[1], x[2], x[3]};
+            asm volatile("" : "+v"(ii), "+v"(ll), "+v"(xx[0]), "+v"(xx[1]), "+v"(xx[2]), "+v"(xx[3]));
+            load_k<P>(kk, g, hsrc, links, dets, par, ii, xx, ll, A);
+            compute_k<P, DAG>(kk, g, xx, A, hop);
+        }
     }
     cx<R> acc[12];
     if constexpr (STAGE == 1) {
 #pragma unroll
-        for (int c = 0; c < 12; ++c) hop[c] = scale(hop[c], (R)-0.5);
+        for (int q = 0; q < 12; ++q) hop[q] = scale(hop[q], (R)-0.5);
         clover_apply<P>(diag, g.Vh, par, i, hop, acc);
     } else {
         cx<R> sp[12];
         load_spinor<P>(dsrc, g.Vh, par, i, sp);
         clover_apply<P>(diag, g.Vh, par, i, sp, acc);
 #pragma unroll
-        for (int c = 0; c < 12; ++c) acc[c] = acc[c] + scale(hop[c], (R)0.5);
+        for (int q = 0; q < 12; ++q) acc[q] = acc[q] + scale(hop[q], (R)0.5);
     }
     store_spinor<P>(out, g.Vh, par, i, acc);
 }
@@ -381,12 +405,15 @@ template <int P, bool DAG>
 int schur_launch_t(qdw_op* op, const void* in, void* out, hipStream_t st)
 {
     const Geom& g = op->g;
-    const int nb = (g.Vh + 255) / 256;
-    schur_kernel<P, DAG, 1><<<nb, 256, 0, st>>>(g, in, nullptr, out, op->links[P], op->det[P],
-                                                op->cloverinv[P]);
+    const int ntile1 = (g.S + 255) / 256;
+    const int nb = g.L[0] * ntile1;
+    // the hop loop is software-pipelined where the registers allow it (FP64, FP32), as for D
+    constexpr bool PIPE = P == F64 || P == F32;
+    schur_kernel<P, DAG, 1, PIPE><<<nb, 256, 0, st>>>(g, ntile1, in, nullptr, out, op->links[P],
+                                                      op->det[P], op->cloverinv[P]);
     QDW_LAUNCH_CHECK();
-    schur_kernel<P, DAG, 2><<<nb, 256, 0, st>>>(g, out, in, out, op->links[P], op->det[P],
-                                                op->clover[P]);
+    schur_kernel<P, DAG, 2, PIPE><<<nb, 256, 0, st>>>(g, ntile1, out, in, out, op->links[P],
+                                                      op->det[P], op->clover[P]);
     QDW_LAUNCH_CHECK();
     return QDW_OK;
 }
