@@ -604,6 +604,121 @@ __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, c
     }
 }
 
+// ------------------------------------------------------------------ last layer: mix, then transport
+//
+// With one output channel the order of the two linear maps of a layer pays to be swapped:
+// W_p acts on spin and channel, T_p on colour and site, so
+//     out(x) = sum_p sum_b W_p[0][b] (T_p in_b)(x) = sum_p (T_p m_p)(x),
+//     m_p(y) = sum_b W_p[0][b] in_b(y).
+// Pass 1 forms the nine m_p at every site on the matrix cores (rows (site, colour), K = 8
+// channels x 4 spins x re/im, N = 9 paths x 4 spins x re/im), storing them in bf16; pass 2
+// is a plain stencil over them. Each site then gathers 9 spinors instead of 72.
+
+// Bm[n][k]: n = (p*4 + s)*2 + re/im (72, padded to 80), k = (b*4 + t)*2 + re/im (64)
+__global__ void nn_embed_mix_kernel(const float* W, uint16_t* Bm)
+{
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= 80 * 64) return;
+    const int n = tid / 64, k = tid - n * 64;
+    float v = 0.f;
+    if (n < 72) {
+        const int p = n >> 3, sro = n & 7;            // (s, re/im) of the output
+        const int b = k >> 3, tri = k & 7;            // (t, re/im) of the input
+        v = embed(W, 8, 1, (p * 8 + b) * 8 + tri, sro);
+    }
+    Bm[tid] = float_to_bf16(v);
+}
+
+__global__ __launch_bounds__(256) void nn_mix_paths_kernel(Geom g, const void* const* in,
+                                                           const uint16_t* Bm, void* const* mix)
+{
+    constexpr int KB = 64, LS = KB + 8, NT = 5;
+    constexpr int TILE_B = 192 * LS * 2, OUT_B = 9 * 24 * 64 * 4;
+    __shared__ __attribute__((aligned(16))) char lds[TILE_B > OUT_B ? TILE_B : OUT_B];
+    uint16_t* tile = (uint16_t*)lds;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int Vp = padded(g.Vh);
+    const long q0 = (long)blockIdx.x * 64;
+    const int par = (int)(q0 / Vp), i0 = (int)(q0 - (long)par * Vp);
+    const int i = i0 + lane;
+    const cx<float> zero12[12] = {};
+    // rows of the tile: the site's eight input channels (channels wave and wave + 4)
+    if (i < g.Vh) {
+        cx<float> w0[12], w1[12];
+        load_spinor<BF16S>(in[wave], g.Vh, par, i, w0);
+        load_spinor<BF16S>(in[wave + 4], g.Vh, par, i, w1);
+        nn_put_rows<LS>(tile, lane, wave * 8, w0);
+        nn_put_rows<LS>(tile, lane, (wave + 4) * 8, w1);
+    } else {
+        nn_put_rows<LS>(tile, lane, wave * 8, zero12);
+        nn_put_rows<LS>(tile, lane, (wave + 4) * 8, zero12);
+    }
+    __syncthreads();
+    f4 acc[3][NT];
+    for (int r = 0; r < 3; ++r)
+        for (int j = 0; j < NT; ++j) acc[r][j] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int kk = 0; kk < KB; kk += 16) {
+        const int kl = kk + 4 * (lane >> 4);
+        s4 bf[NT];
+        for (int j = 0; j < NT; ++j)
+            bf[j] = *(const s4*)(Bm + (j * 16 + (lane & 15)) * KB + kl);
+        for (int r = 0; r < 3; ++r) {
+            const s4 a = *(const s4*)&tile[(wave * 48 + r * 16 + (lane & 15)) * LS + kl];
+            for (int j = 0; j < NT; ++j)
+                acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bf[j], acc[r][j], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+    // outputs staged as [path][real][site], then written as bf16 chunks
+    float* ob = (float*)lds;
+    for (int r = 0; r < 3; ++r)
+        for (int j = 0; j < NT; ++j)
+            for (int e = 0; e < 4; ++e) {
+                const int m = wave * 48 + r * 16 + 4 * (lane >> 4) + e;
+                const int n = j * 16 + (lane & 15);
+                if (n >= 72) continue;
+                const int ms = m / 3, c = m - ms * 3;
+                const int p = n >> 3, sp = (n >> 1) & 3, ri = n & 1;
+                ob[(p * 24 + (sp * 3 + c) * 2 + ri) * 64 + ms] = acc[r][j][e];
+            }
+    __syncthreads();
+    for (int u = threadIdx.x; u < 9 * 3 * 64; u += 256) {
+        const int p = u / 192, rem = u - p * 192, ch = rem >> 6, site = rem & 63;
+        if (i0 + site >= g.Vh) continue;
+        Chunk<BF16S> cval;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) cval.v[j] = float_to_bf16(ob[(p * 24 + ch * 8 + j) * 64 + site]);
+        uint4 raw;
+        __builtin_memcpy(&raw, &cval, 16);
+        ((uint4*)mix[p])[chunk_at(g.Vh, 3, par, ch, i0 + site)] = raw;
+    }
+}
+
+// out(x) = m_0(x) + sum_{p = 1..8} (T_p m_p)(x)   (FP32 output)
+__global__ __launch_bounds__(256) void nn_transport_sum_kernel(Geom g, const void* const* mix,
+                                                               float* out, const void* links,
+                                                               const void* dets)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int par = blockIdx.y;
+    if (i >= g.Vh) return;
+    int x[4], lex;
+    eo_coords(g, par, i, x, lex);
+    cx<float> acc[12];
+    load_spinor<BF16S>(mix[0], g.Vh, par, i, acc);
+    for (int p = 1; p < kPaths; ++p) {
+        int j;
+        float sg;
+        cx<float> u[6], d, sp[12], w[12];
+        nn_path_setup(g, par, i, x, lex, p, links, dets, j, sg, u, d);
+        load_spinor<BF16S>(mix[p], g.Vh, 1 - par, j, sp);
+        nn_path_apply(((p - 1) & 1) == 0, u, d, sg, sp, w);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[k] = acc[k] + w[k];
+    }
+    store_spinor<F32>(out, g.Vh, par, i, acc);
+}
+
 __global__ void fill_kernel(uint32_t* p, long n)
 {
     for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x)
@@ -655,13 +770,16 @@ struct NnWork {
     void* Bk;                    // [Kmax][Nmax]
     float* part;                 // [nsplit][Kmax][Nmax]
     float* dB;                   // [Kmax][Nmax]
-    float** ptrs;                // device pointer tables (16 slots)
+    void* mix[kPaths];           // bf16 fields m_p of the last layer's path mixing
+    uint16_t* Bm;                // [80][64] bf16: the last layer's mixing matrix
+    float** ptrs;                // device pointer tables (8 pointers per slot)
     char* end;
 };
 
 constexpr int kSplit = 64;
 
-size_t nn_layout(const qdw_op* op, bool training, char* base, NnWork* W)
+// need_A: the materialised transport matrix A (FP32-operand forward passes, training)
+size_t nn_layout(const qdw_op* op, bool training, char* base, NnWork* W, bool need_A = true)
 {
     const Geom& g = op->g;
     const size_t fb = spinor_bytes(g, F32);
@@ -677,7 +795,9 @@ size_t nn_layout(const qdw_op* op, bool training, char* base, NnWork* W)
     for (int h = 0; h < 2; ++h)
         for (int c = 0; c < 8; ++c) W->grad[h][c] = training ? (float*)take(fb) : nullptr;
     W->efield = training ? (float*)take(fb) : nullptr;
-    W->A = take((size_t)Mp * kMaxK * 4);
+    W->A = need_A || training ? take((size_t)Mp * kMaxK * 4) : nullptr;
+    for (int p = 0; p < kPaths; ++p) W->mix[p] = take(spinor_bytes(g, BF16S));
+    W->Bm = (uint16_t*)take(80 * 64 * 2);
     W->dA = training ? (float*)take((size_t)Mp * kMaxK * 4) : nullptr;
     W->G = training ? take((size_t)Mp * kMaxN * 4) : nullptr;
     W->Bt = take((size_t)kMaxN * kMaxK * 4);
@@ -725,13 +845,24 @@ int forward(qdw_op* op, const float* weights, NnWork& W, hipStream_t st)
             const void* D = op->det[F32];
             const void* const* pin = (const void* const*)W.ptrs;
             void* const* pout = (void* const*)(W.ptrs + 8);
-            if (Cin == 1)
+            if (Cin == 1) {
                 nn_layer_fused_kernel<1, 8, F32, BF16S><<<nb, 256, 0, st>>>(g, Kp, pin, W.Bt, pout, L, D);
-            else if (Cout == 8)
+                QDW_LAUNCH_CHECK();
+            } else if (Cout == 8) {
                 nn_layer_fused_kernel<8, 8, BF16S, BF16S><<<nb, 256, 0, st>>>(g, Kp, pin, W.Bt, pout, L, D);
-            else
-                nn_layer_fused_kernel<8, 1, BF16S, F32><<<nb, 256, 0, st>>>(g, Kp, pin, W.Bt, pout, L, D);
-            QDW_LAUNCH_CHECK();
+                QDW_LAUNCH_CHECK();
+            } else {
+                // one output channel: mix the paths first, then transport 9 fields
+                if ((rc = set_ptrs(W.ptrs, (float* const*)W.mix, kPaths, 3, st))) return rc;
+                nn_embed_mix_kernel<<<(80 * 64 + 255) / 256, 256, 0, st>>>(
+                    weights + 2 * layer_w_offset(l), W.Bm);
+                QDW_LAUNCH_CHECK();
+                nn_mix_paths_kernel<<<nb, 256, 0, st>>>(g, pin, W.Bm, (void* const*)(W.ptrs + 24));
+                QDW_LAUNCH_CHECK();
+                nn_transport_sum_kernel<<<dim3((g.Vh + 255) / 256, 2), 256, 0, st>>>(
+                    g, (const void* const*)(W.ptrs + 24), W.act[l + 1][0], L, D);
+                QDW_LAUNCH_CHECK();
+            }
         } else {
             nn_transport_kernel<F32M, F32><<<(unsigned)((nq * Cin + 255) / 256), 256, 0, st>>>(
                 g, Cin, Kp, Mp, (const void* const*)W.ptrs, W.A, op->links[F32], op->det[F32]);
@@ -808,7 +939,7 @@ char* align_work(void* work) { return (char*)(((uintptr_t)work + 255) & ~(uintpt
 size_t nn_precond_workspace(const qdw_op* op)
 {
     NnWork W;
-    return nn_layout(op, false, nullptr, &W);
+    return nn_layout(op, false, nullptr, &W, false);  // bf16 forward only: no A
 }
 
 // phi = N(rho): rho, phi FP64 eo-SoA fields; |rho| given (sets the FP32 scale)
@@ -816,7 +947,7 @@ int nn_precondition(qdw_op* op, const void* weights, const void* rho, void* phi,
                     char* work, hipStream_t st)
 {
     NnWork W;
-    nn_layout(op, false, work, &W);
+    nn_layout(op, false, work, &W, false);
     const Geom& g = op->g;
     int rc;
     if (!(rho_norm > 0.0)) return run_map(op, Zero<F64>{phi, g.Vh}, st);
