@@ -29,11 +29,14 @@
  *  - A qdw_op may be used from one stream at a time (its reduction scratch is shared).
  *
  * Field layout ("eo-SoA", what dw_apply and the solvers read and write): sites split by
- * parity (x0+x1+x2+x3) mod 2, even first (the paper's even-odd ordering, Fig. 3 left),
- * each parity stored as [chunk][V/2] 16-byte chunks of the site's 24 reals (12 complex,
- * index spin*3 + colour, interleaved re/im). Within a parity the site with lexicographic
- * index lex = ((x0*L1 + x1)*L2 + x2)*L3 + x3 sits at position lex/2. Use qdw_pack /
- * qdw_unpack to convert from and to the canonical layout [V][4][3] complex128.
+ * parity (x0+x1+x2+x3) mod 2, even first (the paper's even-odd ordering, Fig. 3 left).
+ * Within a parity the site with lexicographic index lex = ((x0*L1 + x1)*L2 + x2)*L3 + x3
+ * sits at position i = lex/2; positions are grouped in blocks of 64 (the count per parity
+ * padded to a multiple of 64), and a block stores 16-byte chunk 0 of its 64 sites, then
+ * chunk 1, ...: [parity][i/64][chunk][i%64]. A site's 24 reals (12 complex, index
+ * spin*3 + colour, interleaved re/im) fill 12 chunks in FP64, 6 in FP32, 3 in FP16/BF16.
+ * qdw_field_bytes gives a field's size; qdw_pack / qdw_unpack convert from and to the
+ * canonical layout [V][4][3] complex128. The padding positions hold no site.
  */
 #ifndef QDW_H
 #define QDW_H
