@@ -14,7 +14,8 @@ Contents, each written from its definition (stencil loops live in ``oracle.c``):
 * ``fgcr``: flexible GCR with restarts (Sec. 3.1, Table 2 settings res, nmx, nkv);
 * ``sap`` / ``mr_blocks``: Schwarz alternating procedure (Sec. 3, Fig. 2 and 3): chessboard
   blocks, grey then white, ``nmr`` minimal-residual steps per block, ``ncy`` cycles;
-* ``sap_adaptive``: the adaptive variant of Sec. 3.2;
+* ``sap_adaptive``: the adaptive variant of Sec. 3.2; ``sap_eo``: SAP with even-odd
+  reduced block solves;
 * ``Schur`` / ``cgne_schur``: the even-odd reduced operator A_ee - D_eo A_oo^-1 D_oe and
   CG on its normal equations;
 * ``nn_*``: a gauge-covariant linear network of parallel-transport layers, forward and
@@ -463,6 +464,60 @@ def sap(op: Operator, rho, bs, ncy: int, nmr: int):
         for colour in (0, 1):
             chi, _rb = mr_blocks(op, r, bs, colour, nmr, bid, col, nblk)
             psi = psi + chi
+            r = rho - op.dw(psi)
+    return psi
+
+
+def sap_eo(op: Operator, rho, bs, ncy: int, nmr: int):
+    """SAP whose block problems are solved through their even-odd reduction (the block
+    matrix is even-odd ordered like the whole lattice, Sec. 3 / Fig. 3 left): for the
+    block residual r = (r_e, r_o) and the Dirichlet block operator D_b,
+
+        r^_e = r_e - D_eo^b A_oo^-1 r_o,
+        chi_e = nmr MR steps from 0 on D^_b = A_ee - D_eo^b A_oo^-1 D_oe^b with source r^_e,
+        chi_o = A_oo^-1 (r_o - D_oe^b chi_e),
+
+    then psi += chi and the full residual is recomputed after each colour, as in ``sap``.
+    The blocks of D_b come from the block-restricted operator itself:
+    D_b (x_e, 0) = (A_ee x_e, D_oe^b x_e) and D_b (0, t) = (D_eo^b t, A_oo t).
+    """
+    rho = np.asarray(rho, dtype=np.complex128).reshape(op.V, 4, 3)
+    if ncy == 0:
+        return rho.copy()
+    bid, col, nblk = block_ids(op.dims, bs)
+    par = site_parity(op.dims)
+    even = (par == 0)[:, None, None]
+    odd = (par == 1)[:, None, None]
+    ainv = np.linalg.inv(op.A)
+
+    def inv_odd(y):
+        return np.where(odd, np.einsum("sab,sb->sa", ainv, y.reshape(-1, 12)).reshape(y.shape), 0)
+
+    def schur_b(x):  # D^_b on even fields (zero elsewhere)
+        y = op.dw_blocks(np.where(even, x, 0), bs)
+        z = op.dw_blocks(inv_odd(y), bs)
+        return np.where(even, y - z, 0)
+
+    psi = np.zeros_like(rho)
+    r = rho.copy()
+    for _ in range(ncy):
+        for colour in (0, 1):
+            mask = (col == colour)[:, None, None]
+            rb = np.where(mask, r, 0)
+            rhat = np.where(even, rb - op.dw_blocks(inv_odd(rb), bs), 0)
+            chi_e = np.zeros_like(rb)
+            res = rhat
+            for _k in range(nmr):
+                v = np.where(mask, schur_b(res), 0)
+                num = _block_sum(np.sum(np.conj(v) * res, axis=(1, 2)), bid, nblk)
+                den = _block_sum(np.sum(np.abs(v) ** 2, axis=(1, 2)).astype(np.complex128), bid,
+                                 nblk).real
+                omega = np.where(den > 0, num / np.where(den > 0, den, 1.0), 0.0)
+                w = omega[bid][:, None, None]
+                chi_e = chi_e + w * res
+                res = res - w * v
+            chi_o = inv_odd(np.where(odd, rb - op.dw_blocks(chi_e, bs), 0))
+            psi = psi + np.where(mask, chi_e + chi_o, 0)
             r = rho - op.dw(psi)
     return psi
 
