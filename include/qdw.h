@@ -227,11 +227,14 @@ enum {
     QDW_PRECOND_SAP = 1,   /* Schwarz alternating procedure (Sec. 3)                          */
     QDW_PRECOND_NN = 2,    /* learned gauge-covariant network (not from the paper)            */
     QDW_PRECOND_NN_SAP = 3, /* network while it reduces the GCR residual, then SAP            */
-    QDW_PRECOND_SAP_ADAPTIVE = 4 /* adaptive SAP (Sec. 3.2): ncy and nmr are maxima; a cycle
+    QDW_PRECOND_SAP_ADAPTIVE = 4, /* adaptive SAP (Sec. 3.2): ncy and nmr are maxima; a cycle
                                     stops the application when it did not lower |rho|; a
                                     block's MR stops after >= 4 steps when |r_b| > sap_alpha
                                     times its previous value, when |r_b| grew, or when
                                     |r_b| < res |eta| / (number of blocks)                    */
+    QDW_PRECOND_SAP_EO = 5 /* SAP whose block problems are solved on their even-odd reduced
+                              form (as sap_eo_apply); nmr MR steps on the reduced block
+                              operator per block solve                                     */
 };
 
 /* Settings of the SAP-preconditioned flexible GCR (Sec. 3.1, Table 2). The large and the
@@ -343,6 +346,15 @@ size_t qdw_sap_workspace_bytes(const qdw_op* op, qdw_prec sdtype);
  * ncy = 0 copies rho. Errors: QDW_EBLOCK for an unsupported block size. */
 int sap_apply(qdw_op* op, const void* rho, void* phi, int ncy, int nmr, const int bs[4],
               qdw_prec sdtype, void* work, size_t work_bytes, void* stream);
+
+/* As sap_apply, with every block problem D_b chi = r_b solved through its even-odd
+ * reduction (the site-diagonal clover term A, the in-block hops between the parities):
+ * r^_e = r_e - D_eo A_oo^-1 r_o; nmr MR steps from 0 on the reduced block operator
+ * A_ee - D_eo A_oo^-1 D_oe give chi_e; chi_o = A_oo^-1 (r_o - D_oe chi_e), which leaves the
+ * odd half of the block residual at zero. Parity is the site's parity on the whole lattice.
+ * Same arguments, workspace and errors as sap_apply. */
+int sap_eo_apply(qdw_op* op, const void* rho, void* phi, int ncy, int nmr, const int bs[4],
+                 qdw_prec sdtype, void* work, size_t work_bytes, void* stream);
 
 #ifdef __cplusplus
 }

@@ -163,7 +163,7 @@ size_t precond_bytes(const qdw_op* op, const qdw_sap_gcr_params& p)
 {
     size_t b = 0;
     if (p.precond == QDW_PRECOND_SAP || p.precond == QDW_PRECOND_NN_SAP ||
-        p.precond == QDW_PRECOND_SAP_ADAPTIVE)
+        p.precond == QDW_PRECOND_SAP_ADAPTIVE || p.precond == QDW_PRECOND_SAP_EO)
         b = sap_workspace(op, p.sdtype);
     if (p.precond == QDW_PRECOND_NN || p.precond == QDW_PRECOND_NN_SAP)
         b = std::max(b, nn_precond_workspace(op));
@@ -198,7 +198,8 @@ int gcr_impl(qdw_op* op, const void* eta, void* psi, const qdw_sap_gcr_params& p
     BlockGeom B{};
     int rc;
     const bool adaptive = p.precond == QDW_PRECOND_SAP_ADAPTIVE;
-    if (p.precond == QDW_PRECOND_SAP || p.precond == QDW_PRECOND_NN_SAP || adaptive)
+    const bool sap_eo = p.precond == QDW_PRECOND_SAP_EO;
+    if (p.precond == QDW_PRECOND_SAP || p.precond == QDW_PRECOND_NN_SAP || adaptive || sap_eo)
         if ((rc = make_block_geom(g, p.bs, &B))) return rc;
 #define TRY(x) do { if ((rc = (x)) != QDW_OK) return rc; } while (0)
     info->status = 0;
@@ -230,8 +231,10 @@ int gcr_impl(qdw_op* op, const void* eta, void* psi, const qdw_sap_gcr_params& p
             bool use_nn = nn_ok;
             if (use_nn) {
                 TRY(nn_precondition(op, p.nn_weights, L.rho, L.phi[k], rn, L.pre, st));
-            } else if (p.precond == QDW_PRECOND_SAP || p.precond == QDW_PRECOND_NN_SAP) {
-                TRY(sap_run(op, L.rho, L.phi[k], rn, p.ncy, p.nmr, B, p.sdtype, L.pre, st));
+            } else if (p.precond == QDW_PRECOND_SAP || p.precond == QDW_PRECOND_NN_SAP ||
+                       sap_eo) {
+                TRY(sap_run(op, L.rho, L.phi[k], rn, p.ncy, p.nmr, B, p.sdtype, L.pre, st,
+                            sap_eo));
                 info->n_dw_lo += p.ncy * p.nmr;
             } else if (adaptive) {
                 // block tolerance: the solve's absolute target shared among the blocks
@@ -353,10 +356,10 @@ extern "C" int sap_gcr_solve(qdw_op* op, const void* eta, void* psi, const qdw_s
     QDW_CHECK(eta != psi, QDW_EINVAL, "sap_gcr_solve: eta and psi must be distinct");
     QDW_CHECK(p->nkv >= 1 && p->nkv <= kMaxKv, QDW_EINVAL, "sap_gcr_solve: need 1 <= nkv <= 16");
     QDW_CHECK(p->nmx >= 1 && p->res > 0.0, QDW_EINVAL, "sap_gcr_solve: need nmx >= 1, res > 0");
-    QDW_CHECK(p->precond >= QDW_PRECOND_NONE && p->precond <= QDW_PRECOND_SAP_ADAPTIVE, QDW_EINVAL,
+    QDW_CHECK(p->precond >= QDW_PRECOND_NONE && p->precond <= QDW_PRECOND_SAP_EO, QDW_EINVAL,
               "sap_gcr_solve: bad preconditioner");
     const bool sap = p->precond == QDW_PRECOND_SAP || p->precond == QDW_PRECOND_NN_SAP ||
-                     p->precond == QDW_PRECOND_SAP_ADAPTIVE;
+                     p->precond == QDW_PRECOND_SAP_ADAPTIVE || p->precond == QDW_PRECOND_SAP_EO;
     if (p->precond == QDW_PRECOND_SAP_ADAPTIVE)
         QDW_CHECK(p->sap_alpha > 0.0, QDW_EINVAL, "sap_gcr_solve: adaptive SAP needs sap_alpha > 0");
     if (sap) {

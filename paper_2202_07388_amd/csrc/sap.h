@@ -29,9 +29,10 @@ int make_block_geom(const Geom& g, const int bs[4], BlockGeom* B);
 
 size_t sap_workspace(const qdw_op* op, int sdtype);
 
-// phi = M_SAP rho (FP64 fields); |rho| must be passed in (it sets the storage scale)
+// phi = M_SAP rho (FP64 fields); |rho| must be passed in (it sets the storage scale);
+// eo: block solves through the block's even-odd reduction
 int sap_run(qdw_op* op, const void* rho, void* phi, double rho_norm, int ncy, int nmr,
-            const BlockGeom& B, int sdtype, char* work, hipStream_t st);
+            const BlockGeom& B, int sdtype, char* work, hipStream_t st, bool eo = false);
 
 // adaptive SAP (Sec. 3.2): at most ncy_max cycles (stop when a cycle did not lower |r|), at
 // most nmr_max MR steps per block with the exits of SapAdapt; tol is the absolute block
@@ -47,6 +48,7 @@ int sap_ctrl_reset_total(int* ctrl, hipStream_t st);
 // ncy Schwarz cycles on the storage-precision fields rs (residual, updated), psis
 // (solution, accumulated) and delta (scratch), for nrhs right-hand sides at bat's stride
 int sap_cycles(qdw_op* op, const BlockGeom& B, int sdtype, int ncy, int nmr, void* rs,
-               void* psis, void* delta, const RhsStride& bat, int nrhs, hipStream_t st);
+               void* psis, void* delta, const RhsStride& bat, int nrhs, hipStream_t st,
+               bool eo = false);
 
 }  // namespace qdw

@@ -273,6 +273,185 @@ __global__ __launch_bounds__(256) void sap_mr_kernel(Geom g, BlockGeom B, int co
     store_spinor<SP>(rs, g.Vh, par, i, r);
 }
 
+// The same block solve through the block's even-odd reduction: for the block residual
+// r = (r_e, r_o) (A = the clover term, H = the sum of the hops inside the block, so that
+// D_eo = D_oe = -1/2 H between the parities)
+//   r^_e  = r_e - D_eo A_oo^-1 r_o = r_e + 1/2 H A_oo^-1 r_o
+//   chi_e = nmr MR steps from 0 on D^_b = A_ee - 1/4 H A_oo^-1 H with source r^_e
+//   chi_o = A_oo^-1 (r_o - D_oe chi_e) = A_oo^-1 (r_o + 1/2 H chi_e)
+// after which the block residual is (the MR residual, 0). Even lanes hold A, odd lanes
+// A^-1 in registers; every application of H is one pass of the in-block hops over LDS.
+template <int SP>
+__global__ __launch_bounds__(256) void sap_mr_eo_kernel(Geom g, BlockGeom B, int colour, int nmr,
+                                                        void* __restrict__ rs,
+                                                        void* __restrict__ psis,
+                                                        void* __restrict__ delta,
+                                                        const void* __restrict__ links,
+                                                        const void* __restrict__ dets,
+                                                        const void* __restrict__ clover,
+                                                        const void* __restrict__ cloverinv,
+                                                        RhsStride bat)
+{
+    __shared__ float rl[24][kBMax];
+    __shared__ float hb[4][12][kBMax];
+    __shared__ double red[4][3];
+    if (bat.gate && !bat.gate[(long)blockIdx.y * bat.gstride]) return;
+    rs = (char*)rs + blockIdx.y * bat.fstride;
+    psis = (char*)psis + blockIdx.y * bat.fstride;
+    delta = (char*)delta + blockIdx.y * bat.fstride;
+    const int t = threadIdx.x;
+    const int nw = B.bvol >> 6;
+    int b[4];
+    {
+        int r = 2 * blockIdx.x;
+        b[3] = r % B.nb[3]; r /= B.nb[3];
+        b[2] = r % B.nb[2]; r /= B.nb[2];
+        b[1] = r % B.nb[1];
+        b[0] = r / B.nb[1];
+        if (((b[0] + b[1] + b[2] + b[3]) & 1) != colour) b[3] += 1;
+    }
+    int l[4];
+    {
+        int r = t;
+        l[3] = r % B.bs[3]; r /= B.bs[3];
+        l[2] = r % B.bs[2]; r /= B.bs[2];
+        l[1] = r % B.bs[1];
+        l[0] = r / B.bs[1];
+    }
+    int x[4];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) x[mu] = b[mu] * B.bs[mu] + l[mu];
+    const int lex = ((x[0] * g.L[1] + x[1]) * g.L[2] + x[2]) * g.L[3] + x[3];
+    const int par = (x[0] + x[1] + x[2] + x[3]) & 1;
+    const int i = lex >> 1;
+    const bool ev = par == 0;
+
+    cx<float> r[12];
+    load_spinor<SP>(rs, g.Vh, par, i, r);
+    float cl[72];  // A on even sites, A^-1 on odd sites
+    load_clover<SP>(ev ? clover : cloverinv, g.Vh, par, i, cl);
+    cx<float> u[4][6], d[4];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) load_link<SP>(links, dets, g.Vh, par, i, mu, u[mu], d[mu]);
+
+    auto diag = [&](const cx<float> v[12], cx<float> o[12]) {
+        herm6_apply<float>(cl, v, o);
+        herm6_apply<float>(cl + 36, v + 6, o + 6);
+    };
+    // vh = H src over the block (src: this lane's value; written to LDS here)
+    auto hops = [&](const cx<float> src[12], cx<float> vh[12]) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            rl[2 * c][t] = src[c].re;
+            rl[2 * c + 1][t] = src[c].im;
+        }
+        __syncthreads();  // rl holds src
+        push_backward<SP, 0>(hb, B, l, t, src, u[0], d[0]);
+        push_backward<SP, 1>(hb, B, l, t, src, u[1], d[1]);
+        push_backward<SP, 2>(hb, B, l, t, src, u[2], d[2]);
+        push_backward<SP, 3>(hb, B, l, t, src, u[3], d[3]);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) vh[c] = {0.f, 0.f};
+        hop_forward<SP, 0>(rl, B, l, t, u[0], d[0], vh);
+        hop_forward<SP, 1>(rl, B, l, t, u[1], d[1], vh);
+        hop_forward<SP, 2>(rl, B, l, t, u[2], d[2], vh);
+        hop_forward<SP, 3>(rl, B, l, t, u[3], d[3], vh);
+        __syncthreads();  // every pushed half spinor is in hb
+        hop_backward<0>(hb, l, t, vh);
+        hop_backward<1>(hb, l, t, vh);
+        hop_backward<2>(hb, l, t, vh);
+        hop_backward<3>(hb, l, t, vh);
+        __syncthreads();  // rl and hb are free again
+    };
+    const cx<float> z = {0.f, 0.f};
+    cx<float> w[12], vh[12], res[12], chi[12];
+    // (1) the reduced source
+    if (ev) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) w[c] = z;
+    } else {
+        diag(r, w);
+    }
+    hops(w, vh);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        res[c] = ev ? r[c] + scale(vh[c], 0.5f) : z;
+        chi[c] = z;
+    }
+    // (2) MR on the reduced block operator
+    for (int k = 0; k < nmr; ++k) {
+        hops(res, vh);  // odd lanes: H res
+        if (ev) {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) w[c] = z;
+        } else {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) vh[c] = scale(vh[c], -0.5f);
+            diag(vh, w);  // A^-1 D_oe res
+        }
+        hops(w, vh);  // even lanes: H A^-1 D_oe res
+        cx<float> v[12];
+        if (ev) {
+            diag(res, v);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) v[c] = v[c] + scale(vh[c], 0.5f);
+        } else {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) v[c] = z;
+        }
+        float nre = 0.f, nim = 0.f, den = 0.f;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            const cx<float> q = cmul_conj(v[c], res[c]);
+            nre += q.re;
+            nim += q.im;
+            den += v[c].re * v[c].re + v[c].im * v[c].im;
+        }
+        double a0 = nre, a1 = nim, a2 = den;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            a0 += __shfl_xor(a0, o, 64);
+            a1 += __shfl_xor(a1, o, 64);
+            a2 += __shfl_xor(a2, o, 64);
+        }
+        if ((t & 63) == 0) {
+            red[t >> 6][0] = a0;
+            red[t >> 6][1] = a1;
+            red[t >> 6][2] = a2;
+        }
+        __syncthreads();
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        for (int q = 0; q < nw; ++q) {
+            s0 += red[q][0];
+            s1 += red[q][1];
+            s2 += red[q][2];
+        }
+        const cx<float> om = s2 > 0.0 ? cx<float>{(float)(s0 / s2), (float)(s1 / s2)}
+                                      : cx<float>{0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            chi[c] = chi[c] + om * res[c];
+            res[c] = res[c] - om * v[c];
+        }
+        // red is rewritten only after the two barriers of the next step's first hops
+    }
+    // (3) the odd half of the block solution
+    hops(chi, vh);  // odd lanes: H chi_e
+    if (!ev) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) w[c] = r[c] + scale(vh[c], 0.5f);
+        diag(w, chi);
+    }
+    // (4) accumulate; the block residual is (res_e, 0)
+    cx<float> p[12];
+    load_spinor<SP>(psis, g.Vh, par, i, p);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) p[c] = p[c] + chi[c];
+    store_spinor<SP>(psis, g.Vh, par, i, p);
+    store_spinor<SP>(delta, g.Vh, par, i, chi);
+    store_spinor<SP>(rs, g.Vh, par, i, res);
+}
+
 // acc += the hops of D delta that enter x's block from outside (without the -1/2), for
 // a site x of a block of colour 1 - `colour` (delta lives on the colour blocks)
 template <int SP, int MU>
@@ -341,14 +520,20 @@ __global__ __launch_bounds__(256) void sap_boundary_kernel(Geom g, BlockGeom B, 
 
 template <int SP>
 int cycles_impl(qdw_op* op, const BlockGeom& B, int ncy, int nmr, void* rs, void* psis,
-                void* delta, const RhsStride& bat, int nrhs, hipStream_t st)
+                void* delta, const RhsStride& bat, int nrhs, bool eo, hipStream_t st)
 {
     const Geom& g = op->g;
     const dim3 gmr(B.nblk / 2, nrhs), gbd(walk_blocks(g), nrhs);
     for (int cy = 0; cy < ncy; ++cy)
         for (int c = 0; c < 2; ++c) {
-            sap_mr_kernel<SP><<<gmr, B.bvol, 0, st>>>(g, B, c, nmr, rs, psis, delta, op->links[SP],
-                                                      op->det[SP], op->clover[SP], bat, SapAdapt{});
+            if (eo)
+                sap_mr_eo_kernel<SP><<<gmr, B.bvol, 0, st>>>(g, B, c, nmr, rs, psis, delta,
+                                                             op->links[SP], op->det[SP],
+                                                             op->clover[SP], op->cloverinv[SP], bat);
+            else
+                sap_mr_kernel<SP><<<gmr, B.bvol, 0, st>>>(g, B, c, nmr, rs, psis, delta,
+                                                          op->links[SP], op->det[SP],
+                                                          op->clover[SP], bat, SapAdapt{});
             QDW_LAUNCH_CHECK();
             sap_boundary_kernel<SP><<<gbd, 2 * g.ts, 0, st>>>(g, B, c, rs, delta, op->links[SP],
                                                               op->det[SP], bat);
@@ -359,7 +544,7 @@ int cycles_impl(qdw_op* op, const BlockGeom& B, int ncy, int nmr, void* rs, void
 
 template <int SP>
 int sap_impl(qdw_op* op, const void* rho, void* phi, double rho_norm, int ncy, int nmr,
-             const BlockGeom& B, char* work, hipStream_t st)
+             const BlockGeom& B, char* work, bool eo, hipStream_t st)
 {
     const Geom& g = op->g;
     const size_t fb = spinor_bytes(g, SP);
@@ -374,7 +559,7 @@ int sap_impl(qdw_op* op, const void* rho, void* phi, double rho_norm, int ncy, i
     const double s = std::sqrt(24.0 * g.V) / rho_norm;
     if ((rc = run_map(op, ScaleNorm<F64, SP>{rho, rs, s, g.Vh}, st, op->scalars + S_SAP))) return rc;
     if ((rc = run_map(op, Zero<SP>{psis, g.Vh}, st))) return rc;
-    if ((rc = sap_cycles(op, B, SP, ncy, nmr, rs, psis, delta, RhsStride{}, 1, st))) return rc;
+    if ((rc = sap_cycles(op, B, SP, ncy, nmr, rs, psis, delta, RhsStride{}, 1, st, eo))) return rc;
     return run_map(op, Axpby<SP, F64>{psis, phi, 1.0 / s, 0.0, g.Vh}, st);
 }
 
@@ -468,12 +653,12 @@ int sap_ctrl_reset_total(int* ctrl, hipStream_t st)
 }
 
 int sap_cycles(qdw_op* op, const BlockGeom& B, int sdtype, int ncy, int nmr, void* rs,
-               void* psis, void* delta, const RhsStride& bat, int nrhs, hipStream_t st)
+               void* psis, void* delta, const RhsStride& bat, int nrhs, hipStream_t st, bool eo)
 {
     switch (sdtype) {
-    case F32: return cycles_impl<F32>(op, B, ncy, nmr, rs, psis, delta, bat, nrhs, st);
-    case F16S: return cycles_impl<F16S>(op, B, ncy, nmr, rs, psis, delta, bat, nrhs, st);
-    case BF16S: return cycles_impl<BF16S>(op, B, ncy, nmr, rs, psis, delta, bat, nrhs, st);
+    case F32: return cycles_impl<F32>(op, B, ncy, nmr, rs, psis, delta, bat, nrhs, eo, st);
+    case F16S: return cycles_impl<F16S>(op, B, ncy, nmr, rs, psis, delta, bat, nrhs, eo, st);
+    case BF16S: return cycles_impl<BF16S>(op, B, ncy, nmr, rs, psis, delta, bat, nrhs, eo, st);
     default: QDW_CHECK(false, QDW_EINVAL, "SAP: sdtype must be QDW_F32, QDW_F16S or QDW_BF16S");
     }
 }
@@ -481,12 +666,12 @@ int sap_cycles(qdw_op* op, const BlockGeom& B, int sdtype, int ncy, int nmr, voi
 size_t sap_workspace(const qdw_op* op, int sdtype) { return 3 * spinor_bytes(op->g, sdtype) + 256; }
 
 int sap_run(qdw_op* op, const void* rho, void* phi, double rho_norm, int ncy, int nmr,
-            const BlockGeom& B, int sdtype, char* work, hipStream_t st)
+            const BlockGeom& B, int sdtype, char* work, hipStream_t st, bool eo)
 {
     switch (sdtype) {
-    case F32: return sap_impl<F32>(op, rho, phi, rho_norm, ncy, nmr, B, work, st);
-    case F16S: return sap_impl<F16S>(op, rho, phi, rho_norm, ncy, nmr, B, work, st);
-    case BF16S: return sap_impl<BF16S>(op, rho, phi, rho_norm, ncy, nmr, B, work, st);
+    case F32: return sap_impl<F32>(op, rho, phi, rho_norm, ncy, nmr, B, work, eo, st);
+    case F16S: return sap_impl<F16S>(op, rho, phi, rho_norm, ncy, nmr, B, work, eo, st);
+    case BF16S: return sap_impl<BF16S>(op, rho, phi, rho_norm, ncy, nmr, B, work, eo, st);
     default: QDW_CHECK(false, QDW_EINVAL, "SAP: sdtype must be QDW_F32, QDW_F16S or QDW_BF16S");
     }
 }
@@ -501,16 +686,20 @@ extern "C" size_t qdw_sap_workspace_bytes(const qdw_op* op, qdw_prec sdtype)
     return sap_workspace(op, sdtype);
 }
 
-extern "C" int sap_apply(qdw_op* op, const void* rho, void* phi, int ncy, int nmr, const int bs[4],
-                         qdw_prec sdtype, void* work, size_t work_bytes, void* stream)
+namespace {
+
+int sap_apply_impl(const char* fn, qdw_op* op, const void* rho, void* phi, int ncy, int nmr,
+                   const int bs[4], qdw_prec sdtype, void* work, size_t work_bytes,
+                   void* stream, bool eo)
 {
-    QDW_CHECK(op && rho && phi && bs && work, QDW_EINVAL, "sap_apply: null argument");
-    QDW_CHECK(rho != phi, QDW_EINVAL, "sap_apply: rho and phi must be distinct");
-    QDW_CHECK(ncy >= 0 && nmr >= 0, QDW_EINVAL, "sap_apply: ncy and nmr must be >= 0");
+    const std::string f(fn);
+    QDW_CHECK(op && rho && phi && bs && work, QDW_EINVAL, f + ": null argument");
+    QDW_CHECK(rho != phi, QDW_EINVAL, f + ": rho and phi must be distinct");
+    QDW_CHECK(ncy >= 0 && nmr >= 0, QDW_EINVAL, f + ": ncy and nmr must be >= 0");
     QDW_CHECK(sdtype >= QDW_F32 && sdtype <= QDW_BF16S, QDW_EINVAL,
-              "sap_apply: sdtype must be QDW_F32, QDW_F16S or QDW_BF16S");
+              f + ": sdtype must be QDW_F32, QDW_F16S or QDW_BF16S");
     QDW_CHECK(work_bytes >= sap_workspace(op, sdtype), QDW_EWORKSPACE,
-              "sap_apply: workspace smaller than qdw_sap_workspace_bytes()");
+              f + ": workspace smaller than qdw_sap_workspace_bytes()");
     BlockGeom B;
     int rc = make_block_geom(op->g, bs, &B);
     if (rc) return rc;
@@ -519,7 +708,24 @@ extern "C" int sap_apply(qdw_op* op, const void* rho, void* phi, int ncy, int nm
     double n2;
     if ((rc = read_scalars(op, S_TMP, 1, &n2, st))) return rc;
     char* wk = (char*)(((uintptr_t)work + 255) & ~(uintptr_t)255);
-    return sap_run(op, rho, phi, std::sqrt(n2), ncy, nmr, B, sdtype, wk, st);
+    return sap_run(op, rho, phi, std::sqrt(n2), ncy, nmr, B, sdtype, wk, st, eo);
+}
+
+}  // namespace
+
+extern "C" int sap_apply(qdw_op* op, const void* rho, void* phi, int ncy, int nmr, const int bs[4],
+                         qdw_prec sdtype, void* work, size_t work_bytes, void* stream)
+{
+    return sap_apply_impl("sap_apply", op, rho, phi, ncy, nmr, bs, sdtype, work, work_bytes,
+                          stream, false);
+}
+
+extern "C" int sap_eo_apply(qdw_op* op, const void* rho, void* phi, int ncy, int nmr,
+                            const int bs[4], qdw_prec sdtype, void* work, size_t work_bytes,
+                            void* stream)
+{
+    return sap_apply_impl("sap_eo_apply", op, rho, phi, ncy, nmr, bs, sdtype, work, work_bytes,
+                          stream, true);
 }
 
 extern "C" int sap_adaptive_apply(qdw_op* op, const void* rho, void* phi, int ncy_max, int nmr_max,

@@ -95,7 +95,7 @@ class SapGcrParams(ctypes.Structure):
                 ("nn_weights", ctypes.c_void_p), ("sap_alpha", ctypes.c_double)]
 
 
-PRECOND = {"none": 0, "sap": 1, "nn": 2, "nn_sap": 3, "sap_adaptive": 4}
+PRECOND = {"none": 0, "sap": 1, "nn": 2, "nn_sap": 3, "sap_adaptive": 4, "sap_eo": 5}
 
 _OPTIONAL: list = [
     ("qdw_sap_gcr_workspace_bytes", [_P, ctypes.POINTER(SapGcrParams)], ctypes.c_size_t),
@@ -107,6 +107,8 @@ _OPTIONAL: list = [
                             ctypes.c_size_t, ctypes.POINTER(ctypes.c_int), _P, _P], ctypes.c_int),
     ("sap_apply", [_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int * 4),
                    ctypes.c_int, _P, ctypes.c_size_t, _P], ctypes.c_int),
+    ("sap_eo_apply", [_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int * 4),
+                      ctypes.c_int, _P, ctypes.c_size_t, _P], ctypes.c_int),
     ("qdw_axpby", [_P, ctypes.c_double, _P, ctypes.c_double, _P, ctypes.c_int, _P], ctypes.c_int),
     ("qdw_norm2", [_P, _P, ctypes.c_int, ctypes.POINTER(ctypes.c_double), _P], ctypes.c_int),
     ("qdw_cdot", [_P, _P, _P, ctypes.c_int, ctypes.POINTER(ctypes.c_double * 2), _P],
@@ -411,16 +413,18 @@ def sap_adaptive_apply(op: Op, rho, phi, ncy_max: int = 20, nmr_max: int = 20,
 
 
 def sap_apply(op: Op, rho, phi, ncy: int = 5, nmr: int = 4, bs=(4, 4, 4, 4),
-              sdtype: str = "f16"):
-    """phi = M_SAP rho (FP64 eo-SoA fields)."""
+              sdtype: str = "f16", eo: bool = False):
+    """phi = M_SAP rho (FP64 eo-SoA fields); eo=True solves the blocks through their
+    even-odd reduction (sap_eo_apply)."""
     L = load()
     nb = int(L.qdw_sap_workspace_bytes(op.handle, PREC[sdtype]))
     if nb == 0:
         raise QdwError("bad SAP storage precision")
     ws = _workspace(op, nb)
     b = (ctypes.c_int * 4)(*bs)
-    _check(L.sap_apply(op.handle, _ptr(rho), _ptr(phi), ncy, nmr, ctypes.byref(b),
-                       PREC[sdtype], _ptr(ws), ws.numel(), _stream()), "sap_apply")
+    fn, name = (L.sap_eo_apply, "sap_eo_apply") if eo else (L.sap_apply, "sap_apply")
+    _check(fn(op.handle, _ptr(rho), _ptr(phi), ncy, nmr, ctypes.byref(b), PREC[sdtype],
+              _ptr(ws), ws.numel(), _stream()), name)
     return phi
 
 
