@@ -13,8 +13,9 @@ Also reported, each timed on its own outside the K steps:
     -> FP64 precision cascade; and the even-odd reduced normal equations D^+ D^ psi_e =
     eta_e (FP64 and FP32 inner), which the solver of the full equations is compared with;
   * the 24^3 x 48 solve of D psi = eta to 1e-10 (eps = 0.35, m0 = -0.08): plain FP64 GCR
-    against SAP-preconditioned GCR (4^4 blocks, 5 cycles, 4 MR steps, FP16 and FP32) and
-    adaptive SAP (at most 20 cycles and 20 MR steps, alpha 0.9 and 0.7, FP16);
+    against SAP-preconditioned GCR (4^4 blocks, 5 cycles, 4 MR steps, FP16 and FP32), the
+    same with even-odd reduced block solves (FP16) and adaptive SAP (at most 20 cycles and
+    20 MR steps, alpha 0.9 and 0.7, FP16);
   * the learned preconditioner: trained on the GPU on 2000 residual/error pairs from
     plain FP64 GCR solves on four 16^3 x 32 fields (eps = 0.3, m0 = -0.05), then used as
     the flexible-GCR preconditioner on the 32^3 x 64 field against SAP-GCR and plain GCR,
@@ -52,7 +53,7 @@ SAP_M0, SAP_EPS, SAP_SEED = -0.08, 0.35, 7388 + 20
 # D-kernel shapes (ts, nt, pipe, walk, march) at 32^3 x 64, as the autotuner picks them on
 # MI355X (profiles/dw_autotune_32c64.md); pinned so that a kernel trace of this script
 # holds only the timed shape's launches (--autotune picks them live)
-PINNED_SHAPES = {"f64": (64, 16, 1, 0, 1), "f32": (128, 16, 1, 0, 1), "f16": (64, 2, 0, 0, 0)}
+PINNED_SHAPES = {"f64": (64, 32, 0, 0, 1), "f32": (128, 16, 1, 0, 1), "f16": (64, 2, 0, 0, 0)}
 # algorithmic bytes per site of one application of D (each datum read once)
 BYTES_PER_SITE = {"f64": 1376, "f32": 688, "f16": 344}
 # HBM traffic measured with rocprofv3 counters for the FP64 kernel (profiles/); reported
@@ -155,6 +156,7 @@ def gcr_solves(qdw, syn):
     for name, kw in (("plain_fp64", dict(base, precond="none")),
                      ("sap_fp16", dict(base, precond="sap", sdtype="f16")),
                      ("sap_fp32", dict(base, precond="sap", sdtype="f32")),
+                     ("sap_eo_fp16", dict(base, precond="sap_eo", sdtype="f16")),
                      ("sap_adaptive_fp16_alpha0.9", dict(adaptive, alpha=0.9)),
                      ("sap_adaptive_fp16_alpha0.7", dict(adaptive, alpha=0.7))):
         x = op.new_field("f64")

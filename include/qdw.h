@@ -124,7 +124,7 @@ int dw_apply_multi(qdw_op* op, const void* const* in, void* const* out, int nrhs
                    qdw_prec prec, void* stream);
 
 /* Autotuner of the D kernel for this operator (not from the paper): times every shape --
- * workgroup size (64 or 128 sites per parity), walk chunk (1, 2, 4, 8 or 16 time slices,
+ * workgroup size (64 or 128 sites per parity), walk chunk (1, 2, 4, ..., 64 time slices,
  * dividing T), hop-loop form (plain or software-pipelined), tile order (walk 0: tiles of a
  * time slice in index order; 1: x1 slabs innermost, so the x1 neighbours of a tile are
  * loaded by nearby workgroups) and form (march 0: one workgroup per tile and slice; 1: a
@@ -139,7 +139,7 @@ int dw_apply_multi(qdw_op* op, const void* const* in, void* const* out, int nrhs
  * may differ in the last bit. */
 int qdw_autotune(qdw_op* op, qdw_prec prec, int nrhs, char* report, size_t report_len,
                  void* stream);
-/* Set / read the D kernel's shape for precision prec by hand (ts 64 or 128, nt in 1..16
+/* Set / read the D kernel's shape for precision prec by hand (ts 64 or 128, nt in 1..64
  * dividing T, pipe 0 or 1, walk 0 or 1, march 0 or 1; shape5 = {ts, nt, pipe, walk,
  * march}); QDW_EINVAL for anything else. */
 int qdw_set_dw_shape(qdw_op* op, qdw_prec prec, int ts, int nt, int pipe, int walk, int march);

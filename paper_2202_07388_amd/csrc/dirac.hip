@@ -592,8 +592,8 @@ int check_shape(const qdw_op* op, int prec, int ts, int nt, int pipe, int walk, 
               "than 64 KB of LDS");
     QDW_CHECK(march == 0 || march == 1, QDW_EINVAL, "D kernel shape: march must be 0 or 1");
     QDW_CHECK(ts == 64 || ts == 128, QDW_EINVAL, "D kernel shape: ts must be 64 or 128");
-    QDW_CHECK(nt >= 1 && nt <= 16 && op->g.L[0] % nt == 0, QDW_EINVAL,
-              "D kernel shape: nt must divide T and lie in 1..16");
+    QDW_CHECK(nt >= 1 && nt <= 64 && op->g.L[0] % nt == 0, QDW_EINVAL,
+              "D kernel shape: nt must divide T and lie in 1..64");
     QDW_CHECK(pipe == 0 || pipe == 1, QDW_EINVAL, "D kernel shape: pipe must be 0 or 1");
     QDW_CHECK(walk == 0 || walk == 1, QDW_EINVAL, "D kernel shape: walk must be 0 or 1");
     return QDW_OK;
@@ -646,7 +646,7 @@ extern "C" int qdw_autotune(qdw_op* op, qdw_prec prec, int nrhs, char* report, s
     for (int march = 0; march < 2; ++march)
         for (int walk = 0; walk < 2; ++walk)
             for (int ts : {64, 128})
-                for (int nt = 1; nt <= 16; nt *= 2) {
+                for (int nt = 1; nt <= 64; nt *= 2) {
                     if (g.L[0] % nt) continue;
                     if (march && march_lds(prec, ts) > 65536) continue;
                     for (int pipe = 0; pipe < 2; ++pipe)

@@ -35,7 +35,7 @@ struct Geom {
     int S;         // even-odd sites per time slice and parity (L1*L2*L3/2)
     int ts;        // sites per parity of a site-kernel workgroup (64 or 128; 2*ts lanes)
     int ntile;     // workgroups per time slice
-    int nt;        // time slices per chunk of the workgroup walk (a divisor of T, <= 16)
+    int nt;        // time slices per chunk of the workgroup walk (a divisor of T, <= 64)
     int walk;      // workgroup order within a chunk (walk_site)
     int slab;      // even-odd sites per parity of one x1 slab of a time slice (L2*L3/2)
     int tps;       // ts-site tiles per slab (walk 1)
