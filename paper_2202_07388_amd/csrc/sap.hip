@@ -95,6 +95,141 @@ __device__ __forceinline__ void hop_backward(float (*hb)[12][kBMax], const int l
     }
 }
 
+// The lane's clover blocks (or their inverses) and its four forward links, held in
+// registers through all MR steps of a block: as FP32 values for FP32 storage, and as the
+// stored 16-bit values for FP16 / BF16 storage (half the registers, which lets two
+// workgroups share a CU), widened to FP32 where they are used (exactly). opaque() hides the
+// stored values from the optimiser, so that the widening is redone after each call rather
+// than hoisted out of the loop into registers held for the whole kernel.
+template <int SP, bool PACKED = (SP == F16S || SP == BF16S)>
+struct SiteOps {
+    float cl[72];
+    cx<float> u[4][6], d[4];
+    __device__ __forceinline__ void load(const Geom& g, const void* clover, const void* links,
+                                         const void* dets, int par, int i)
+    {
+        load_clover<SP>(clover, g.Vh, par, i, cl);
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) load_link<SP>(links, dets, g.Vh, par, i, mu, u[mu], d[mu]);
+    }
+    __device__ __forceinline__ void opaque() {}
+    template <int MU>
+    __device__ __forceinline__ void link(cx<float> uu[6], cx<float>& dd) const
+    {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) uu[c] = u[MU][c];
+        dd = d[MU];
+    }
+    // o = A v (both chirality blocks)
+    __device__ __forceinline__ void diag(const cx<float> v[12], cx<float> o[12]) const
+    {
+        herm6_apply<float>(cl, v, o);
+        herm6_apply<float>(cl + 36, v + 6, o + 6);
+    }
+};
+
+template <int SP>
+struct SiteOps<SP, true> {
+    uint32_t cl[36];    // the 72 stored 16-bit clover values, two per register
+    uint32_t lk[4][7];  // per link: rows 0, 1 (12 values) and det U (2 values)
+    __device__ __forceinline__ static float widen(uint32_t w, int hi)
+    {
+        const uint16_t b = hi ? (uint16_t)(w >> 16) : (uint16_t)(w & 0xFFFFu);
+        if constexpr (SP == F16S) {
+            _Float16 h;
+            __builtin_memcpy(&h, &b, 2);
+            return (float)h;
+        } else {
+            return bf16_to_float(b);
+        }
+    }
+    __device__ __forceinline__ void load(const Geom& g, const void* clover, const void* links,
+                                         const void* dets, int par, int i)
+    {
+        const long base = chunk_at(g.Vh, Traits<SP>::CLOVER_CHUNKS, par, 0, i);
+#pragma unroll
+        for (int k = 0; k < Traits<SP>::CLOVER_CHUNKS; ++k) {
+            const Chunk<SP> c = load_chunk<SP>(clover, base + (long)k * kSB);
+            __builtin_memcpy(cl + 4 * k, &c, 16);
+        }
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            const long row = (long)(par * 4 + mu);
+            const Chunk<SP> c0 = load_chunk_cached<SP>(links, chunk_at(g.Vh, 2, row, 0, i));
+            const Chunk<SP> c1 = load_chunk_cached<SP>(links, chunk_at(g.Vh, 2, row, 1, i));
+            uint32_t w1[4];
+            __builtin_memcpy(lk[mu], &c0, 16);
+            __builtin_memcpy(w1, &c1, 16);
+            lk[mu][4] = w1[0];
+            lk[mu][5] = w1[1];
+            lk[mu][6] = w1[2];
+        }
+        (void)dets;
+    }
+    __device__ __forceinline__ void opaque()
+    {
+#pragma unroll
+        for (int k = 0; k < 36; ++k) asm volatile("" : "+v"(cl[k]));
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+            for (int k = 0; k < 7; ++k) asm volatile("" : "+v"(lk[mu][k]));
+    }
+    template <int MU>
+    __device__ __forceinline__ void link(cx<float> uu[6], cx<float>& dd) const
+    {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) uu[c] = {widen(lk[MU][c], 0), widen(lk[MU][c], 1)};
+        dd = {widen(lk[MU][6], 0), widen(lk[MU][6], 1)};
+    }
+    __device__ __forceinline__ void diag(const cx<float> v[12], cx<float> o[12]) const
+    {
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            float a[36];
+#pragma unroll
+            for (int k = 0; k < 36; ++k) a[k] = widen(cl[(36 * b + k) >> 1], (36 * b + k) & 1);
+            herm6_apply<float>(a, v + 6 * b, o + 6 * b);
+        }
+    }
+};
+
+// the four in-block hand-overs from this lane's site, then (after a barrier) the four
+// in-block forward hops into it; the caller adds the backward hops after the barrier
+template <int SP>
+__device__ __forceinline__ void push_all(float (*hb)[12][kBMax], const BlockGeom& B,
+                                         const int l[4], int t, const cx<float> src[12],
+                                         SiteOps<SP>& so)
+{
+    cx<float> u[6], d;
+    so.opaque();
+    so.template link<0>(u, d);
+    push_backward<SP, 0>(hb, B, l, t, src, u, d);
+    so.template link<1>(u, d);
+    push_backward<SP, 1>(hb, B, l, t, src, u, d);
+    so.template link<2>(u, d);
+    push_backward<SP, 2>(hb, B, l, t, src, u, d);
+    so.template link<3>(u, d);
+    push_backward<SP, 3>(hb, B, l, t, src, u, d);
+}
+
+template <int SP>
+__device__ __forceinline__ void forward_all(float (*rl)[kBMax], const BlockGeom& B,
+                                            const int l[4], int t, SiteOps<SP>& so,
+                                            cx<float> vh[12])
+{
+    cx<float> u[6], d;
+    so.opaque();
+    so.template link<0>(u, d);
+    hop_forward<SP, 0>(rl, B, l, t, u, d, vh);
+    so.template link<1>(u, d);
+    hop_forward<SP, 1>(rl, B, l, t, u, d, vh);
+    so.template link<2>(u, d);
+    hop_forward<SP, 2>(rl, B, l, t, u, d, vh);
+    so.template link<3>(u, d);
+    hop_forward<SP, 3>(rl, B, l, t, u, d, vh);
+}
+
 // sum over the block of a per-lane value (one FP64 result, the same in every lane);
 // `slots` must not be read by any lane between the barrier inside and the next barrier
 __device__ __forceinline__ double block_sum(double v, double* slots, int t, int nw)
@@ -108,8 +243,10 @@ __device__ __forceinline__ double block_sum(double v, double* slots, int t, int 
     return s;
 }
 
+// 16-bit storage: registers for two waves per SIMD (two 256-site blocks per CU)
 template <int SP>
-__global__ __launch_bounds__(256) void sap_mr_kernel(Geom g, BlockGeom B, int colour, int nmr,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SP == F32 ? 1 : 2)))
+void sap_mr_kernel(Geom g, BlockGeom B, int colour, int nmr,
                                                      void* __restrict__ rs, void* __restrict__ psis,
                                                      void* __restrict__ delta,
                                                      const void* __restrict__ links,
@@ -155,11 +292,8 @@ __global__ __launch_bounds__(256) void sap_mr_kernel(Geom g, BlockGeom B, int co
 
     cx<float> r[12], chi[12];
     load_spinor<SP>(rs, g.Vh, par, i, r);
-    float cl[72];
-    load_clover<SP>(clover, g.Vh, par, i, cl);
-    cx<float> u[4][6], d[4];
-#pragma unroll
-    for (int mu = 0; mu < 4; ++mu) load_link<SP>(links, dets, g.Vh, par, i, mu, u[mu], d[mu]);
+    SiteOps<SP> so;
+    so.load(g, clover, links, dets, par, i);
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
         chi[c] = {0.f, 0.f};
@@ -180,25 +314,19 @@ __global__ __launch_bounds__(256) void sap_mr_kernel(Geom g, BlockGeom B, int co
     }
     for (int k = 0; k < nmr && go; ++k) {
         __syncthreads();  // rl holds the current block residual
-        push_backward<SP, 0>(hb, B, l, t, r, u[0], d[0]);
-        push_backward<SP, 1>(hb, B, l, t, r, u[1], d[1]);
-        push_backward<SP, 2>(hb, B, l, t, r, u[2], d[2]);
-        push_backward<SP, 3>(hb, B, l, t, r, u[3], d[3]);
+        push_all<SP>(hb, B, l, t, r, so);
         cx<float> v[12], vh[12];
 #pragma unroll
         for (int c = 0; c < 12; ++c) vh[c] = {0.f, 0.f};
-        hop_forward<SP, 0>(rl, B, l, t, u[0], d[0], vh);
-        hop_forward<SP, 1>(rl, B, l, t, u[1], d[1], vh);
-        hop_forward<SP, 2>(rl, B, l, t, u[2], d[2], vh);
-        hop_forward<SP, 3>(rl, B, l, t, u[3], d[3], vh);
+        forward_all<SP>(rl, B, l, t, so, vh);
         __syncthreads();  // every pushed half spinor is in hb
         hop_backward<0>(hb, l, t, vh);
         hop_backward<1>(hb, l, t, vh);
         hop_backward<2>(hb, l, t, vh);
         hop_backward<3>(hb, l, t, vh);
         // v = D_b r = A r - 1/2 (hops inside the block)
-        herm6_apply<float>(cl, r, v);
-        herm6_apply<float>(cl + 36, r + 6, v + 6);
+        so.opaque();
+        so.diag(r, v);
 #pragma unroll
         for (int c = 0; c < 12; ++c) v[c] = v[c] - scale(vh[c], 0.5f);
         // omega = (v, r) / (v, v) over the block
@@ -282,7 +410,8 @@ __global__ __launch_bounds__(256) void sap_mr_kernel(Geom g, BlockGeom B, int co
 // after which the block residual is (the MR residual, 0). Even lanes hold A, odd lanes
 // A^-1 in registers; every application of H is one pass of the in-block hops over LDS.
 template <int SP>
-__global__ __launch_bounds__(256) void sap_mr_eo_kernel(Geom g, BlockGeom B, int colour, int nmr,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SP == F32 ? 1 : 2)))
+void sap_mr_eo_kernel(Geom g, BlockGeom B, int colour, int nmr,
                                                         void* __restrict__ rs,
                                                         void* __restrict__ psis,
                                                         void* __restrict__ delta,
@@ -328,15 +457,12 @@ __global__ __launch_bounds__(256) void sap_mr_eo_kernel(Geom g, BlockGeom B, int
 
     cx<float> r[12];
     load_spinor<SP>(rs, g.Vh, par, i, r);
-    float cl[72];  // A on even sites, A^-1 on odd sites
-    load_clover<SP>(ev ? clover : cloverinv, g.Vh, par, i, cl);
-    cx<float> u[4][6], d[4];
-#pragma unroll
-    for (int mu = 0; mu < 4; ++mu) load_link<SP>(links, dets, g.Vh, par, i, mu, u[mu], d[mu]);
+    SiteOps<SP> so;  // A on even sites, A^-1 on odd sites
+    so.load(g, ev ? clover : cloverinv, links, dets, par, i);
 
     auto diag = [&](const cx<float> v[12], cx<float> o[12]) {
-        herm6_apply<float>(cl, v, o);
-        herm6_apply<float>(cl + 36, v + 6, o + 6);
+        so.opaque();
+        so.diag(v, o);
     };
     // vh = H src over the block (src: this lane's value; written to LDS here)
     auto hops = [&](const cx<float> src[12], cx<float> vh[12]) {
@@ -346,16 +472,10 @@ __global__ __launch_bounds__(256) void sap_mr_eo_kernel(Geom g, BlockGeom B, int
             rl[2 * c + 1][t] = src[c].im;
         }
         __syncthreads();  // rl holds src
-        push_backward<SP, 0>(hb, B, l, t, src, u[0], d[0]);
-        push_backward<SP, 1>(hb, B, l, t, src, u[1], d[1]);
-        push_backward<SP, 2>(hb, B, l, t, src, u[2], d[2]);
-        push_backward<SP, 3>(hb, B, l, t, src, u[3], d[3]);
+        push_all<SP>(hb, B, l, t, src, so);
 #pragma unroll
         for (int c = 0; c < 12; ++c) vh[c] = {0.f, 0.f};
-        hop_forward<SP, 0>(rl, B, l, t, u[0], d[0], vh);
-        hop_forward<SP, 1>(rl, B, l, t, u[1], d[1], vh);
-        hop_forward<SP, 2>(rl, B, l, t, u[2], d[2], vh);
-        hop_forward<SP, 3>(rl, B, l, t, u[3], d[3], vh);
+        forward_all<SP>(rl, B, l, t, so, vh);
         __syncthreads();  // every pushed half spinor is in hb
         hop_backward<0>(hb, l, t, vh);
         hop_backward<1>(hb, l, t, vh);
