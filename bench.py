@@ -11,7 +11,8 @@ Also reported, each timed on its own outside the K steps:
   * the 32^3 x 64 normal-equation solve to FP64 true residual 1e-10: plain FP64 CG
     against FP32, FP16 and BF16 regular steps with FP64 reset steps, and the BF16 -> FP32
     -> FP64 precision cascade; and the even-odd reduced normal equations D^+ D^ psi_e =
-    eta_e (FP64 and FP32 inner), which the solver of the full equations is compared with;
+    eta_e (FP64, FP32 and FP16 inner, and the cascade), which the solver of the full
+    equations is compared with;
   * the 24^3 x 48 solve of D psi = eta to 1e-10 (eps = 0.35, m0 = -0.08): plain FP64 GCR
     against SAP-preconditioned GCR (4^4 blocks, 5 cycles, 4 MR steps, FP16 and FP32), the
     same with even-odd reduced block solves (FP16) and adaptive SAP (at most 20 cycles and
@@ -136,7 +137,9 @@ def cgne_solves(op, qdw, psi):
                      ("f16", dict(inner="f16")), ("bf16", dict(inner="bf16")),
                      ("cascade_bf16_f32_f64", dict(cascade=True)),
                      ("schur_f64", dict(inner="f64", schur=True)),
-                     ("schur_f32", dict(inner="f32", schur=True))):
+                     ("schur_f32", dict(inner="f32", schur=True)),
+                     ("schur_f16", dict(inner="f16", schur=True)),
+                     ("schur_cascade_bf16_f32_f64", dict(cascade=True, schur=True))):
         x = op.new_field("f64")
         info = qdw.cgne_solve(op, eta, x, res=1e-10, nmx=20000, **kw)
         out[name] = solve_record(info)
