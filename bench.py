@@ -153,7 +153,7 @@ def gcr_solves(qdw, syn):
     op = qdw.Op(SAP_DIMS, su3, th, SAP_M0, CSW, -1)
     del su3, th
     eta = op.pack(syn.gaussian_spinor(SAP_DIMS, SAP_SEED + 1000), "f64")
-    out = {}
+    out = {"dw_shape": qdw.autotune(op, "f64", 1).split(";")[0]}  # the outer FP64 D
     base = dict(ncy=5, nmr=4)
     adaptive = dict(precond="sap_adaptive", sdtype="f16", ncy=20, nmr=20)
     for name, kw in (("plain_fp64", dict(base, precond="none")),

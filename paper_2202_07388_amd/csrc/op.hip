@@ -490,6 +490,20 @@ extern "C" int qdw_create(const qdw_lattice* lat, const double* su3, const doubl
         op->dw_shape[p].walk = 0;
         op->dw_shape[p].march = 0;
     }
+    {
+        // FP64 and FP32: the marching form on 64-site tiles, with the longest walk chunk
+        // (at most 32 slices, dividing T) that still gives 512 workgroups, two per CU, so
+        // that they march side by side in one round
+        const int ntile = (g.S + 63) / 64;
+        int nt = 1;
+        for (int d = 32; d >= 1; d /= 2)
+            if (L[0] % d == 0 && (long)(L[0] / d) * ntile >= 512) {
+                nt = d;
+                break;
+            }
+        op->dw_shape[F64] = {64, nt, 0, 0, 1};
+        op->dw_shape[F32] = {64, nt, 1, 0, 1};
+    }
     op->m0 = m0;
     op->csw = csw;
     (void)hipGetDevice(&op->device);
