@@ -56,6 +56,18 @@ __device__ __forceinline__ long pidx(long Mp, long m, int k)
     return (((long)(k >> 3) * Mp + m) << 3) + (k & 7);
 }
 
+// two FP32 values rounded to bf16 (to nearest even, by the conversion instruction) and
+// packed into one register, lo in the low half
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi)
+{
+    const bf16x2_t b = __builtin_convertvector(f32x2_t{lo, hi}, bf16x2_t);
+    uint32_t r;
+    __builtin_memcpy(&r, &b, 4);
+    return r;
+}
+
 // 8 consecutive values of one panel row
 template <bool F32M>
 __device__ __forceinline__ void put8(void* A, long at, const float v[8])
@@ -66,10 +78,10 @@ __device__ __forceinline__ void put8(void* A, long at, const float v[8])
         d[1] = make_float4(v[4], v[5], v[6], v[7]);
     } else {
         uint4 r;
-        r.x = (uint32_t)float_to_bf16(v[0]) | ((uint32_t)float_to_bf16(v[1]) << 16);
-        r.y = (uint32_t)float_to_bf16(v[2]) | ((uint32_t)float_to_bf16(v[3]) << 16);
-        r.z = (uint32_t)float_to_bf16(v[4]) | ((uint32_t)float_to_bf16(v[5]) << 16);
-        r.w = (uint32_t)float_to_bf16(v[6]) | ((uint32_t)float_to_bf16(v[7]) << 16);
+        r.x = pack_bf16x2(v[0], v[1]);
+        r.y = pack_bf16x2(v[2], v[3]);
+        r.z = pack_bf16x2(v[4], v[5]);
+        r.w = pack_bf16x2(v[6], v[7]);
         *(uint4*)((uint16_t*)A + at) = r;
     }
 }
@@ -441,6 +453,35 @@ __device__ __forceinline__ void nn_path_setup(const Geom& g, int par, int i, con
     }
 }
 
+// the 3x3 matrix s U of a path's link, its third row rebuilt once (s = +-1, so folding it
+// into the matrix changes no rounding)
+__device__ __forceinline__ void nn_link_matrix(const cx<float> u[6], cx<float> d, float sg,
+                                               cx<float> m[9])
+{
+    m[6] = d * conj_(u[1] * u[5] - u[2] * u[4]);
+    m[7] = d * conj_(u[2] * u[3] - u[0] * u[5]);
+    m[8] = d * conj_(u[0] * u[4] - u[1] * u[3]);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) m[k] = u[k];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) m[k] = scale(m[k], sg);
+}
+
+// w = M sp (forward path) or M^+ sp (backward path) for the four spins
+__device__ __forceinline__ void nn_apply_m(bool fwd, const cx<float> m[9], const cx<float> sp[12],
+                                           cx<float> w[12])
+{
+#pragma unroll
+    for (int sd = 0; sd < 4; ++sd) {
+        const cx<float> h0 = sp[3 * sd], h1 = sp[3 * sd + 1], h2 = sp[3 * sd + 2];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+            w[3 * sd + r] = fwd ? m[3 * r] * h0 + m[3 * r + 1] * h1 + m[3 * r + 2] * h2
+                                : cmul_conj(m[r], h0) + cmul_conj(m[3 + r], h1) +
+                                      cmul_conj(m[6 + r], h2);
+    }
+}
+
 // w = s U sp (forward path) or s U^+ sp (backward path), spin by spin pairs
 __device__ __forceinline__ void nn_path_apply(bool fwd, const cx<float> u[6], cx<float> d, float sg,
                                               const cx<float> sp[12], cx<float> w[12])
@@ -454,16 +495,46 @@ __device__ __forceinline__ void nn_path_apply(bool fwd, const cx<float> u[6], cx
     }
 }
 
+// LDS row stride (in bf16 halves) of a tile with KB columns: at least KB + 8, rows 16-byte
+// aligned, and a lane's three rows (the lane-to-lane step of the 16-byte row writes) 4 banks
+// apart modulo the 64 banks, so the 64 lanes of a write hit every bank equally
+constexpr int tile_stride(int kb)
+{
+    int ls = (kb + 8 + 7) / 8 * 8;
+    while ((3 * ls / 2) % 64 != 4) ls += 8;
+    return ls;
+}
+
+// orders the LDS accesses of one wavefront's lanes (writes before, reads after), without
+// waiting for the other wavefronts of the workgroup
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// first row q (site) of the 64-site block of this workgroup in the forward kernels, whose
+// grid is one workgroup per block of either parity: blocks of the two parities alternate
+// (the even and odd sites of one index range are lexicographic neighbours along x3), and
+// each XCD takes one contiguous range of blocks, so that the neighbour windows a workgroup
+// gathers were mostly loaded into its XCD's L2 by workgroups running beside it
+__device__ __forceinline__ long nn_block_q0(int Vp)
+{
+    const int w = xcd_tile(blockIdx.x, gridDim.x);
+    return (long)(w & 1) * Vp + (long)(w >> 1) * 64;
+}
+
 // the three rows (site sl, colour c) of one (path, channel) group, as bf16, into the tile
 template <int LS>
 __device__ __forceinline__ void nn_put_rows(uint16_t* tile, int sl, int k0, const cx<float> w[12])
 {
     for (int c = 0; c < 3; ++c) {
         uint4 r;
-        r.x = (uint32_t)float_to_bf16(w[c].re) | ((uint32_t)float_to_bf16(w[c].im) << 16);
-        r.y = (uint32_t)float_to_bf16(w[3 + c].re) | ((uint32_t)float_to_bf16(w[3 + c].im) << 16);
-        r.z = (uint32_t)float_to_bf16(w[6 + c].re) | ((uint32_t)float_to_bf16(w[6 + c].im) << 16);
-        r.w = (uint32_t)float_to_bf16(w[9 + c].re) | ((uint32_t)float_to_bf16(w[9 + c].im) << 16);
+        r.x = pack_bf16x2(w[c].re, w[c].im);
+        r.y = pack_bf16x2(w[3 + c].re, w[3 + c].im);
+        r.z = pack_bf16x2(w[6 + c].re, w[6 + c].im);
+        r.w = pack_bf16x2(w[9 + c].re, w[9 + c].im);
         *(uint4*)&tile[(sl * 3 + c) * LS + k0] = r;
     }
 }
@@ -475,7 +546,7 @@ __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, c
 {
     constexpr int PB = CIN == 1 ? kPaths : 1;          // paths per batch
     constexpr int KB = (PB * CIN * 8 + 15) & ~15;      // columns per batch (80 or 64)
-    constexpr int LS = KB + 8;                         // LDS row stride (halves)
+    constexpr int LS = tile_stride(KB);                // LDS row stride (halves)
     constexpr int NT = COUT * 8 >= 16 ? COUT * 8 / 16 : 1;  // 16-column tiles of N
     static_assert(CIN == 1 || CIN == 8, "channel counts of the network");
     // LDS: the transported tile during the batches, then the output block (COUT channels x
@@ -485,9 +556,12 @@ __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, c
     uint16_t* tile = (uint16_t*)lds;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int Vp = padded(g.Vh);
-    const long q0 = (long)blockIdx.x * 64;
-    // this lane's transport site
-    const int sl = lane;
+    const long q0 = nn_block_q0(Vp);
+    // this lane's transport site: Cin = 8, the wave's own 16 sites (the rows its matrix-core
+    // products read), four lanes per site, channels cg and cg + 4 per lane, so no wave waits
+    // for another between the batches; Cin = 1, all 64 sites, paths split over the waves
+    const int sl = CIN == 8 ? wave * 16 + (lane & 15) : lane;
+    const int cg = lane >> 4;
     const long qs = q0 + sl;
     const int par = (int)(qs / Vp), i = (int)(qs - (long)par * Vp);
     const bool real = i < g.Vh;
@@ -501,13 +575,13 @@ __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, c
     } pf;
     auto prefetch = [&](int p) {
         if (p == 0) {
-            load_spinor<PIN>(in[wave], g.Vh, par, i, pf.s0);
-            load_spinor<PIN>(in[wave + 4], g.Vh, par, i, pf.s1);
+            load_spinor<PIN>(in[cg], g.Vh, par, i, pf.s0);
+            load_spinor<PIN>(in[cg + 4], g.Vh, par, i, pf.s1);
         } else {
             int j;
             nn_path_setup(g, par, i, x, lex, p, links, dets, j, pf.sg, pf.u, pf.d);
-            load_spinor<PIN>(in[wave], g.Vh, 1 - par, j, pf.s0);
-            load_spinor<PIN>(in[wave + 4], g.Vh, 1 - par, j, pf.s1);
+            load_spinor<PIN>(in[cg], g.Vh, 1 - par, j, pf.s0);
+            load_spinor<PIN>(in[cg + 4], g.Vh, 1 - par, j, pf.s1);
         }
     };
     if (CIN == 8 && real) prefetch(0);
@@ -516,21 +590,23 @@ __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, c
         for (int j = 0; j < NT; ++j) acc[r][j] = f4{0.f, 0.f, 0.f, 0.f};
     for (int p0 = 0; p0 < kPaths; p0 += PB) {
         if constexpr (CIN == 8) {
-            // channels wave and wave + 4 of path p0: the loads were issued before the
-            // previous batch's mixing (below), so they overlap it
+            // channels cg and cg + 4 of path p0: the loads were issued before the previous
+            // batch's mixing (below), so they overlap it. The wave writes and then reads
+            // only its own rows of the tile, in program order, so it needs no barrier.
             if (!real) {
-                nn_put_rows<LS>(tile, sl, wave * 8, zero12);
-                nn_put_rows<LS>(tile, sl, (wave + 4) * 8, zero12);
+                nn_put_rows<LS>(tile, sl, cg * 8, zero12);
+                nn_put_rows<LS>(tile, sl, (cg + 4) * 8, zero12);
             } else if (p0 == 0) {
-                nn_put_rows<LS>(tile, sl, wave * 8, pf.s0);
-                nn_put_rows<LS>(tile, sl, (wave + 4) * 8, pf.s1);
+                nn_put_rows<LS>(tile, sl, cg * 8, pf.s0);
+                nn_put_rows<LS>(tile, sl, (cg + 4) * 8, pf.s1);
             } else {
                 const bool fwd = ((p0 - 1) & 1) == 0;
-                cx<float> w[12];
-                nn_path_apply(fwd, pf.u, pf.d, pf.sg, pf.s0, w);
-                nn_put_rows<LS>(tile, sl, wave * 8, w);
-                nn_path_apply(fwd, pf.u, pf.d, pf.sg, pf.s1, w);
-                nn_put_rows<LS>(tile, sl, (wave + 4) * 8, w);
+                cx<float> w[12], m[9];
+                nn_link_matrix(pf.u, pf.d, pf.sg, m);
+                nn_apply_m(fwd, m, pf.s0, w);
+                nn_put_rows<LS>(tile, sl, cg * 8, w);
+                nn_apply_m(fwd, m, pf.s1, w);
+                nn_put_rows<LS>(tile, sl, (cg + 4) * 8, w);
             }
             if (real && p0 + 1 < kPaths) prefetch(p0 + 1);
         } else {
@@ -549,7 +625,9 @@ __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, c
                     cx<float> u[6], d, sp[12];
                     nn_path_setup(g, par, i, x, lex, p, links, dets, j, sg, u, d);
                     load_spinor<PIN>(in[0], g.Vh, 1 - par, j, sp);
-                    nn_path_apply(((p - 1) & 1) == 0, u, d, sg, sp, w);
+                    cx<float> m[9];
+                    nn_link_matrix(u, d, sg, m);
+                    nn_apply_m(((p - 1) & 1) == 0, m, sp, w);
                 }
                 nn_put_rows<LS>(tile, sl, p * 8, w);
             }
@@ -557,7 +635,8 @@ __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, c
             for (int rr = threadIdx.x; rr < 192; rr += 256)
                 *(uint4*)&tile[rr * LS + kPaths * 8] = uint4{0u, 0u, 0u, 0u};
         }
-        __syncthreads();
+        if constexpr (CIN == 1) __syncthreads();  // the waves filled each other's rows
+        else wave_sync();                         // the wave's own rows, by its other lanes
         // mixing: rows 48*wave .. +48 of the tile times B[p0*CIN*8 .. +KB][0 .. 16 NT]
         const long kglob = (long)p0 * CIN * 8;
         for (int kk = 0; kk < KB; kk += 16) {
@@ -571,8 +650,9 @@ __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, c
                     acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bf[j], acc[r][j], 0, 0, 0);
             }
         }
-        __syncthreads();  // the tile is rewritten by the next batch
+        if constexpr (CIN == 8) wave_sync();  // its rows are rewritten by the next batch
     }
+    __syncthreads();  // the output block below reuses the tile
     // outputs: row m = 3 * site + c, column n = (a * 4 + s) * 2 + re/im, staged in LDS as
     // [channel][real][site] (the 64 sites are one aligned block of one parity), then
     // written in the output precision as contiguous 16-byte chunks
@@ -632,13 +712,13 @@ __global__ void nn_embed_mix_kernel(const float* W, uint16_t* Bm)
 __global__ __launch_bounds__(256) void nn_mix_paths_kernel(Geom g, const void* const* in,
                                                            const uint16_t* Bm, void* const* mix)
 {
-    constexpr int KB = 64, LS = KB + 8, NT = 5;
+    constexpr int KB = 64, LS = tile_stride(KB), NT = 5;
     constexpr int TILE_B = 192 * LS * 2, OUT_B = 9 * 24 * 64 * 4;
     __shared__ __attribute__((aligned(16))) char lds[TILE_B > OUT_B ? TILE_B : OUT_B];
     uint16_t* tile = (uint16_t*)lds;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int Vp = padded(g.Vh);
-    const long q0 = (long)blockIdx.x * 64;
+    const long q0 = nn_block_q0(Vp);
     const int par = (int)(q0 / Vp), i0 = (int)(q0 - (long)par * Vp);
     const int i = i0 + lane;
     const cx<float> zero12[12] = {};
@@ -685,11 +765,12 @@ __global__ __launch_bounds__(256) void nn_mix_paths_kernel(Geom g, const void* c
     for (int u = threadIdx.x; u < 9 * 3 * 64; u += 256) {
         const int p = u / 192, rem = u - p * 192, ch = rem >> 6, site = rem & 63;
         if (i0 + site >= g.Vh) continue;
-        Chunk<BF16S> cval;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) cval.v[j] = float_to_bf16(ob[(p * 24 + ch * 8 + j) * 64 + site]);
         uint4 raw;
-        __builtin_memcpy(&raw, &cval, 16);
+        const float* src = &ob[(p * 24 + ch * 8) * 64 + site];
+        raw.x = pack_bf16x2(src[0], src[64]);
+        raw.y = pack_bf16x2(src[2 * 64], src[3 * 64]);
+        raw.z = pack_bf16x2(src[4 * 64], src[5 * 64]);
+        raw.w = pack_bf16x2(src[6 * 64], src[7 * 64]);
         ((uint4*)mix[p])[chunk_at(g.Vh, 3, par, ch, i0 + site)] = raw;
     }
 }
@@ -699,20 +780,25 @@ __global__ __launch_bounds__(256) void nn_transport_sum_kernel(Geom g, const voi
                                                                float* out, const void* links,
                                                                const void* dets)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int par = blockIdx.y;
+    // 256-site blocks of the two parities alternate, XCD-contiguously (as nn_block_q0)
+    const int w = xcd_tile(blockIdx.x, gridDim.x);
+    const int par = w & 1;
+    const int i = (w >> 1) * 256 + (int)threadIdx.x;
     if (i >= g.Vh) return;
     int x[4], lex;
     eo_coords(g, par, i, x, lex);
     cx<float> acc[12];
     load_spinor<BF16S>(mix[0], g.Vh, par, i, acc);
+#pragma unroll 1
     for (int p = 1; p < kPaths; ++p) {
         int j;
         float sg;
         cx<float> u[6], d, sp[12], w[12];
         nn_path_setup(g, par, i, x, lex, p, links, dets, j, sg, u, d);
         load_spinor<BF16S>(mix[p], g.Vh, 1 - par, j, sp);
-        nn_path_apply(((p - 1) & 1) == 0, u, d, sg, sp, w);
+        cx<float> m[9];
+        nn_link_matrix(u, d, sg, m);
+        nn_apply_m(((p - 1) & 1) == 0, m, sp, w);
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[k] = acc[k] + w[k];
     }
@@ -859,7 +945,7 @@ int forward(qdw_op* op, const float* weights, NnWork& W, hipStream_t st)
                 QDW_LAUNCH_CHECK();
                 nn_mix_paths_kernel<<<nb, 256, 0, st>>>(g, pin, W.Bm, (void* const*)(W.ptrs + 24));
                 QDW_LAUNCH_CHECK();
-                nn_transport_sum_kernel<<<dim3((g.Vh + 255) / 256, 2), 256, 0, st>>>(
+                nn_transport_sum_kernel<<<2 * ((g.Vh + 255) / 256), 256, 0, st>>>(
                     g, (const void* const*)(W.ptrs + 24), W.act[l + 1][0], L, D);
                 QDW_LAUNCH_CHECK();
             }
