@@ -230,6 +230,38 @@ __device__ __forceinline__ void forward_all(float (*rl)[kBMax], const BlockGeom&
     hop_forward<SP, 3>(rl, B, l, t, u, d, vh);
 }
 
+// The same hand-over and forward hop with the neighbour's lane given explicitly (-1: the
+// neighbour is outside the block), for blocks whose lanes are not numbered by site
+template <int SP, int MU>
+__device__ __forceinline__ void push_to(float (*hb)[12][kBMax], int dst, const cx<float> r[12],
+                                        const cx<float> u[6], cx<float> d)
+{
+    if (dst >= 0) {
+        cx<float> h[6], w[6];
+        project<float, MU, +1>(r, h);
+        su3_mul<float, true>(u, d, h, w);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            hb[MU][2 * c][dst] = w[c].re;
+            hb[MU][2 * c + 1][dst] = w[c].im;
+        }
+    }
+}
+
+template <int SP, int MU>
+__device__ __forceinline__ void forward_from(float (*rl)[kBMax], int src, const cx<float> u[6],
+                                             cx<float> d, cx<float> v[12])
+{
+    if (src >= 0) {
+        cx<float> s[12], h[6], w[6];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) s[c] = {rl[2 * c][src], rl[2 * c + 1][src]};
+        project<float, MU, -1>(s, h);
+        su3_mul<float, false>(u, d, h, w);
+        expand_add<float, MU, -1>(w, v);
+    }
+}
+
 // sum over the block of a per-lane value (one FP64 result, the same in every lane);
 // `slots` must not be read by any lane between the barrier inside and the next barrier
 __device__ __forceinline__ double block_sum(double v, double* slots, int t, int nw)
@@ -439,14 +471,31 @@ void sap_mr_eo_kernel(Geom g, BlockGeom B, int colour, int nmr,
         b[0] = r / B.nb[1];
         if (((b[0] + b[1] + b[2] + b[3]) & 1) != colour) b[3] += 1;
     }
-    int l[4];
-    {
-        int r = t;
-        l[3] = r % B.bs[3]; r /= B.bs[3];
-        l[2] = r % B.bs[2]; r /= B.bs[2];
-        l[1] = r % B.bs[1];
-        l[0] = r / B.bs[1];
+    // Lanes by parity: with an even x3 extent the block's sites 2e and 2e + 1 (its local
+    // index) have opposite parities, and lane e (first half) takes the even one of the
+    // pair, lane half + e the odd one. Every hop pass below sends from one parity to the
+    // other, so whole wavefronts skip the half they have no part in. With an odd x3
+    // extent lanes are numbered by site (correct, without the saving).
+    const int half = B.bvol >> 1;
+    const bool split = (B.bs[3] & 1) == 0;
+    const int bpar = (b[0] * B.bs[0] + b[1] * B.bs[1] + b[2] * B.bs[2] + b[3] * B.bs[3]) & 1;
+    auto local = [&](int site, int lc[4]) {
+        int r = site;
+        lc[3] = r % B.bs[3]; r /= B.bs[3];
+        lc[2] = r % B.bs[2]; r /= B.bs[2];
+        lc[1] = r % B.bs[1];
+        lc[0] = r / B.bs[1];
+    };
+    int site = t;
+    if (split) {
+        const int want = t >= half ? 1 : 0;
+        const int s0 = 2 * (t - want * half);
+        int l0[4];
+        local(s0, l0);
+        site = s0 + (((bpar + l0[0] + l0[1] + l0[2] + l0[3]) & 1) != want ? 1 : 0);
     }
+    int l[4];
+    local(site, l);
     int x[4];
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) x[mu] = b[mu] * B.bs[mu] + l[mu];
@@ -454,6 +503,13 @@ void sap_mr_eo_kernel(Geom g, BlockGeom B, int colour, int nmr,
     const int par = (x[0] + x[1] + x[2] + x[3]) & 1;
     const int i = lex >> 1;
     const bool ev = par == 0;
+    // lanes of the +mu neighbours inside the block (the other parity), -1 at the block edge
+    int nbl[4];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        const int sn = site + B.lstride[mu];
+        nbl[mu] = l[mu] < B.bs[mu] - 1 ? (split ? (1 - par) * half + (sn >> 1) : sn) : -1;
+    }
 
     cx<float> r[12];
     load_spinor<SP>(rs, g.Vh, par, i, r);
@@ -464,23 +520,48 @@ void sap_mr_eo_kernel(Geom g, BlockGeom B, int colour, int nmr,
         so.opaque();
         so.diag(v, o);
     };
-    // vh = H src over the block (src: this lane's value; written to LDS here)
-    auto hops = [&](const cx<float> src[12], cx<float> vh[12]) {
+    // vh = H src on the lanes of the parity other than `from` (0 on the lanes of `from`);
+    // src is non-zero on the lanes of `from` only
+    auto hops = [&](int from, const cx<float> src[12], cx<float> vh[12]) {
+        const bool sends = par == from;
+        if (sends) {
 #pragma unroll
-        for (int c = 0; c < 12; ++c) {
-            rl[2 * c][t] = src[c].re;
-            rl[2 * c + 1][t] = src[c].im;
+            for (int c = 0; c < 12; ++c) {
+                rl[2 * c][t] = src[c].re;
+                rl[2 * c + 1][t] = src[c].im;
+            }
         }
         __syncthreads();  // rl holds src
-        push_all<SP>(hb, B, l, t, src, so);
 #pragma unroll
         for (int c = 0; c < 12; ++c) vh[c] = {0.f, 0.f};
-        forward_all<SP>(rl, B, l, t, so, vh);
+        cx<float> u[6], d;
+        so.opaque();
+        if (sends) {
+            so.template link<0>(u, d);
+            push_to<SP, 0>(hb, nbl[0], src, u, d);
+            so.template link<1>(u, d);
+            push_to<SP, 1>(hb, nbl[1], src, u, d);
+            so.template link<2>(u, d);
+            push_to<SP, 2>(hb, nbl[2], src, u, d);
+            so.template link<3>(u, d);
+            push_to<SP, 3>(hb, nbl[3], src, u, d);
+        } else {
+            so.template link<0>(u, d);
+            forward_from<SP, 0>(rl, nbl[0], u, d, vh);
+            so.template link<1>(u, d);
+            forward_from<SP, 1>(rl, nbl[1], u, d, vh);
+            so.template link<2>(u, d);
+            forward_from<SP, 2>(rl, nbl[2], u, d, vh);
+            so.template link<3>(u, d);
+            forward_from<SP, 3>(rl, nbl[3], u, d, vh);
+        }
         __syncthreads();  // every pushed half spinor is in hb
-        hop_backward<0>(hb, l, t, vh);
-        hop_backward<1>(hb, l, t, vh);
-        hop_backward<2>(hb, l, t, vh);
-        hop_backward<3>(hb, l, t, vh);
+        if (!sends) {
+            hop_backward<0>(hb, l, t, vh);
+            hop_backward<1>(hb, l, t, vh);
+            hop_backward<2>(hb, l, t, vh);
+            hop_backward<3>(hb, l, t, vh);
+        }
         __syncthreads();  // rl and hb are free again
     };
     const cx<float> z = {0.f, 0.f};
@@ -492,7 +573,7 @@ void sap_mr_eo_kernel(Geom g, BlockGeom B, int colour, int nmr,
     } else {
         diag(r, w);
     }
-    hops(w, vh);
+    hops(1, w, vh);
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
         res[c] = ev ? r[c] + scale(vh[c], 0.5f) : z;
@@ -500,7 +581,7 @@ void sap_mr_eo_kernel(Geom g, BlockGeom B, int colour, int nmr,
     }
     // (2) MR on the reduced block operator
     for (int k = 0; k < nmr; ++k) {
-        hops(res, vh);  // odd lanes: H res
+        hops(0, res, vh);  // odd lanes: H res
         if (ev) {
 #pragma unroll
             for (int c = 0; c < 12; ++c) w[c] = z;
@@ -509,7 +590,7 @@ void sap_mr_eo_kernel(Geom g, BlockGeom B, int colour, int nmr,
             for (int c = 0; c < 12; ++c) vh[c] = scale(vh[c], -0.5f);
             diag(vh, w);  // A^-1 D_oe res
         }
-        hops(w, vh);  // even lanes: H A^-1 D_oe res
+        hops(1, w, vh);  // even lanes: H A^-1 D_oe res
         cx<float> v[12];
         if (ev) {
             diag(res, v);
@@ -556,7 +637,7 @@ void sap_mr_eo_kernel(Geom g, BlockGeom B, int colour, int nmr,
         // red is rewritten only after the two barriers of the next step's first hops
     }
     // (3) the odd half of the block solution
-    hops(chi, vh);  // odd lanes: H chi_e
+    hops(0, chi, vh);  // odd lanes: H chi_e
     if (!ev) {
 #pragma unroll
         for (int c = 0; c < 12; ++c) w[c] = r[c] + scale(vh[c], 0.5f);

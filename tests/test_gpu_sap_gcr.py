@@ -208,8 +208,10 @@ def test_sap_eo_matches_oracle(lat8, sdtype, ncy, nmr):
 
 
 @pytest.mark.parametrize("dims,bs", [((8, 4, 4, 8), (4, 2, 2, 4)), ((8, 8, 4, 8), (2, 4, 2, 4)),
-                                     ((8, 8, 8, 4), (4, 4, 4, 2))])
+                                     ((8, 8, 8, 4), (4, 4, 4, 2)), ((8, 8, 32, 2), (4, 4, 16, 1))])
 def test_sap_eo_small_blocks_and_rectangular(dims, bs):
+    """64- to 256-site blocks; the last case has an odd x3 block extent, where the kernel
+    numbers its lanes by site instead of by parity."""
     gop, oop, _, _ = make_pair(dims, 0.1, 1.5, 0.3, seed=5)
     rho = syn.gaussian_spinor(dims, 6)
     r = gop.pack(rho, "f64")
