@@ -25,7 +25,8 @@ Also reported, each timed on its own outside the K steps:
     with 12 point sources, one per spin and colour; 24^3 x 48 with 4 Gaussian sources;
     8^3 x 16 with 24 Gaussian sources; three independent fields, eps = 0.3, m0 = -0.05),
     mixed-precision SAP-GCR to 1e-10 as one graph-replayed batch against the same 40
-    solves one after another, with the D-kernel shape the autotuner picked per lattice;
+    solves one after another, with plain and with even-odd reduced SAP blocks, and the
+    D-kernel shape the autotuner picked per lattice;
   * the FP64 oracle timed on the host on a bounded sample (cpu_baseline).
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-solves]
@@ -232,8 +233,8 @@ BATCH = (((32, 16, 16, 16), "point", 12, 7388 + 31), ((48, 24, 24, 24), "gauss",
 
 
 def batched_solves(qdw, syn):
-    """40 right-hand sides over three lattices: one batched SAP-GCR against 40 single solves."""
-    import torch
+    """40 right-hand sides over three lattices: one batched SAP-GCR against 40 single solves,
+    with plain SAP and with even-odd reduced SAP blocks."""
     ops, etas, shapes = [], [], {}
     for dims, kind, n, seed in BATCH:
         su3, th = syn.gauge_field(dims, EPS, EPS_U1, seed)
@@ -246,8 +247,18 @@ def batched_solves(qdw, syn):
                    else syn.gaussian_spinor(dims, seed + 1000 + r))
             ops.append(op)
             etas.append(op.pack(src, "f64"))
+    out = {}
+    for precond in ("sap", "sap_eo"):
+        out[precond] = batched_run(qdw, ops, etas, shapes, precond)
+    for o in set(ops):
+        o.close()
+    return out
+
+
+def batched_run(qdw, ops, etas, shapes, precond):
+    import torch
     kw = dict(res=1e-10, nmx=2000, nkv=16, ncy=5, nmr=4, bs=(4, 4, 4, 4), sdtype="f16",
-              precond="sap")
+              precond=precond)
     psis = [o.new_field("f64") for o in ops]
     qdw.sap_gcr_solve_batched(ops[:2], etas[:2], psis[:2], **kw)  # warm-up (code objects)
     torch.cuda.synchronize()
@@ -280,10 +291,9 @@ def batched_solves(qdw, syn):
     rec = {"rhs": len(ops), "site_rhs": site_rhs, "s_batched": round(t_batch, 4),
            "graph_setup_ms": round(graph_ms, 2), "s_sequential_single": round(t_seq, 4),
            "speedup": round(t_seq / t_batch, 3), "lattices": per,
-           "settings": "SAP-GCR nkv 16, 4^4 blocks, ncy 5, nmr 4, FP16 SAP storage, res 1e-10"}
-    log("  batched: %s" % json.dumps(rec))
-    for o in set(ops):
-        o.close()
+           "settings": "SAP-GCR nkv 16, 4^4 blocks, ncy 5, nmr 4, FP16 SAP storage, res 1e-10, "
+                       "precond %s" % precond}
+    log("  batched %s: %s" % (precond, json.dumps(rec)))
     return rec
 
 

@@ -276,8 +276,9 @@ int sap_gcr_solve(qdw_op* op, const void* eta, void* psi, const qdw_sap_gcr_para
 /* Several flexible-GCR solves at once (not from the paper: batching across right-hand
  * sides and lattices): problem j solves D_j psi_j = eta_j with operator ops[j] (ops may
  * repeat: the right-hand sides of one operator are solved together; operators may have
- * different lattice volumes), all with settings p (precond QDW_PRECOND_NONE or
- * QDW_PRECOND_SAP). Each solve takes the same steps, with the same arithmetic, as
+ * different lattice volumes), all with settings p (precond QDW_PRECOND_NONE,
+ * QDW_PRECOND_SAP or QDW_PRECOND_SAP_EO). Each solve takes the same steps, with the same
+ * arithmetic, as
  * sap_gcr_solve on its own; all convergence decisions are made on the device, one
  * restart cycle (nkv steps + restart step) of the whole batch is captured once as a HIP
  * graph and replayed until every solve has finished (the host waits once per replay).

@@ -413,6 +413,12 @@ int by_k(int k, Fill fill)
     }
 }
 
+// SAP (plain or with even-odd reduced block solves) with at least one cycle
+inline bool sap_precond(const qdw_sap_gcr_params& p)
+{
+    return (p.precond == QDW_PRECOND_SAP || p.precond == QDW_PRECOND_SAP_EO) && p.ncy > 0;
+}
+
 template <int SP>
 int precondition(const Group& G, const qdw_sap_gcr_params& p, void* phi_k, hipStream_t st)
 {
@@ -425,7 +431,8 @@ int precondition(const Group& G, const qdw_sap_gcr_params& p, void* phi_k, hipSt
     bat.fstride = G.fbs;
     bat.gate = G.fl + F_INCYCLE;
     bat.gstride = F_SIZE;
-    if ((rc = sap_cycles(G.op, G.B, SP, p.ncy, p.nmr, G.rs, G.psis, G.delta, bat, G.nr, st)))
+    if ((rc = sap_cycles(G.op, G.B, SP, p.ncy, p.nmr, G.rs, G.psis, G.delta, bat, G.nr, st,
+                         p.precond == QDW_PRECOND_SAP_EO)))
         return rc;
     return brun(G, SapOut<SP>{{G.psis, G.fbs}, {(char*)phi_k, G.fb}, G.sc, Vh, V}, F_INCYCLE, st);
 }
@@ -433,7 +440,7 @@ int precondition(const Group& G, const qdw_sap_gcr_params& p, void* phi_k, hipSt
 int cycle(const Group& G, const qdw_sap_gcr_params& p, hipStream_t st)
 {
     const int Vh = G.op->g.Vh, nr = G.nr;
-    const bool sap = p.precond == QDW_PRECOND_SAP && p.ncy > 0;
+    const bool sap = sap_precond(p);
     const void* in[kMaxRhs];
     void* out[kMaxRhs];
     int rc;
@@ -523,7 +530,7 @@ int plan(qdw_op* const* ops, int n, const qdw_sap_gcr_params& p, char* base,
         QDW_CHECK((int)G->prob.size() <= kMaxRhs, QDW_EINVAL,
                   "sap_gcr_solve_batched: at most 64 right-hand sides per operator");
     }
-    const bool sap = p.precond == QDW_PRECOND_SAP && p.ncy > 0;
+    const bool sap = sap_precond(p);
     size_t off = 0;
     auto take = [&](size_t nb) {
         char* at = base ? base + off : nullptr;
@@ -567,9 +574,12 @@ int check_params(const qdw_sap_gcr_params* p)
 {
     QDW_CHECK(p->nkv >= 1 && p->nkv <= kMaxKv, QDW_EINVAL, "sap_gcr_solve_batched: need 1 <= nkv <= 16");
     QDW_CHECK(p->nmx >= 1 && p->res > 0.0, QDW_EINVAL, "sap_gcr_solve_batched: need nmx >= 1, res > 0");
-    QDW_CHECK(p->precond == QDW_PRECOND_NONE || p->precond == QDW_PRECOND_SAP, QDW_EINVAL,
-              "sap_gcr_solve_batched: preconditioner must be QDW_PRECOND_NONE or QDW_PRECOND_SAP");
-    if (p->precond == QDW_PRECOND_SAP) {
+    QDW_CHECK(p->precond == QDW_PRECOND_NONE || p->precond == QDW_PRECOND_SAP ||
+                  p->precond == QDW_PRECOND_SAP_EO,
+              QDW_EINVAL,
+              "sap_gcr_solve_batched: preconditioner must be QDW_PRECOND_NONE, QDW_PRECOND_SAP "
+              "or QDW_PRECOND_SAP_EO");
+    if (p->precond != QDW_PRECOND_NONE) {
         QDW_CHECK(p->ncy >= 0 && p->nmr >= 0, QDW_EINVAL, "sap_gcr_solve_batched: ncy, nmr must be >= 0");
         QDW_CHECK(p->sdtype >= QDW_F32 && p->sdtype <= QDW_BF16S, QDW_EINVAL,
                   "sap_gcr_solve_batched: sdtype must be QDW_F32, QDW_F16S or QDW_BF16S");
@@ -722,7 +732,7 @@ extern "C" int sap_gcr_solve_batched(qdw_op* const* ops, const void* const* etas
         so += G.nr;
     }
     QDW_HIP(hipStreamSynchronize(res.cs));
-    const bool sap = p->precond == QDW_PRECOND_SAP && p->ncy > 0;
+    const bool sap = sap_precond(*p);
     so = 0;
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     for (const Group& G : gs) {

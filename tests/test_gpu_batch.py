@@ -175,7 +175,8 @@ def _solve_batched(ops, probs, **kw):
 KW = dict(res=1e-10, nmx=400, nkv=8, ncy=4, nmr=4, bs=(4, 4, 4, 4))
 
 
-@pytest.mark.parametrize("precond,sdtype", [("sap", "f16"), ("sap", "f32"), ("none", "f32")])
+@pytest.mark.parametrize("precond,sdtype", [("sap", "f16"), ("sap", "f32"), ("none", "f32"),
+                                            ("sap_eo", "f16")])
 def test_batched_equals_single_solves(batch, precond, sdtype):
     ops, probs = batch
     infos, psis, gms = _solve_batched(ops, probs, precond=precond, sdtype=sdtype, **KW)
