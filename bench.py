@@ -19,8 +19,8 @@ Also reported, each timed on its own outside the K steps:
     20 MR steps, alpha 0.9 and 0.7, FP16);
   * the learned preconditioner: trained on the GPU on 2000 residual/error pairs from
     plain FP64 GCR solves on four 16^3 x 32 fields (eps = 0.3, m0 = -0.05), then used as
-    the flexible-GCR preconditioner on the 32^3 x 64 field against SAP-GCR and plain GCR,
-    all to 1e-10;
+    the flexible-GCR preconditioner on the 32^3 x 64 field against SAP-GCR (plain and with
+    even-odd reduced blocks) and plain GCR, all to 1e-10;
   * a batch of 40 right-hand sides over three lattices of different volumes (16^3 x 32
     with 12 point sources, one per spin and colour; 24^3 x 48 with 4 Gaussian sources;
     8^3 x 16 with 24 Gaussian sources; three independent fields, eps = 0.3, m0 = -0.05),
@@ -218,7 +218,8 @@ def learned_preconditioner(qdw, syn, op, psi):
     for name, kw in (("plain_fp64", dict(precond="none")),
                      ("nn", dict(precond="nn", nn_weights=w)),
                      ("nn_then_sap_fp16", dict(precond="nn_sap", nn_weights=w, sdtype="f16")),
-                     ("sap_fp16", dict(precond="sap", sdtype="f16"))):
+                     ("sap_fp16", dict(precond="sap", sdtype="f16")),
+                     ("sap_eo_fp16", dict(precond="sap_eo", sdtype="f16"))):
         x = op.new_field("f64")
         info = qdw.sap_gcr_solve(op, eta, x, res=1e-10, nmx=5000, nkv=16, ncy=5, nmr=4,
                                  bs=(4, 4, 4, 4), **kw)
