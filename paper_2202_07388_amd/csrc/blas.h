@@ -135,7 +135,7 @@ __device__ inline void finalize_body(const double* partials, int nblk, int ns, d
         red[threadIdx.x] = s;
         __syncthreads();
         for (int w = 128; w > 0; w >>= 1) {
-            if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
             __syncthreads();
         }
         if (threadIdx.x == 0) sums[j] = red[0];

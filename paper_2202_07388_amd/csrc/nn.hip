@@ -482,19 +482,6 @@ __device__ __forceinline__ void nn_apply_m(bool fwd, const cx<float> m[9], const
     }
 }
 
-// w = s U sp (forward path) or s U^+ sp (backward path), spin by spin pairs
-__device__ __forceinline__ void nn_path_apply(bool fwd, const cx<float> u[6], cx<float> d, float sg,
-                                              const cx<float> sp[12], cx<float> w[12])
-{
-    cx<float> h[6], o[6];
-    for (int half = 0; half < 2; ++half) {
-        for (int k = 0; k < 6; ++k) h[k] = scale(sp[6 * half + k], sg);
-        if (fwd) su3_mul<float, false>(u, d, h, o);
-        else su3_mul<float, true>(u, d, h, o);
-        for (int k = 0; k < 6; ++k) w[6 * half + k] = o[k];
-    }
-}
-
 // LDS row stride (in bf16 halves) of a tile with KB columns: at least KB + 8, rows 16-byte
 // aligned, and a lane's three rows (the lane-to-lane step of the 16-byte row writes) 4 banks
 // apart modulo the 64 banks, so the 64 lanes of a write hit every bank equally

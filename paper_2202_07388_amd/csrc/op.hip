@@ -77,15 +77,6 @@ __device__ inline M3 link_u3(const double* su3, const double* theta, long lex, i
     return m;
 }
 
-__device__ inline void lex_coords(const Geom& g, long lex, int x[4])
-{
-    long r = lex;
-    x[3] = (int)(r % g.L[3]); r /= g.L[3];
-    x[2] = (int)(r % g.L[2]); r /= g.L[2];
-    x[1] = (int)(r % g.L[1]); r /= g.L[1];
-    x[0] = (int)r;
-}
-
 __device__ inline long lex_of(const Geom& g, const int x[4])
 {
     return ((long)(x[0] * g.L[1] + x[1]) * g.L[2] + x[2]) * g.L[3] + x[3];
@@ -132,7 +123,7 @@ __global__ void unitarity_kernel(const double* su3, long nlinks, unsigned long l
     red[threadIdx.x] = dev;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+        if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
         __syncthreads();
     }
     // non-negative doubles order like their bit patterns
