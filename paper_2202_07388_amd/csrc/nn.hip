@@ -555,77 +555,12 @@ __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, c
     int x[4] = {0, 0, 0, 0}, lex = 0;
     if (real) eo_coords(g, par, i, x, lex);
     const cx<float> zero12[12] = {};
-    // Cin = 8: the inputs of the next path (two channels' neighbour spinors and the link)
-    struct Prefetch {
-        cx<float> s0[12], s1[12], u[6], d;
-        float sg;
-    } pf;
-    auto prefetch = [&](int p) {
-        if (p == 0) {
-            load_spinor<PIN>(in[cg], g.Vh, par, i, pf.s0);
-            load_spinor<PIN>(in[cg + 4], g.Vh, par, i, pf.s1);
-        } else {
-            int j;
-            nn_path_setup(g, par, i, x, lex, p, links, dets, j, pf.sg, pf.u, pf.d);
-            load_spinor<PIN>(in[cg], g.Vh, 1 - par, j, pf.s0);
-            load_spinor<PIN>(in[cg + 4], g.Vh, 1 - par, j, pf.s1);
-        }
-    };
-    if (CIN == 8 && real) prefetch(0);
+    static_assert(CIN == 1 || PIN == BF16S, "hidden channels are stored in bf16");
     f4 acc[3][NT];
     for (int r = 0; r < 3; ++r)
         for (int j = 0; j < NT; ++j) acc[r][j] = f4{0.f, 0.f, 0.f, 0.f};
-    for (int p0 = 0; p0 < kPaths; p0 += PB) {
-        if constexpr (CIN == 8) {
-            // channels cg and cg + 4 of path p0: the loads were issued before the previous
-            // batch's mixing (below), so they overlap it. The wave writes and then reads
-            // only its own rows of the tile, in program order, so it needs no barrier.
-            if (!real) {
-                nn_put_rows<LS>(tile, sl, cg * 8, zero12);
-                nn_put_rows<LS>(tile, sl, (cg + 4) * 8, zero12);
-            } else if (p0 == 0) {
-                nn_put_rows<LS>(tile, sl, cg * 8, pf.s0);
-                nn_put_rows<LS>(tile, sl, (cg + 4) * 8, pf.s1);
-            } else {
-                const bool fwd = ((p0 - 1) & 1) == 0;
-                cx<float> w[12], m[9];
-                nn_link_matrix(pf.u, pf.d, pf.sg, m);
-                nn_apply_m(fwd, m, pf.s0, w);
-                nn_put_rows<LS>(tile, sl, cg * 8, w);
-                nn_apply_m(fwd, m, pf.s1, w);
-                nn_put_rows<LS>(tile, sl, (cg + 4) * 8, w);
-            }
-            if (real && p0 + 1 < kPaths) prefetch(p0 + 1);
-        } else {
-            // paths wave, wave + 4, wave + 8 of the single channel
-            for (int p = wave; p < kPaths; p += 4) {
-                cx<float> w[12];
-                if (!real) {
-                    nn_put_rows<LS>(tile, sl, p * 8, zero12);
-                    continue;
-                }
-                if (p == 0) {
-                    load_spinor<PIN>(in[0], g.Vh, par, i, w);
-                } else {
-                    int j;
-                    float sg;
-                    cx<float> u[6], d, sp[12];
-                    nn_path_setup(g, par, i, x, lex, p, links, dets, j, sg, u, d);
-                    load_spinor<PIN>(in[0], g.Vh, 1 - par, j, sp);
-                    cx<float> m[9];
-                    nn_link_matrix(u, d, sg, m);
-                    nn_apply_m(((p - 1) & 1) == 0, m, sp, w);
-                }
-                nn_put_rows<LS>(tile, sl, p * 8, w);
-            }
-            // zero padding columns 72..79
-            for (int rr = threadIdx.x; rr < 192; rr += 256)
-                *(uint4*)&tile[rr * LS + kPaths * 8] = uint4{0u, 0u, 0u, 0u};
-        }
-        if constexpr (CIN == 1) __syncthreads();  // the waves filled each other's rows
-        else wave_sync();                         // the wave's own rows, by its other lanes
-        // mixing: rows 48*wave .. +48 of the tile times B[p0*CIN*8 .. +KB][0 .. 16 NT]
-        const long kglob = (long)p0 * CIN * 8;
+    // rows 48*wave .. +48 of the tile times B[kglob .. +KB][0 .. 16 NT] on the matrix cores
+    auto mix = [&](long kglob) {
         for (int kk = 0; kk < KB; kk += 16) {
             const int kl = kk + 4 * (lane >> 4);
             s4 bf[NT];
@@ -637,7 +572,106 @@ __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, c
                     acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bf[j], acc[r][j], 0, 0, 0);
             }
         }
-        if constexpr (CIN == 8) wave_sync();  // its rows are rewritten by the next batch
+    };
+    if constexpr (CIN == 8) {
+        // The inputs of one path for this lane -- the neighbour spinors of its two channels
+        // as stored (bf16, widened when used) and the link -- in two stages: the loads of
+        // path p + 1 are issued before the work on path p, so a whole path's transport and
+        // mixing cover their latency. The stages alternate by name (no indexed arrays).
+        struct Stage {
+            uint4 s0[3], s1[3];
+            cx<float> u[6], d;
+            float sg;
+        };
+        auto fetch = [&](int p, Stage& S) {
+            int j = i, pp = par;
+            S.sg = 1.f;
+            if (p > 0) {
+                nn_path_setup(g, par, i, x, lex, p, links, dets, j, S.sg, S.u, S.d);
+                pp = 1 - par;
+            }
+            const long b0 = chunk_at(g.Vh, 3, pp, 0, j);
+            const uint4* c0 = (const uint4*)in[cg];
+            const uint4* c1 = (const uint4*)in[cg + 4];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                S.s0[k] = c0[b0 + (long)k * kSB];
+                S.s1[k] = c1[b0 + (long)k * kSB];
+            }
+        };
+        auto widen = [](const uint4 raw[3], cx<float> s[12]) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const uint32_t w[4] = {raw[k].x, raw[k].y, raw[k].z, raw[k].w};
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    s[4 * k + q] = {bf16_to_float((uint16_t)(w[q] & 0xFFFFu)),
+                                    bf16_to_float((uint16_t)(w[q] >> 16))};
+            }
+        };
+        // path p0 from stage `cur` while the loads of path p0 + 1 go into `nxt`; the wave
+        // writes and then reads only its own rows of the tile, so it needs no barrier
+        auto path = [&](int p0, Stage& cur, Stage& nxt) {
+            if (real && p0 + 1 < kPaths) fetch(p0 + 1, nxt);
+            if (!real) {
+                nn_put_rows<LS>(tile, sl, cg * 8, zero12);
+                nn_put_rows<LS>(tile, sl, (cg + 4) * 8, zero12);
+            } else {
+                cx<float> a[12];
+                if (p0 == 0) {
+                    widen(cur.s0, a);
+                    nn_put_rows<LS>(tile, sl, cg * 8, a);
+                    widen(cur.s1, a);
+                    nn_put_rows<LS>(tile, sl, (cg + 4) * 8, a);
+                } else {
+                    const bool fwd = ((p0 - 1) & 1) == 0;
+                    cx<float> w[12], m[9];
+                    nn_link_matrix(cur.u, cur.d, cur.sg, m);
+                    widen(cur.s0, a);
+                    nn_apply_m(fwd, m, a, w);
+                    nn_put_rows<LS>(tile, sl, cg * 8, w);
+                    widen(cur.s1, a);
+                    nn_apply_m(fwd, m, a, w);
+                    nn_put_rows<LS>(tile, sl, (cg + 4) * 8, w);
+                }
+            }
+            wave_sync();  // the wave's own rows, by its other lanes
+            mix((long)p0 * 64);
+            wave_sync();  // its rows are rewritten by the next path
+        };
+        Stage SA, SB;
+        if (real) fetch(0, SA);
+        for (int p0 = 0; p0 < kPaths; p0 += 2) {
+            path(p0, SA, SB);
+            if (p0 + 1 < kPaths) path(p0 + 1, SB, SA);
+        }
+    } else {
+        // paths wave, wave + 4, wave + 8 of the single channel, one batch
+        for (int p = wave; p < kPaths; p += 4) {
+            cx<float> w[12];
+            if (!real) {
+                nn_put_rows<LS>(tile, sl, p * 8, zero12);
+                continue;
+            }
+            if (p == 0) {
+                load_spinor<PIN>(in[0], g.Vh, par, i, w);
+            } else {
+                int j;
+                float sg;
+                cx<float> u[6], d, sp[12];
+                nn_path_setup(g, par, i, x, lex, p, links, dets, j, sg, u, d);
+                load_spinor<PIN>(in[0], g.Vh, 1 - par, j, sp);
+                cx<float> m[9];
+                nn_link_matrix(u, d, sg, m);
+                nn_apply_m(((p - 1) & 1) == 0, m, sp, w);
+            }
+            nn_put_rows<LS>(tile, sl, p * 8, w);
+        }
+        // zero padding columns 72..79
+        for (int rr = threadIdx.x; rr < 192; rr += 256)
+            *(uint4*)&tile[rr * LS + kPaths * 8] = uint4{0u, 0u, 0u, 0u};
+        __syncthreads();  // the waves filled each other's rows
+        mix(0);
     }
     __syncthreads();  // the output block below reuses the tile
     // outputs: row m = 3 * site + c, column n = (a * 4 + s) * 2 + re/im, staged in LDS as
