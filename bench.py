@@ -7,7 +7,7 @@ bytes (1376 B per site: spinor in and out, 4 links of 12 + 1 reals, 72 clover re
 each read once), inputs resident in HBM.
 
 Also reported, each timed on its own outside the K steps:
-  * D in FP32 and FP16 storage, D^+ in FP64;
+  * D in FP32 and FP16 storage, D^+ in FP64, and FP64 D on 4 fields in one launch;
   * the 32^3 x 64 normal-equation solve to FP64 true residual 1e-10: plain FP64 CG
     against FP32, FP16 and BF16 regular steps with FP64 reset steps, and the BF16 -> FP32
     -> FP64 precision cascade; and the even-odd reduced normal equations D^+ D^ psi_e =
@@ -30,7 +30,7 @@ Also reported, each timed on its own outside the K steps:
   * the FP64 oracle timed on the host on a bounded sample (cpu_baseline).
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-solves]
-                       [--legs cgne,nn,gcr,batch] [--autotune] [--calibrate]
+                       [--legs multi,cgne,nn,gcr,batch] [--autotune] [--calibrate]
 """
 from __future__ import annotations
 
@@ -128,6 +128,30 @@ def solve_record(info):
     return {"s": round(info["t_sec"], 4), "steps": info["n_steps"], "status": info["status"],
             "resets_or_restarts": info["nreset"], "rel_res_true": info["rel_res_true"],
             "dw_fp64": info["n_dw_hi"], "dw_low": info["n_dw_lo"]}
+
+
+def multi_rhs(op, qdw, psi, n=4):
+    """D on n FP64 fields in one launch (links and clover read once for all of them), in the
+    shape the autotuner picks for n fields: per-field time and the rate in algorithmic
+    bytes. The operator's FP64 shape is restored afterwards."""
+    keep = qdw.get_dw_shape(op, "f64")
+    xs = [op.pack(psi * (1.0 + 0.25 * r), "f64") for r in range(n)]
+    ys = [op.new_field("f64") for _ in range(n)]
+    try:
+        shape = qdw.autotune(op, "f64", n).split(";")[0]
+        f = lambda: qdw.dw_apply_multi(op, xs, ys, "f64")
+        for _ in range(3):
+            f()
+        d = time_launches(f, 20)
+    finally:
+        qdw.set_dw_shape(op, "f64", *keep)
+    per_site = n * 2 * 192 + 4 * 104 + 576
+    rec = {"rhs": n, "ms": round(d * 1e3, 4), "ms_per_field": round(d * 1e3 / n, 4),
+           "bytes_per_site": per_site, "GB_s": round(per_site * op.V / d / 1e9, 1),
+           "shape": shape}
+    log("  multi-RHS D: %s" % rec)
+    del xs, ys
+    return rec
 
 
 def cgne_solves(op, qdw, psi):
@@ -306,9 +330,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solves", action="store_true")
     ap.add_argument("--no-nn", action="store_true", help="skip training the learned preconditioner")
-    ap.add_argument("--legs", default="cgne,nn,gcr,batch",
-                    help="comma-separated solve legs to run after the D timing "
-                         "(cgne, nn, gcr, batch); kernel traces of one leg use this")
+    ap.add_argument("--legs", default="multi,cgne,nn,gcr,batch",
+                    help="comma-separated legs to run after the D timing (multi: D on 4 "
+                         "fields in one launch; cgne, nn, gcr, batch: solves); kernel "
+                         "traces of one leg use this")
     ap.add_argument("--autotune", action="store_true",
                     help="pick the 32^3x64 D-kernel shapes with the autotuner instead of the "
                          "pinned ones (its own launches then join any kernel trace)")
@@ -421,6 +446,8 @@ def main():
         legs.discard("nn")
     if legs:
         log("solves: %s ..." % sorted(legs))
+    if "multi" in legs:
+        out["dw_multi_rhs_f64"] = multi_rhs(op, qdw, psi)
     if "cgne" in legs:
         out["cgne_32c64"] = cgne_solves(op, qdw, psi)
     if "nn" in legs:
