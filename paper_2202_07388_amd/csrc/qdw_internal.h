@@ -292,13 +292,16 @@ __device__ __forceinline__ bool walk_site(const Geom& g, int logical, int tid, i
 
 inline int walk_blocks(const Geom& g) { return g.L[0] * g.ntile; }
 
-// Several right-hand sides of one lattice in one launch (blockIdx.y = right-hand side): their
-// fields sit at a fixed byte stride, and gate[r * gstride] == 0 marks a finished one, whose
-// workgroups return at once. The default is a single field and no gate.
+// Several right-hand sides of one lattice in one launch, the right-hand side the fastest-
+// varying workgroup index (the workgroups of one tile or block for all of them run side by
+// side and share its links and clover through L2): their fields sit at a fixed byte stride,
+// and gate[r * gstride] == 0 marks a finished one, whose workgroups return at once. The
+// default is a single field and no gate.
 struct RhsStride {
     long fstride = 0;
     const int* gate = nullptr;
     int gstride = 0;
+    int nrhs = 1;
 };
 
 }  // namespace qdw

@@ -290,17 +290,19 @@ void sap_mr_kernel(Geom g, BlockGeom B, int colour, int nmr,
     __shared__ float hb[4][12][kBMax];
     __shared__ double red[4][3];
     __shared__ double red2[2][4];
-    // right-hand side blockIdx.y of a batch (fields at a fixed byte stride)
-    if (bat.gate && !bat.gate[(long)blockIdx.y * bat.gstride]) return;
-    rs = (char*)rs + blockIdx.y * bat.fstride;
-    psis = (char*)psis + blockIdx.y * bat.fstride;
-    delta = (char*)delta + blockIdx.y * bat.fstride;
+    // right-hand side `rhs` of a batch (fields at a fixed byte stride), block `blk` of the
+    // colour
+    const int rhs = (int)blockIdx.x % bat.nrhs, blk = (int)blockIdx.x / bat.nrhs;
+    if (bat.gate && !bat.gate[(long)rhs * bat.gstride]) return;
+    rs = (char*)rs + rhs * bat.fstride;
+    psis = (char*)psis + rhs * bat.fstride;
+    delta = (char*)delta + rhs * bat.fstride;
     const int t = threadIdx.x;
     const int nw = B.bvol >> 6;
     // the blockIdx-th block of this colour (blocks per x3 row is even, so colours alternate)
     int b[4];
     {
-        int r = 2 * blockIdx.x;
+        int r = 2 * blk;
         b[3] = r % B.nb[3]; r /= B.nb[3];
         b[2] = r % B.nb[2]; r /= B.nb[2];
         b[1] = r % B.nb[1];
@@ -423,7 +425,7 @@ void sap_mr_kernel(Geom g, BlockGeom B, int colour, int nmr,
                 prev = cur;
         }
     }
-    if (ad.steps && t == 0) ad.steps[blockIdx.x] = nsteps;
+    if (ad.steps && t == 0) ad.steps[blk] = nsteps;
     cx<float> p[12];
     load_spinor<SP>(psis, g.Vh, par, i, p);
 #pragma unroll
@@ -456,15 +458,16 @@ void sap_mr_eo_kernel(Geom g, BlockGeom B, int colour, int nmr,
     __shared__ float rl[24][kBMax];
     __shared__ float hb[4][12][kBMax];
     __shared__ double red[4][3];
-    if (bat.gate && !bat.gate[(long)blockIdx.y * bat.gstride]) return;
-    rs = (char*)rs + blockIdx.y * bat.fstride;
-    psis = (char*)psis + blockIdx.y * bat.fstride;
-    delta = (char*)delta + blockIdx.y * bat.fstride;
+    const int rhs = (int)blockIdx.x % bat.nrhs, blk = (int)blockIdx.x / bat.nrhs;
+    if (bat.gate && !bat.gate[(long)rhs * bat.gstride]) return;
+    rs = (char*)rs + rhs * bat.fstride;
+    psis = (char*)psis + rhs * bat.fstride;
+    delta = (char*)delta + rhs * bat.fstride;
     const int t = threadIdx.x;
     const int nw = B.bvol >> 6;
     int b[4];
     {
-        int r = 2 * blockIdx.x;
+        int r = 2 * blk;
         b[3] = r % B.nb[3]; r /= B.nb[3];
         b[2] = r % B.nb[2]; r /= B.nb[2];
         b[1] = r % B.nb[1];
@@ -694,11 +697,13 @@ __global__ __launch_bounds__(256) void sap_boundary_kernel(Geom g, BlockGeom B, 
                                                            const void* __restrict__ dets,
                                                            RhsStride bat)
 {
-    if (bat.gate && !bat.gate[(long)blockIdx.y * bat.gstride]) return;
-    rs = (char*)rs + blockIdx.y * bat.fstride;
-    delta = (const char*)delta + blockIdx.y * bat.fstride;
+    const int logical = xcd_tile(blockIdx.x, gridDim.x);
+    const int rhs = logical % bat.nrhs, tile = logical / bat.nrhs;
+    if (bat.gate && !bat.gate[(long)rhs * bat.gstride]) return;
+    rs = (char*)rs + rhs * bat.fstride;
+    delta = (const char*)delta + rhs * bat.fstride;
     int par, i;
-    if (!walk_site(g, xcd_tile(blockIdx.x, gridDim.x), threadIdx.x, par, i)) return;
+    if (!walk_site(g, tile, threadIdx.x, par, i)) return;
     int x[4], lex;
     eo_coords(g, par, i, x, lex);
     const int bc = (x[0] / B.bs[0] + x[1] / B.bs[1] + x[2] / B.bs[2] + x[3] / B.bs[3]) & 1;
@@ -721,10 +726,12 @@ __global__ __launch_bounds__(256) void sap_boundary_kernel(Geom g, BlockGeom B, 
 
 template <int SP>
 int cycles_impl(qdw_op* op, const BlockGeom& B, int ncy, int nmr, void* rs, void* psis,
-                void* delta, const RhsStride& bat, int nrhs, bool eo, hipStream_t st)
+                void* delta, const RhsStride& bat_in, int nrhs, bool eo, hipStream_t st)
 {
     const Geom& g = op->g;
-    const dim3 gmr(B.nblk / 2, nrhs), gbd(walk_blocks(g), nrhs);
+    RhsStride bat = bat_in;
+    bat.nrhs = nrhs;
+    const dim3 gmr(B.nblk / 2 * nrhs), gbd(walk_blocks(g) * nrhs);
     for (int cy = 0; cy < ncy; ++cy)
         for (int c = 0; c < 2; ++c) {
             if (eo)
