@@ -194,40 +194,56 @@ struct SiteOps<SP, true> {
     }
 };
 
-// the four in-block hand-overs from this lane's site, then (after a barrier) the four
-// in-block forward hops into it; the caller adds the backward hops after the barrier
-template <int SP>
-__device__ __forceinline__ void push_all(float (*hb)[12][kBMax], const BlockGeom& B,
-                                         const int l[4], int t, const cx<float> src[12],
-                                         SiteOps<SP>& so)
+// w = M h (DAGGER: M^+ h) with the full 3x3 matrix M, for both spin components of h
+template <bool DAGGER>
+__device__ __forceinline__ void mat_mul(const cx<float> m[9], const cx<float> h[6], cx<float> w[6])
 {
-    cx<float> u[6], d;
-    so.opaque();
-    so.template link<0>(u, d);
-    push_backward<SP, 0>(hb, B, l, t, src, u, d);
-    so.template link<1>(u, d);
-    push_backward<SP, 1>(hb, B, l, t, src, u, d);
-    so.template link<2>(u, d);
-    push_backward<SP, 2>(hb, B, l, t, src, u, d);
-    so.template link<3>(u, d);
-    push_backward<SP, 3>(hb, B, l, t, src, u, d);
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        const cx<float> h0 = h[3 * a], h1 = h[3 * a + 1], h2 = h[3 * a + 2];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            if (!DAGGER)
+                w[3 * a + r] = m[3 * r] * h0 + m[3 * r + 1] * h1 + m[3 * r + 2] * h2;
+            else
+                w[3 * a + r] = cmul_conj(m[r], h0) + cmul_conj(m[3 + r], h1) + cmul_conj(m[6 + r], h2);
+        }
+    }
 }
 
-template <int SP>
-__device__ __forceinline__ void forward_all(float (*rl)[kBMax], const BlockGeom& B,
-                                            const int l[4], int t, SiteOps<SP>& so,
-                                            cx<float> vh[12])
+// direction MU of a block-D application for this lane: the hand-over of U^+ (1 + gamma) r
+// to the +MU neighbour (read by it after the barrier) and the forward hop from it, with the
+// link widened and its third row rebuilt once for both
+template <int SP, int MU>
+__device__ __forceinline__ void push_and_forward(float (*hb)[12][kBMax], float (*rl)[kBMax],
+                                                 const BlockGeom& B, const int l[4], int t,
+                                                 const cx<float> r[12], const SiteOps<SP>& so,
+                                                 cx<float> v[12])
 {
-    cx<float> u[6], d;
-    so.opaque();
-    so.template link<0>(u, d);
-    hop_forward<SP, 0>(rl, B, l, t, u, d, vh);
-    so.template link<1>(u, d);
-    hop_forward<SP, 1>(rl, B, l, t, u, d, vh);
-    so.template link<2>(u, d);
-    hop_forward<SP, 2>(rl, B, l, t, u, d, vh);
-    so.template link<3>(u, d);
-    hop_forward<SP, 3>(rl, B, l, t, u, d, vh);
+    if (l[MU] < B.bs[MU] - 1) {
+        cx<float> u[6], d, m[9];
+        so.template link<MU>(u, d);
+        m[6] = d * conj_(u[1] * u[5] - u[2] * u[4]);
+        m[7] = d * conj_(u[2] * u[3] - u[0] * u[5]);
+        m[8] = d * conj_(u[0] * u[4] - u[1] * u[3]);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) m[c] = u[c];
+        const int nb = t + B.lstride[MU];
+        cx<float> h[6], w[6];
+        project<float, MU, +1>(r, h);
+        mat_mul<true>(m, h, w);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            hb[MU][2 * c][nb] = w[c].re;
+            hb[MU][2 * c + 1][nb] = w[c].im;
+        }
+        cx<float> sn[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) sn[c] = {rl[2 * c][nb], rl[2 * c + 1][nb]};
+        project<float, MU, -1>(sn, h);
+        mat_mul<false>(m, h, w);
+        expand_add<float, MU, -1>(w, v);
+    }
 }
 
 // The same hand-over and forward hop with the neighbour's lane given explicitly (-1: the
@@ -348,11 +364,14 @@ void sap_mr_kernel(Geom g, BlockGeom B, int colour, int nmr,
     }
     for (int k = 0; k < nmr && go; ++k) {
         __syncthreads();  // rl holds the current block residual
-        push_all<SP>(hb, B, l, t, r, so);
         cx<float> v[12], vh[12];
 #pragma unroll
         for (int c = 0; c < 12; ++c) vh[c] = {0.f, 0.f};
-        forward_all<SP>(rl, B, l, t, so, vh);
+        so.opaque();
+        push_and_forward<SP, 0>(hb, rl, B, l, t, r, so, vh);
+        push_and_forward<SP, 1>(hb, rl, B, l, t, r, so, vh);
+        push_and_forward<SP, 2>(hb, rl, B, l, t, r, so, vh);
+        push_and_forward<SP, 3>(hb, rl, B, l, t, r, so, vh);
         __syncthreads();  // every pushed half spinor is in hb
         hop_backward<0>(hb, l, t, vh);
         hop_backward<1>(hb, l, t, vh);
