@@ -98,3 +98,37 @@ def test_cascade_workspace_without_gpu(lib):
 def test_schur_entry_points_reject_null_without_gpu(lib):
     assert lib.dw_schur_apply(None, None, None, 0, None) == -1
     assert lib.dw_schur_dag_apply(None, None, None, 0, None) == -1
+
+
+def test_sap_eo_rejects_bad_arguments_without_gpu(lib):
+    import ctypes
+    bs = (ctypes.c_int * 4)(4, 4, 4, 4)
+    rc = lib.sap_eo_apply(None, None, None, 5, 4, ctypes.byref(bs), 2, None, 0, None)
+    assert rc == -1 and b"sap_eo_apply" in lib.qdw_last_error()
+
+
+def test_bench_refuses_several_gpus():
+    """One GPU only: --gpus above 1 exits with a message, before touching a device."""
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_traffic_record_is_consistent_and_current():
+    """The HBM byte count bench.py reports as roofline.traffic: its parts add up, the read
+    bytes are FETCH_SIZE scaled by the calibration factor, and it was taken on the current
+    FP64 D kernel sources in the shape the benchmark times (re-profile after changing them:
+    otherwise the benchmark reports no traffic)."""
+    import json
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    t = json.load(open(bench.TRAFFIC_FILE))
+    assert t["read_bytes"] + t["write_bytes"] == t["bytes_per_launch"]
+    assert t["fetch_scale"] == 2.0
+    assert list(t["shape"]) == list(bench.PINNED_SHAPES["f64"])
+    assert t["kernel_hash"] == bench.kernel_hash()
+    assert bench.measured_traffic(bench.PINNED_SHAPES["f64"]) == t["bytes_per_launch"]
+    # at least the compulsory stored bytes (1216 per site read, one spinor written)
+    assert t["bytes_per_launch"] >= (1216 + 192) * 2 ** 21
