@@ -55,7 +55,7 @@ SAP_M0, SAP_EPS, SAP_SEED = -0.08, 0.35, 7388 + 20
 # D-kernel shapes (ts, nt, pipe, walk, march) at 32^3 x 64, as the autotuner picks them on
 # MI355X (profiles/dw_autotune_32c64.md); pinned so that a kernel trace of this script
 # holds only the timed shape's launches (--autotune picks them live)
-PINNED_SHAPES = {"f64": (64, 32, 0, 0, 1), "f32": (128, 16, 1, 0, 1), "f16": (64, 2, 0, 0, 0)}
+PINNED_SHAPES = {"f64": (64, 32, 0, 0, 1), "f32": (128, 16, 1, 0, 1), "f16": (128, 2, 0, 0, 0)}
 # algorithmic bytes per site of one application of D (each datum read once)
 BYTES_PER_SITE = {"f64": 1376, "f32": 688, "f16": 344}
 # HBM traffic measured with rocprofv3 counters for the FP64 kernel (profiles/); reported

@@ -141,8 +141,8 @@ int qdw_autotune(qdw_op* op, qdw_prec prec, int nrhs, char* report, size_t repor
                  void* stream);
 /* Shapes at qdw_create: FP64 and FP32 march on 64-site tiles with the longest walk chunk
  * (at most 32, dividing T) that still gives at least 512 workgroups (FP64 plain, FP32
- * pipelined hop loop); FP16 / BF16 storage: one workgroup per tile and slice, 128-site
- * tiles, nt the largest divisor of T up to 8.
+ * pipelined hop loop); FP16 / BF16 storage: the plain one-lane-per-site form on 128-site
+ * tiles, nt = 2.
  * Set / read the D kernel's shape for precision prec by hand (ts 64 or 128, nt in 1..64
  * dividing T, pipe 0 or 1, walk 0 or 1, march 0 or 1; shape5 = {ts, nt, pipe, walk,
  * march}); QDW_EINVAL for anything else. */

@@ -116,11 +116,13 @@ __device__ __forceinline__ void compute_k(int k, const Geom& g, const int x[4], 
     }
 }
 
+// One lane per site. With half-precision storage and no software pipelining the kernel
+// fits four waves per SIMD without spilling (123 VGPRs instead of 156 at three), which
+// hides more of the gather latency.
 template <int P, bool DAG, bool PIPE>
-__global__ __launch_bounds__(256) void dw_kernel(Geom g, RhsTable tab, int nrhs,
-                                                 const void* __restrict__ links,
-                                                 const void* __restrict__ dets,
-                                                 const void* __restrict__ clover)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P >= F16S && !PIPE ? 4 : 1)))
+void dw_kernel(Geom g, RhsTable tab, int nrhs, const void* __restrict__ links,
+               const void* __restrict__ dets, const void* __restrict__ clover)
 {
     using R = typename Traits<P>::real;
     const int logical = xcd_tile(blockIdx.x, gridDim.x);

@@ -474,14 +474,8 @@ extern "C" int qdw_create(const qdw_lattice* lat, const double* su3, const doubl
             if (L[0] % d == 0) nt = d;
         set_walk(g, 128, nt, 0);
     }
-    for (int p = 0; p < 4; ++p) {  // defaults; qdw_autotune may change them
-        op->dw_shape[p].ts = g.ts;
-        op->dw_shape[p].nt = g.nt;
-        op->dw_shape[p].pipe = (p == F64 || p == F32) ? 1 : 0;
-        op->dw_shape[p].walk = 0;
-        op->dw_shape[p].march = 0;
-    }
     {
+        // default D-kernel shapes (qdw_autotune or qdw_set_dw_shape may change them).
         // FP64 and FP32: the marching form on 64-site tiles, with the longest walk chunk
         // (at most 32 slices, dividing T) that still gives 512 workgroups, two per CU, so
         // that they march side by side in one round
@@ -494,6 +488,10 @@ extern "C" int qdw_create(const qdw_lattice* lat, const double* su3, const doubl
             }
         op->dw_shape[F64] = {64, nt, 0, 0, 1};
         op->dw_shape[F32] = {64, nt, 1, 0, 1};
+        // half-precision storage: the plain form (one lane per site, four waves per SIMD)
+        // on 128-site tiles in chunks of two slices (T is even)
+        op->dw_shape[F16S] = {128, 2, 0, 0, 0};
+        op->dw_shape[BF16S] = {128, 2, 0, 0, 0};
     }
     op->m0 = m0;
     op->csw = csw;

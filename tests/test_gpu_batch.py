@@ -29,6 +29,22 @@ def ragged():
     return gop, oop, srcs
 
 
+@pytest.mark.parametrize("dims", [(6, 4, 6, 10), (4, 4, 4, 4)])
+def test_default_shapes(dims):
+    """Shapes at creation: FP64 and FP32 march on 64-site tiles (nt = 1 here, where no walk
+    chunk gives 512 workgroups), the half-precision storage forms take the plain form on
+    128-site tiles in chunks of two slices."""
+    su3, th = syn.gauge_field(dims, 0.3, 0.1, 5)
+    op = qdw.Op(dims, su3, th, -0.05, 1.7, -1)
+    try:
+        assert qdw.get_dw_shape(op, "f64") == (64, 1, 0, 0, 1)
+        assert qdw.get_dw_shape(op, "f32") == (64, 1, 1, 0, 1)
+        for prec in ("f16", "bf16"):
+            assert qdw.get_dw_shape(op, prec) == (128, 2, 0, 0, 0)
+    finally:
+        op.close()
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32", "f16", "bf16"])
 def test_multi_rhs_equals_single(ragged, prec):
     import torch
