@@ -482,6 +482,23 @@ __device__ __forceinline__ void nn_apply_m(bool fwd, const cx<float> m[9], const
     }
 }
 
+// one path's 64 x 64 block of the 8-channel layer's weights (bf16), as the fused kernel
+// keeps it in LDS
+constexpr int kWBlock = 64 * 64 * 2;
+typedef __attribute__((address_space(1))) const u32x4 g_cu4;
+
+// the 8-channel layer's weights in the fused kernel's LDS image: for each path p the block
+// of Bt (rows n < 64, columns k = 64 p + 0..63) as [k / 4][n][k % 4], so that one lane's
+// four consecutive k of one column n are 8 contiguous bytes and the 16 lanes of a
+// matrix-core operand row read 128 contiguous bytes
+__global__ void nn_embed_lds_kernel(const uint16_t* Bt, int Kpad, uint16_t* Bl)
+{
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= kPaths * 64 * 64) return;
+    const int e = tid & 3, n = (tid >> 2) & 63, kq = (tid >> 8) & 15, p = tid >> 12;
+    Bl[tid] = Bt[(long)n * Kpad + p * 64 + kq * 4 + e];
+}
+
 // LDS row stride (in bf16 halves) of a tile with KB columns: at least KB + 8, rows 16-byte
 // aligned, and a lane's three rows (the lane-to-lane step of the 16-byte row writes) 4 banks
 // apart modulo the 64 banks, so the 64 lanes of a write hit every bank equally
@@ -528,20 +545,28 @@ __device__ __forceinline__ void nn_put_rows(uint16_t* tile, int sl, int k0, cons
 
 template <int CIN, int COUT, int PIN, int POUT>
 __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, const void* const* in,
-                                                             const void* Bt, void* const* out,
-                                                             const void* links, const void* dets)
+                                                             const void* Bt, const void* Bl,
+                                                             void* const* out, const void* links,
+                                                             const void* dets)
 {
     constexpr int PB = CIN == 1 ? kPaths : 1;          // paths per batch
     constexpr int KB = (PB * CIN * 8 + 15) & ~15;      // columns per batch (80 or 64)
     constexpr int LS = tile_stride(KB);                // LDS row stride (halves)
     constexpr int NT = COUT * 8 >= 16 ? COUT * 8 / 16 : 1;  // 16-column tiles of N
     static_assert(CIN == 1 || CIN == 8, "channel counts of the network");
-    // LDS: the transported tile during the batches, then the output block (COUT channels x
-    // 24 reals x 64 sites, FP32)
-    constexpr int TILE_B = 192 * LS * 2, OUT_B = COUT * 24 * 64 * 4;
-    __shared__ __attribute__((aligned(16))) char lds[TILE_B > OUT_B ? TILE_B : OUT_B];
+    static_assert(CIN == 1 || (KB == 64 && NT == 4), "the LDS weight image is a 64 x 64 block");
+    // LDS: the transported tile during the batches (with Cin = 8 followed by two 8 KiB
+    // buffers for the weight blocks of the current and the next path), then the output
+    // block (COUT channels x 24 reals x 64 sites, FP32)
+    constexpr int TILE_B = 192 * LS * 2, W_B = CIN == 8 ? 2 * kWBlock : 0;
+    constexpr int OUT_B = COUT * 24 * 64 * 4;
+    static_assert(TILE_B % 16 == 0, "weight blocks 16-byte aligned");
+    __shared__ __attribute__((aligned(16))) char lds[TILE_B + W_B > OUT_B ? TILE_B + W_B : OUT_B];
     uint16_t* tile = (uint16_t*)lds;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // Cin = 8: the weight block of path p is in buffer p & 1, as [k/4][n][k%4] (bf16)
+    uint16_t* const wbuf = (uint16_t*)(lds + TILE_B);
+    const uint16_t* wb = wbuf;
     const int Vp = padded(g.Vh);
     const long q0 = nn_block_q0(Vp);
     // this lane's transport site: Cin = 8, the wave's own 16 sites (the rows its matrix-core
@@ -565,7 +590,9 @@ __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, c
             const int kl = kk + 4 * (lane >> 4);
             s4 bf[NT];
             for (int j = 0; j < NT; ++j)
-                bf[j] = *(const s4*)((const uint16_t*)Bt + (long)(j * 16 + (lane & 15)) * Kpad + kglob + kl);
+                bf[j] = CIN == 8
+                            ? *(const s4*)&wb[((kl >> 2) * 64 + j * 16 + (lane & 15)) * 4]
+                            : *(const s4*)((const uint16_t*)Bt + (long)(j * 16 + (lane & 15)) * Kpad + kglob + kl);
             for (int r = 0; r < 3; ++r) {
                 const s4 a = *(const s4*)&tile[(wave * 48 + r * 16 + (lane & 15)) * LS + kl];
                 for (int j = 0; j < NT; ++j)
@@ -579,10 +606,16 @@ __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, c
         // path p + 1 are issued before the work on path p, so a whole path's transport and
         // mixing cover their latency. The stages alternate by name (no indexed arrays).
         struct Stage {
-            uint4 s0[3], s1[3];
+            u32x4 s0[3], s1[3];
             cx<float> u[6], d;
             float sg;
         };
+        // the lane's two channel fields, read from the pointer table once and accessed as
+        // global memory: loads through generic pointers would be flat loads, which may
+        // complete out of order with the LDS accesses, so that every wait in the path loop
+        // would become a wait for all loads in flight, the prefetched ones included
+        const g_cu4* const c0 = (const g_cu4*)in[cg];
+        const g_cu4* const c1 = (const g_cu4*)in[cg + 4];
         auto fetch = [&](int p, Stage& S) {
             int j = i, pp = par;
             S.sg = 1.f;
@@ -591,15 +624,13 @@ __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, c
                 pp = 1 - par;
             }
             const long b0 = chunk_at(g.Vh, 3, pp, 0, j);
-            const uint4* c0 = (const uint4*)in[cg];
-            const uint4* c1 = (const uint4*)in[cg + 4];
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 S.s0[k] = c0[b0 + (long)k * kSB];
                 S.s1[k] = c1[b0 + (long)k * kSB];
             }
         };
-        auto widen = [](const uint4 raw[3], cx<float> s[12]) {
+        auto widen = [](const u32x4 raw[3], cx<float> s[12]) {
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 const uint32_t w[4] = {raw[k].x, raw[k].y, raw[k].z, raw[k].w};
@@ -609,10 +640,35 @@ __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, c
                                     bf16_to_float((uint16_t)(w[q] >> 16))};
             }
         };
+        // the weight block of path p: each of the 256 lanes loads 32 contiguous bytes of it
+        // together with the spinor loads of that path, and stores them into the block's
+        // LDS buffer once the path before it is done (one workgroup barrier per path; the
+        // loads stay in registers meanwhile, in flight during the transport and the
+        // matrix-core step)
+        const int tid = threadIdx.x;
+        auto load_w = [&](int p, u32x4 r[2]) {
+            const g_cu4* src = (const g_cu4*)((const char*)Bl + (long)p * kWBlock) + 2 * tid;
+            r[0] = src[0];
+            r[1] = src[1];
+        };
+        auto store_w = [&](int p, const u32x4 r[2]) {
+            u32x4* dst = (u32x4*)((char*)wbuf + (p & 1) * kWBlock) + 2 * tid;
+            dst[0] = r[0];
+            dst[1] = r[1];
+        };
         // path p0 from stage `cur` while the loads of path p0 + 1 go into `nxt`; the wave
-        // writes and then reads only its own rows of the tile, so it needs no barrier
+        // writes and then reads only its own rows of the tile, so it needs no barrier.
+        // Every lane issues the loads, the lanes of padded sites too (their site index is
+        // below the padded row length and their neighbours are those of site 0, so the
+        // loads stay in bounds; the data are not used): with the same loads in flight on
+        // every path through the code, the compiler waits for exactly the loads an
+        // instruction needs instead of all of them
         auto path = [&](int p0, Stage& cur, Stage& nxt) {
-            if (real && p0 + 1 < kPaths) fetch(p0 + 1, nxt);
+            u32x4 wn[2];
+            if (p0 + 1 < kPaths) {
+                fetch(p0 + 1, nxt);
+                load_w(p0 + 1, wn);
+            }
             if (!real) {
                 nn_put_rows<LS>(tile, sl, cg * 8, zero12);
                 nn_put_rows<LS>(tile, sl, (cg + 4) * 8, zero12);
@@ -636,14 +692,32 @@ __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, c
                 }
             }
             wave_sync();  // the wave's own rows, by its other lanes
+            wb = wbuf + (p0 & 1) * (kWBlock / 2);
             mix((long)p0 * 64);
-            wave_sync();  // its rows are rewritten by the next path
+            if (p0 + 1 < kPaths) {
+                // the next block into the other buffer (last read by every wave before the
+                // previous barrier); the barrier also orders the wave's tile reads above
+                // before its rewrite by the next path
+                store_w(p0 + 1, wn);
+                __syncthreads();
+            }
         };
         Stage SA, SB;
-        if (real) fetch(0, SA);
-        for (int p0 = 0; p0 < kPaths; p0 += 2) {
-            path(p0, SA, SB);
-            if (p0 + 1 < kPaths) path(p0 + 1, SB, SA);
+        {
+            u32x4 w0[2];
+            load_w(0, w0);
+            fetch(0, SA);
+            store_w(0, w0);
+        }
+        __syncthreads();
+        // unrolled for the same reason: the stages alternate by name, and the last path
+        // issues no loads
+#pragma unroll
+        for (int p0 = 0; p0 < kPaths; ++p0) {
+            if (p0 & 1)
+                path(p0, SB, SA);
+            else
+                path(p0, SA, SB);
         }
     } else {
         // paths wave, wave + 4, wave + 8 of the single channel, one batch
@@ -879,6 +953,8 @@ struct NnWork {
     float* dB;                   // [Kmax][Nmax]
     void* mix[kPaths];           // bf16 fields m_p of the last layer's path mixing
     uint16_t* Bm;                // [80][64] bf16: the last layer's mixing matrix
+    uint16_t* Bl;                // [9][16][64][4] bf16: the 8-channel layer's weights as
+                                 // the fused kernel's LDS image
     float** ptrs;                // device pointer tables (8 pointers per slot)
     char* end;
 };
@@ -905,6 +981,7 @@ size_t nn_layout(const qdw_op* op, bool training, char* base, NnWork* W, bool ne
     W->A = need_A || training ? take((size_t)Mp * kMaxK * 4) : nullptr;
     for (int p = 0; p < kPaths; ++p) W->mix[p] = take(spinor_bytes(g, BF16S));
     W->Bm = (uint16_t*)take(80 * 64 * 2);
+    W->Bl = (uint16_t*)take((size_t)kPaths * kWBlock);
     W->dA = training ? (float*)take((size_t)Mp * kMaxK * 4) : nullptr;
     W->G = training ? take((size_t)Mp * kMaxN * 4) : nullptr;
     W->Bt = take((size_t)kMaxN * kMaxK * 4);
@@ -953,10 +1030,15 @@ int forward(qdw_op* op, const float* weights, NnWork& W, hipStream_t st)
             const void* const* pin = (const void* const*)W.ptrs;
             void* const* pout = (void* const*)(W.ptrs + 8);
             if (Cin == 1) {
-                nn_layer_fused_kernel<1, 8, F32, BF16S><<<nb, 256, 0, st>>>(g, Kp, pin, W.Bt, pout, L, D);
+                nn_layer_fused_kernel<1, 8, F32, BF16S><<<nb, 256, 0, st>>>(g, Kp, pin, W.Bt, nullptr,
+                                                                             pout, L, D);
                 QDW_LAUNCH_CHECK();
             } else if (Cout == 8) {
-                nn_layer_fused_kernel<8, 8, BF16S, BF16S><<<nb, 256, 0, st>>>(g, Kp, pin, W.Bt, pout, L, D);
+                nn_embed_lds_kernel<<<(kPaths * 64 * 64 + 255) / 256, 256, 0, st>>>(
+                    (const uint16_t*)W.Bt, Kp, W.Bl);
+                QDW_LAUNCH_CHECK();
+                nn_layer_fused_kernel<8, 8, BF16S, BF16S><<<nb, 256, 0, st>>>(g, Kp, pin, W.Bt, W.Bl,
+                                                                              pout, L, D);
                 QDW_LAUNCH_CHECK();
             } else {
                 // one output channel: mix the paths first, then transport 9 fields
