@@ -2,10 +2,10 @@
  * qdw.h -- C ABI of libqdw: the O(a)-improved Wilson-clover Dirac operator and its
  * solvers on one AMD Instinct MI355X (gfx950).
  *
- * The paper (introduction) names the application of the Dirac operator to a spinor
- * field -- a bandwidth-bound variant of a sparse matrix-vector product -- as one of the
- * most important kernels of lattice field theory, and analyses the two solvers that
- * spend their time in it: the mixed-precision conjugate gradient on the normal
+ * In the paper's introduction, applying the Dirac operator to a spinor field -- a
+ * bandwidth-bound relative of a sparse matrix-vector product -- is a key kernel of
+ * lattice field theory, and the paper analyses the two solvers that spend their time
+ * in it: the mixed-precision conjugate gradient on the normal
  * equations (Sec. 2, cgne) and the Schwarz-alternating-procedure preconditioned flexible
  * GCR (Sec. 3, fgcr with the settings of Table 2). This library provides exactly that
  * path as hand-written HIP kernels.

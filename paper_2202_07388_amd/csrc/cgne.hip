@@ -10,8 +10,8 @@
 // GPU never idles waiting for it.
 //
 // Reset step (Sec. 2 / Fig. 1: triggered once the recursive residual has dropped by an
-// amount of the order of the working type's machine epsilon; computationally more
-// expensive): psi += x_lo / s in FP64, r_hi = eta - D^+ D psi with two FP64 applications
+// amount of the order of the working type's machine epsilon; it costs more than a regular
+// step): psi += x_lo / s in FP64, r_hi = eta - D^+ D psi with two FP64 applications
 // of D, then r = s' r_hi rounded to PL with the new scale s' = sqrt(24 V) / |r_hi|, which
 // keeps FP16-stored components near unit size (Table 1: binary16 has no normal numbers
 // below 6.1e-5). By default the search direction is kept (rescaled) -- a reliable update;
