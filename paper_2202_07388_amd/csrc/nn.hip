@@ -808,7 +808,10 @@ __global__ __launch_bounds__(256) void nn_mix_paths_kernel(Geom g, const void* c
                                                            const uint16_t* Bm, void* const* mix)
 {
     constexpr int KB = 64, LS = tile_stride(KB), NT = 5;
-    constexpr int TILE_B = 192 * LS * 2, OUT_B = 9 * 24 * 64 * 4;
+    // output staging in bf16: one row per (path, 16-byte chunk) of 64 sites x 8 halves,
+    // padded by one chunk so that consecutive rows start 4 banks apart
+    constexpr int ROW = 64 * 8 + 8;
+    constexpr int TILE_B = 192 * LS * 2, OUT_B = 9 * 3 * ROW * 2;
     __shared__ __attribute__((aligned(16))) char lds[TILE_B > OUT_B ? TILE_B : OUT_B];
     uint16_t* tile = (uint16_t*)lds;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -844,8 +847,9 @@ __global__ __launch_bounds__(256) void nn_mix_paths_kernel(Geom g, const void* c
         }
     }
     __syncthreads();
-    // outputs staged as [path][real][site], then written as bf16 chunks
-    float* ob = (float*)lds;
+    // outputs rounded to bf16 (the conversion instruction, as for the other bf16 fields)
+    // and staged as [path][chunk][site][8], then written as 16-byte chunks
+    uint16_t* ob = (uint16_t*)lds;
     for (int r = 0; r < 3; ++r)
         for (int j = 0; j < NT; ++j)
             for (int e = 0; e < 4; ++e) {
@@ -854,18 +858,15 @@ __global__ __launch_bounds__(256) void nn_mix_paths_kernel(Geom g, const void* c
                 if (n >= 72) continue;
                 const int ms = m / 3, c = m - ms * 3;
                 const int p = n >> 3, sp = (n >> 1) & 3, ri = n & 1;
-                ob[(p * 24 + (sp * 3 + c) * 2 + ri) * 64 + ms] = acc[r][j][e];
+                const int k = (sp * 3 + c) * 2 + ri;  // real index within the spinor
+                ob[(p * 3 + (k >> 3)) * ROW + ms * 8 + (k & 7)] =
+                    (uint16_t)(pack_bf16x2(acc[r][j][e], 0.f) & 0xFFFFu);
             }
     __syncthreads();
     for (int u = threadIdx.x; u < 9 * 3 * 64; u += 256) {
         const int p = u / 192, rem = u - p * 192, ch = rem >> 6, site = rem & 63;
         if (i0 + site >= g.Vh) continue;
-        uint4 raw;
-        const float* src = &ob[(p * 24 + ch * 8) * 64 + site];
-        raw.x = pack_bf16x2(src[0], src[64]);
-        raw.y = pack_bf16x2(src[2 * 64], src[3 * 64]);
-        raw.z = pack_bf16x2(src[4 * 64], src[5 * 64]);
-        raw.w = pack_bf16x2(src[6 * 64], src[7 * 64]);
+        const uint4 raw = *(const uint4*)&ob[(p * 3 + ch) * ROW + site * 8];
         ((uint4*)mix[p])[chunk_at(g.Vh, 3, par, ch, i0 + site)] = raw;
     }
 }
