@@ -557,9 +557,13 @@ __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, c
     static_assert(CIN == 1 || (KB == 64 && NT == 4), "the LDS weight image is a 64 x 64 block");
     // LDS: the transported tile during the batches (with Cin = 8 followed by two 8 KiB
     // buffers for the weight blocks of the current and the next path), then the output
-    // block (COUT channels x 24 reals x 64 sites, FP32)
+    // block (COUT channels x 24 reals x 64 sites, bf16)
     constexpr int TILE_B = 192 * LS * 2, W_B = CIN == 8 ? 2 * kWBlock : 0;
-    constexpr int OUT_B = COUT * 24 * 64 * 4;
+    // output staging in bf16: one row per (channel, 16-byte chunk) of 64 sites x 8 halves,
+    // padded by one chunk so that consecutive rows start 4 banks apart
+    static_assert(POUT == BF16S, "the layers' outputs are bf16 hidden channels");
+    constexpr int OROW = 64 * 8 + 8;
+    constexpr int OUT_B = COUT * 3 * OROW * 2;
     static_assert(TILE_B % 16 == 0, "weight blocks 16-byte aligned");
     __shared__ __attribute__((aligned(16))) char lds[TILE_B + W_B > OUT_B ? TILE_B + W_B : OUT_B];
     uint16_t* tile = (uint16_t*)lds;
@@ -748,10 +752,11 @@ __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, c
         mix(0);
     }
     __syncthreads();  // the output block below reuses the tile
-    // outputs: row m = 3 * site + c, column n = (a * 4 + s) * 2 + re/im, staged in LDS as
-    // [channel][real][site] (the 64 sites are one aligned block of one parity), then
-    // written in the output precision as contiguous 16-byte chunks
-    float* ob = (float*)lds;
+    // outputs: row m = 3 * site + c, column n = (a * 4 + s) * 2 + re/im, rounded to bf16
+    // (the conversion instruction) and staged in LDS as [channel][chunk][site][8] (the 64
+    // sites are one aligned block of one parity; rows padded as in the tile), then written
+    // as 16-byte chunks
+    uint16_t* ob = (uint16_t*)lds;
     for (int r = 0; r < 3; ++r)
         for (int j = 0; j < NT; ++j)
             for (int e = 0; e < 4; ++e) {
@@ -760,22 +765,17 @@ __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, c
                 const int ms = m / 3, c = m - ms * 3;
                 const int a = n >> 3, sp = (n >> 1) & 3, ri = n & 1;
                 if (a >= COUT) continue;
-                ob[(a * 24 + (sp * 3 + c) * 2 + ri) * 64 + ms] = acc[r][j][e];
+                const int k = (sp * 3 + c) * 2 + ri;  // real index within the spinor
+                ob[(a * 3 + (k >> 3)) * OROW + ms * 8 + (k & 7)] =
+                    (uint16_t)(pack_bf16x2(acc[r][j][e], 0.f) & 0xFFFFu);
             }
     __syncthreads();
-    using T = Traits<POUT>;
-    constexpr int NC = T::SPIN_CHUNKS, PC = T::PER_CHUNK;
     const int opar = (int)(q0 / Vp), oi0 = (int)(q0 - (long)opar * Vp);
-    for (int u = threadIdx.x; u < COUT * NC * 64; u += 256) {
-        const int a = u / (NC * 64), rem = u - a * (NC * 64), ch = rem >> 6, site = rem & 63;
+    for (int u = threadIdx.x; u < COUT * 3 * 64; u += 256) {
+        const int a = u / 192, rem = u - a * 192, ch = rem >> 6, site = rem & 63;
         if (oi0 + site >= g.Vh) continue;
-        Chunk<POUT> cval;
-#pragma unroll
-        for (int j = 0; j < PC; ++j)
-            cval.v[j] = to_store<POUT>((typename T::real)ob[(a * 24 + ch * PC + j) * 64 + site]);
-        uint4 raw;
-        __builtin_memcpy(&raw, &cval, 16);
-        ((uint4*)out[a])[chunk_at(g.Vh, NC, opar, ch, oi0 + site)] = raw;
+        const uint4 raw = *(const uint4*)&ob[(a * 3 + ch) * OROW + site * 8];
+        ((uint4*)out[a])[chunk_at(g.Vh, 3, opar, ch, oi0 + site)] = raw;
     }
 }
 
