@@ -574,8 +574,9 @@ __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, c
     const int Vp = padded(g.Vh);
     const long q0 = nn_block_q0(Vp);
     // this lane's transport site: Cin = 8, the wave's own 16 sites (the rows its matrix-core
-    // products read), four lanes per site, channels cg and cg + 4 per lane, so no wave waits
-    // for another between the batches; Cin = 1, all 64 sites, paths split over the waves
+    // products read), four lanes per site, channels cg and cg + 4 per lane, so a wave's
+    // transport and products need no other wave (the workgroup meets once per path, for
+    // the shared weight block); Cin = 1, all 64 sites, paths split over the waves
     const int sl = CIN == 8 ? wave * 16 + (lane & 15) : lane;
     const int cg = lane >> 4;
     const long qs = q0 + sl;
@@ -661,8 +662,8 @@ __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, c
             dst[1] = r[1];
         };
         // path p0 from stage `cur` while the loads of path p0 + 1 go into `nxt`; the wave
-        // writes and then reads only its own rows of the tile, so it needs no barrier.
-        // Every lane issues the loads, the lanes of padded sites too (their site index is
+        // writes and then reads only its own rows of the tile, so a wave-level sync orders
+        // them. Every lane issues the loads, the lanes of padded sites too (their site index is
         // below the padded row length and their neighbours are those of site 0, so the
         // loads stay in bounds; the data are not used): with the same loads in flight on
         // every path through the code, the compiler waits for exactly the loads an
