@@ -121,6 +121,23 @@ def test_periodic_time_plane_wave():
 
 # ----------------------------------------------------------------- gamma5, gauge
 
+@pytest.mark.parametrize("dims, bc", [((4, 4, 4, 4), -1), ((6, 4, 4, 6), 1), ((6, 4, 4, 6), -1)])
+def test_dw_at_sites_equals_full_operator(dims, bc):
+    """The per-site evaluation used to sample large lattices (its own stencil and clover
+    code) agrees with the full operator at every site."""
+    su3, th = syn.gauge_field(dims, 0.3, 0.1, 7388 + dims[0])
+    op = oracle.Operator(dims, su3, th, -0.05, 1.7, bc)
+    psi = syn.gaussian_spinor(dims, 50)
+    want = op.dw(psi)
+    sites = np.arange(op.V)
+    got = oracle.dw_at_sites(dims, bc, op.u, -0.05, 1.7, psi, sites)
+    assert np.abs(got - want).max() <= 1e-14 * np.abs(want).max()
+    # and on a scattered subset, in a scrambled order
+    sub = np.random.default_rng(1).permutation(op.V)[:37]
+    got = oracle.dw_at_sites(dims, bc, op.u, -0.05, 1.7, psi, sub)
+    assert np.abs(got - want[sub]).max() <= 1e-14 * np.abs(want).max()
+
+
 def test_gamma5_hermiticity(op44):
     x = syn.gaussian_spinor(D44, 11)
     y = syn.gaussian_spinor(D44, 12)
@@ -388,9 +405,137 @@ def test_adaptive_sap_exit_rules(op44):
     assert all(np.all((s >= 1) & (s <= 20)) for s in steps)
     r = np.linalg.norm(rho - op44.dw(psi))
     assert r < np.linalg.norm(rho)
-    # a huge tolerance makes every block exit at once (rule 3): nothing is done
+    # a huge tolerance makes every block exit at once (rule 3): nothing is done, so the first
+    # cycle leaves |r| unchanged and the cycle exit (a cycle that did not lower |r|) fires
+    # after exactly one cycle; a strict comparison (|r| grew) would run all 20
     psi0, c0, s0 = oracle.sap_adaptive(op44, rho, BS2, 20, 20, 0.9, 1e30)
     assert c0 == 1 and np.abs(psi0).max() == 0 and all(np.all(s == 0) for s in s0)
+
+
+def test_adaptive_sap_without_exits_is_plain_sap(op44):
+    """With alpha so large that exit (1) never fires and tol = 0, adaptive SAP runs every
+    block for nmr_max MR steps in every cycle (MR never raises the block residual, so exit (2)
+    stays off) as long as each cycle lowers |r|: it is the plain SAP of Sec. 3, which the
+    block Gauss-Seidel pin fixes."""
+    rho = syn.gaussian_spinor(D44, 37)
+    psi, cycles, steps = oracle.sap_adaptive(op44, rho, BS2, 3, 6, 1e300, 0.0)
+    assert cycles == 3 and all(np.all(s == 6) for s in steps)
+    want = oracle.sap(op44, rho, BS2, 3, 6)
+    assert np.abs(psi - want).max() <= 1e-13 * np.abs(want).max()
+
+
+@pytest.mark.parametrize("nmr_max, expect", [(10, 4), (3, 3)])
+def test_adaptive_sap_alpha_zero_stops_after_four_steps(op44, nmr_max, expect):
+    """alpha = 0 makes exit (1) fire at the first step it may look at, which Sec. 3.2 puts
+    after at least four MR steps: every block takes exactly 4 steps (or nmr_max if smaller),
+    so the application equals plain SAP with nmr = 4 (or nmr_max)."""
+    rho = syn.gaussian_spinor(D44, 38)
+    psi, cycles, steps = oracle.sap_adaptive(op44, rho, BS2, 2, nmr_max, 0.0, 0.0)
+    assert cycles == 2 and all(np.all(s == expect) for s in steps)
+    want = oracle.sap(op44, rho, BS2, 2, expect)
+    assert np.abs(psi - want).max() <= 1e-13 * np.abs(want).max()
+
+
+def _block_norms(v, bid, nblk):
+    return np.sqrt(np.bincount(bid, weights=np.sum(np.abs(v) ** 2, axis=(1, 2)), minlength=nblk))
+
+
+def _stop_steps(hist, alpha, tol, nmr_max):
+    """Sec. 3.2 exit rules applied to one block's MR residual history hist[0..nmr_max]
+    (hist[0] the norm before the first step): the step count at which the block stops."""
+    if hist[0] < tol:
+        return 0
+    for k in range(1, nmr_max + 1):
+        if (k >= 4 and hist[k] > alpha * hist[k - 1]) or hist[k] > hist[k - 1] or hist[k] < tol:
+            return k
+    return nmr_max
+
+
+def _colour_by_rules(op, r, colour, alpha, tol, nmr_max, bid, col, nblk):
+    """Block solves of one colour built from the MR iteration of mr_blocks (pinned by the
+    closed form of one MR step): each block's stop step comes from its own residual history
+    under the exit rules, and its correction is that of mr_blocks run for exactly that many
+    steps. Returns the correction, the steps per block of the colour, and the smallest
+    distance of a step ratio from alpha (so that the test can refuse knife-edge cases)."""
+    blocks = np.unique(bid[col == colour])
+    _, _, norms = oracle.mr_blocks(op, r, BS2, colour, nmr_max, bid, col, nblk, history=True)
+    hist = np.array([_block_norms(np.where((col == colour)[:, None, None], r, 0), bid, nblk)]
+                    + list(norms))
+    steps = np.array([_stop_steps(hist[:, b], alpha, tol, nmr_max) for b in blocks])
+    margin = np.inf
+    for b in blocks:
+        if hist[0, b] > 0:
+            margin = min(margin, np.abs(hist[1:, b] / hist[:-1, b] - alpha).min())
+    chi = np.zeros_like(r)
+    for s in np.unique(steps):
+        if s == 0:
+            continue
+        part, _ = oracle.mr_blocks(op, r, BS2, colour, int(s), bid, col, nblk)
+        sel = np.isin(bid, blocks[steps == s])[:, None, None]
+        chi = chi + np.where(sel, part, 0)
+    return chi, steps, margin
+
+
+@pytest.mark.parametrize("alpha, tol_from", [(0.42, None), (0.42, 2), (0.9, 3)])
+def test_adaptive_sap_steps_follow_the_exit_rules(op44, alpha, tol_from):
+    """One cycle of adaptive SAP against the Sec. 3.2 rules applied to independently
+    computed MR histories: exit (1) after at least 4 steps when |r_b| > alpha times its value
+    one step before, (2) when |r_b| grew, (3) when |r_b| < tol; blocks below tol at the start
+    take no step. The cases make blocks stop at different steps through rules (1) and (3);
+    reading 'previous' as the block's initial residual, or requiring 5 steps, changes them."""
+    rho = syn.gaussian_spinor(D44, 36)
+    bid, col, nblk = oracle.block_ids(D44, BS2)
+    rho = np.where((bid == np.unique(bid[col == 0])[1])[:, None, None], 0, rho)  # one empty block
+    nmr_max = 12
+    tol = 0.0
+    if tol_from is not None:
+        # tol between the block residuals after step tol_from: rule (3) stops some blocks early
+        _, _, norms = oracle.mr_blocks(op44, rho, BS2, 0, nmr_max, bid, col, nblk, history=True)
+        used = np.unique(bid[col == 0])
+        h = norms[tol_from - 1][used]
+        h = h[h > 0]
+        tol = float(np.median(h))
+    chi0, s0, m0 = _colour_by_rules(op44, rho, 0, alpha, tol, nmr_max, bid, col, nblk)
+    r1 = rho - op44.dw(chi0)
+    chi1, s1, m1 = _colour_by_rules(op44, r1, 1, alpha, tol, nmr_max, bid, col, nblk)
+    assert min(m0, m1) > 1e-6  # no step ratio sits on the threshold
+    steps_all = np.concatenate([s0, s1])
+    assert (0 in s0) == (tol > 0)                    # the empty block (rule 3 at the start)
+    assert len(np.unique(steps_all)) >= 3            # the rules act differently per block
+    if tol_from is None:
+        assert 4 in steps_all and np.any(steps_all > 4)
+    else:
+        assert np.any((steps_all > 0) & (steps_all < 4))  # rule (3) before rule (1) may act
+    psi, cycles, steps = oracle.sap_adaptive(op44, rho, BS2, 1, nmr_max, alpha, tol)
+    assert cycles == 1
+    assert np.array_equal(steps[0], s0) and np.array_equal(steps[1], s1)
+    want = chi0 + chi1
+    assert np.abs(psi - want).max() <= 1e-12 * np.abs(want).max()
+
+
+@pytest.mark.parametrize("m0", [-0.8, -1.5])
+def test_adaptive_sap_cycles_stop_when_residual_does_not_drop(m0):
+    """Sec. 3.2: the application stops after the first Schwarz cycle that did not lower |r|.
+    With the MR exits switched off (alpha huge, tol 0) each cycle is a plain SAP cycle, so
+    the expected cycle count is read off the residual norms of plain SAP with 1, 2, ...
+    cycles (pinned by block Gauss-Seidel); for these strongly negative masses SAP stops
+    converging, at cycle 3 (m0 = -0.8) or already at cycle 2 (m0 = -1.5). The cycle that
+    raised |r| is kept, as the exit rules keep the MR step that triggered them."""
+    op = _op(D44, m0=m0)
+    rho = syn.gaussian_spinor(D44, 40)
+    prev = np.linalg.norm(rho)
+    expect = None
+    for c in range(1, 10):
+        n = np.linalg.norm(rho - op.dw(oracle.sap(op, rho, BS2, c, 4)))
+        if n >= prev:
+            expect = c
+            break
+        prev = n
+    assert expect == {-0.8: 3, -1.5: 2}[m0]
+    psi, cycles, steps = oracle.sap_adaptive(op, rho, BS2, 10, 4, 1e300, 0.0)
+    assert cycles == expect and all(np.all(s == 4) for s in steps)
+    want = oracle.sap(op, rho, BS2, expect, 4)
+    assert np.abs(psi - want).max() <= 1e-12 * np.abs(want).max()
 
 
 # ----------------------------------------------------------------- network
@@ -432,6 +577,48 @@ def test_nn_transport_reproduces_hopping_term(opn):
         hop -= 0.5 * spin(np.eye(4) + g[mu], oracle.nn_transport(opn, psi, 2 + 2 * mu))
     diag = np.einsum("xij,xj->xi", opn.A, psi.reshape(-1, 12)).reshape(psi.shape)
     assert np.abs(opn.dw(psi) - (diag + hop)).max() < 1e-13
+
+
+def dirac_weights(m0, route=(3, 5)):
+    """Network weights whose three layers multiply by D at c_sw = 0: layer 1 copies the input
+    into channel route[0] (identity path), layer 2 maps channel route[0] to channel route[1]
+    with W_0 = (4 + m0) 1, W_{+mu} = -1/2 (1 - gamma_mu), W_{-mu} = -1/2 (1 + gamma_mu), and
+    layer 3 copies channel route[1] to the output."""
+    g = oracle.gamma()
+    a, b = route
+    W1 = np.zeros((oracle.NPATH, 8, 1, 4, 4), dtype=np.complex128)
+    W2 = np.zeros((oracle.NPATH, 8, 8, 4, 4), dtype=np.complex128)
+    W3 = np.zeros((oracle.NPATH, 1, 8, 4, 4), dtype=np.complex128)
+    W1[0, a, 0] = np.eye(4)
+    W2[0, b, a] = (4.0 + m0) * np.eye(4)
+    for mu in range(4):
+        W2[1 + 2 * mu, b, a] = -0.5 * (np.eye(4) - g[mu])
+        W2[2 + 2 * mu, b, a] = -0.5 * (np.eye(4) + g[mu])
+    W3[0, 0, b] = np.eye(4)
+    return [W1, W2, W3]
+
+
+@pytest.mark.parametrize("bc", [-1, 1])
+def test_nn_with_dirac_weights_is_the_operator(bc):
+    """With the weights of dirac_weights the network is the Wilson operator without clover
+    term, written independently in oracle.c: this fixes the spin index order of the weight
+    matrices (gamma_1, gamma_3 are not symmetric), the direction and boundary sign of each
+    transport path, and which index of W is the output channel (the copy goes through
+    channels 3 and 5, so swapped channel indices give zero)."""
+    dims = (4, 2, 4, 6)
+    su3, th = syn.gauge_field(dims, 0.3, 0.1, 46)
+    op = oracle.Operator(dims, su3, th, -0.05, 0.0, bc)
+    r = syn.gaussian_spinor(dims, 10)
+    out, _ = oracle.nn_forward(op, dirac_weights(-0.05), r)
+    want = op.dw(r)
+    assert np.abs(out - want).max() <= 1e-13 * np.abs(want).max()
+    # gamma_5 D gamma_5 = D^+ with the projector signs swapped
+    Wd = dirac_weights(-0.05)
+    for p in range(1, oracle.NPATH):
+        Wd[1][p, 5, 3] = -np.eye(4) - Wd[1][p, 5, 3]  # -1/2 (1 -+ g) -> -1/2 (1 +- g)
+    out, _ = oracle.nn_forward(op, Wd, r)
+    want = op.dw_dag(r)
+    assert np.abs(out - want).max() <= 1e-13 * np.abs(want).max()
 
 
 def test_nn_linear_and_equivariant():
