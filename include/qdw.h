@@ -75,18 +75,33 @@ typedef struct qdw_op qdw_op; /* opaque: compressed links and clover, all precis
 /* Message of the last error on this thread ("" if none). */
 const char* qdw_last_error(void);
 
-/* Build an operator on the current device.
+/* Device and host bytes an operator on lattice `lat` keeps: qdw_op_device_bytes(lat) for
+ * the compressed links and clover blocks (and their inverses) in all four precisions and
+ * the reduction scratch, about 3.2 kB per site (6.8 GB at 32^3 x 64); 0 for an invalid
+ * lattice.
+ * qdw_op_host_bytes() for the scalars the host reads back (8 kB). */
+size_t qdw_op_device_bytes(const qdw_lattice* lat);
+size_t qdw_op_host_bytes(void);
+
+/* Build an operator on the current device in memory the caller provides.
  *  su3   (device) complex128 [V][4][3][3], canonical site order: SU(3) part of U_mu(x)
  *  theta (device) float64 [V][4]: U(1) angle of U_mu(x)
  *  m0, csw: bare mass and Sheikholeslami-Wohlert coefficient.
- * Checks that every su3 matrix is unitary with unit determinant to 1e-10
+ *  dev_mem (device) at least qdw_op_device_bytes(lat) bytes, any alignment;
+ *  host_mem (host) at least qdw_op_host_bytes() bytes, pinned (hipHostMalloc or a pinned
+ *  torch tensor) so that the solvers' scalar read-backs overlap with device work.
+ * Both blocks stay owned by the caller, must outlive the operator, and are used by it
+ * alone; the library allocates no memory of its own (the opaque qdw_op handle is a small
+ * host struct). Checks that every su3 matrix is unitary with unit determinant to 1e-10
  * (QDW_ENOTUNITARY otherwise), then stores the two-row compressed links and builds the
  * clover blocks A_+-(x) in FP64 (Sec. 1 names O(a)-improved Wilson fermions); FP32,
- * FP16 and BF16 copies are derived by rounding to nearest even. The op owns its device
- * memory (about 1.5 kB per site) until qdw_destroy. The input buffers may be freed
- * once this call has returned (it synchronises `stream`). */
+ * FP16 and BF16 copies are derived by rounding to nearest even. QDW_EWORKSPACE when a
+ * block is too small. The input buffers may be freed once this call has returned (it
+ * synchronises `stream`). */
 int qdw_create(const qdw_lattice* lat, const double* su3, const double* theta, double m0,
-               double csw, void* stream, qdw_op** out);
+               double csw, void* dev_mem, size_t dev_bytes, void* host_mem, size_t host_bytes,
+               void* stream, qdw_op** out);
+/* Releases the handle (after a device synchronisation); the caller then frees its blocks. */
 int qdw_destroy(qdw_op* op);
 
 /* Number of lattice sites, and bytes of one eo-SoA spinor field in precision `prec`. */
@@ -123,6 +138,9 @@ int dw_schur_dag_apply(qdw_op* op, const void* in, void* out, qdw_prec prec, voi
 int dw_apply_multi(qdw_op* op, const void* const* in, void* const* out, int nrhs,
                    qdw_prec prec, void* stream);
 
+/* Device scratch (bytes) qdw_autotune needs: two fields of precision prec per right-hand
+ * side. 0 on bad arguments. */
+size_t qdw_autotune_workspace_bytes(const qdw_op* op, qdw_prec prec, int nrhs);
 /* Autotuner of the D kernel for this operator (not from the paper): times every shape --
  * workgroup size (64 or 128 sites per parity), walk chunk (1, 2, 4, ..., 64 time slices,
  * dividing T), hop-loop form (plain or software-pipelined), tile order (walk 0: tiles of a
@@ -134,11 +152,13 @@ int dw_apply_multi(qdw_op* op, const void* const* in, void* const* out, int nrhs
  * dw_apply_multi and the solvers from then on), and writes a one-line report (best shape,
  * then every candidate's time in ms as [ts,nt,pipe,walk,march]=ms) to report (host, may be
  * NULL). Times on two scratch fields per right-hand side filled with a fixed non-zero
- * pattern (allocated and freed here); synchronises the stream. Results do not depend on
+ * pattern, in work (device, qdw_autotune_workspace_bytes bytes, clobbered); the two timing
+ * events it creates are destroyed before it returns; synchronises the stream. Results do
+ * not depend on
  * ts, nt or walk; the hop-loop forms and the marching form are separately compiled and
  * may differ in the last bit. */
-int qdw_autotune(qdw_op* op, qdw_prec prec, int nrhs, char* report, size_t report_len,
-                 void* stream);
+int qdw_autotune(qdw_op* op, qdw_prec prec, int nrhs, void* work, size_t work_bytes,
+                 char* report, size_t report_len, void* stream);
 /* Shapes at qdw_create: FP64 and FP32 march on 64-site tiles with the longest walk chunk
  * (at most 32, dividing T) that still gives at least 512 workgroups (FP64 plain, FP32
  * pipelined hop loop); FP16 / BF16 storage: the plain one-lane-per-site form on 128-site
@@ -278,16 +298,32 @@ int sap_gcr_solve(qdw_op* op, const void* eta, void* psi, const qdw_sap_gcr_para
  * repeat: the right-hand sides of one operator are solved together; operators may have
  * different lattice volumes), all with settings p (precond QDW_PRECOND_NONE,
  * QDW_PRECOND_SAP or QDW_PRECOND_SAP_EO). Each solve takes the same steps, with the same
- * arithmetic, as
- * sap_gcr_solve on its own; all convergence decisions are made on the device, one
- * restart cycle (nkv steps + restart step) of the whole batch is captured once as a HIP
- * graph and replayed until every solve has finished (the host waits once per replay).
- * etas, psis: host arrays of n device FP64 eo-SoA fields (psi distinct from each other and
- * from every eta); work: device scratch of qdw_sap_gcr_batched_workspace_bytes bytes;
- * infos: n results (host; t_sec = wall time of the whole batch); graph_ms (host, may be
- * NULL): time to capture and instantiate the graph. Synchronises with the stream. */
+ * arithmetic, as sap_gcr_solve on its own; all convergence decisions are made on the
+ * device, and finished solves are gated off by flags the kernels read on entry.
+ *
+ * A batch plan captures `cycles` restart cycles (nkv steps and the restart step each) of
+ * the whole batch once, as one HIP graph whose branches are the operators' groups, in
+ * the caller's workspace `work` (device, qdw_sap_gcr_batched_workspace_bytes bytes; the
+ * plan keeps using it until destroyed). The plan owns 1 + (number of operators) HIP
+ * streams and as many events, used only to capture, and the graph; it allocates no
+ * memory. A solve with the plan launches the graph on the caller's stream until every
+ * solve has finished, reading the flags after each launch: one launch and one host wait
+ * when `cycles` cycles suffice. etas, psis: host arrays of n device FP64 eo-SoA fields
+ * (psi distinct from each other and from every eta); infos: n results (host; t_sec = wall
+ * time of the solve call); launches (host, may be NULL): graph launches made. The same
+ * plan serves any number of solves (one at a time). qdw_batch_capture_ms: time taken to
+ * capture and instantiate the graph. */
+typedef struct qdw_batch qdw_batch;
 size_t qdw_sap_gcr_batched_workspace_bytes(qdw_op* const* ops, int n,
                                            const qdw_sap_gcr_params* p);
+int qdw_batch_create(qdw_op* const* ops, int n, const qdw_sap_gcr_params* p, int cycles,
+                     void* work, size_t work_bytes, qdw_batch** out);
+int qdw_batch_solve(qdw_batch* b, const void* const* etas, void* const* psis, qdw_info* infos,
+                    int* launches, void* stream);
+double qdw_batch_capture_ms(const qdw_batch* b);
+int qdw_batch_destroy(qdw_batch* b);
+/* One-shot form: a plan of one cycle per launch, one solve, the plan destroyed; graph_ms
+ * (host, may be NULL) receives its capture time. */
 int sap_gcr_solve_batched(qdw_op* const* ops, const void* const* etas, void* const* psis, int n,
                           const qdw_sap_gcr_params* p, void* work, size_t work_bytes,
                           qdw_info* infos, double* graph_ms, void* stream);

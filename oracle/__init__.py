@@ -672,6 +672,59 @@ def nn_loss(op: Operator, weights, r, e):
     return _norm(d) ** 2 / ne2, d / ne2, acts
 
 
+def nn_at_sites(dims, bc_t, u, weights, r, sites):
+    """N(r) at the listed lexicographic sites only ([n, 4, 3]), for lattices too large for a
+    full oracle pass. Layer l's output at x needs its input at x and x +- mu, so the three
+    layers are evaluated on the sites within 0, 1, 2 hops of the requested ones, and the
+    input is read within 3 hops. Transport as in nn_transport: path 1 + 2 mu is
+    s U_mu(x) v(x + mu), path 2 + 2 mu is s U_mu(x - mu)^+ v(x - mu), s = bc_t on hops across
+    the time boundary. u: the [V, 4, 3, 3] links; r: the [V, 4, 3] input."""
+    dims = tuple(int(d) for d in dims)
+    T = dims[0]
+    strides = (dims[1] * dims[2] * dims[3], dims[2] * dims[3], dims[3], 1)
+    r = np.asarray(r).reshape(-1, 4, 3)
+
+    def coords(lex):
+        return [(lex // strides[m]) % dims[m] for m in range(4)]
+
+    def shift(lex, mu, step):
+        x = coords(lex)
+        y = (x[mu] + step) % dims[mu]
+        return lex + (y - x[mu]) * strides[mu]
+
+    def grow(sites_):
+        allp = [sites_]
+        for mu in range(4):
+            allp += [shift(sites_, mu, 1), shift(sites_, mu, -1)]
+        return np.unique(np.concatenate(allp))
+
+    out_sites = np.asarray(sites, dtype=np.int64)
+    need = [np.unique(out_sites)]
+    for _ in range(3):
+        need.append(grow(need[-1]))
+    # need[3]: input sites, need[2]: layer-1 outputs, need[1]: layer-2, need[0]: layer-3
+    x_sites = need[3]
+    x = r[x_sites][None]  # [Cin = 1, n, 4, 3]
+    for l, W in enumerate(weights):
+        o_sites = need[2 - l]
+        pos = lambda q: np.searchsorted(x_sites, q)
+        t = np.empty((9, x.shape[0], len(o_sites), 4, 3), dtype=np.complex128)
+        t[0] = x[:, pos(o_sites)]
+        xo = coords(o_sites)
+        for mu in range(4):
+            fw = shift(o_sites, mu, 1)
+            bw = shift(o_sites, mu, -1)
+            sf = np.where((mu == 0) & (xo[0] == T - 1), bc_t, 1.0)
+            sb = np.where((mu == 0) & (xo[0] == 0), bc_t, 1.0)
+            Uf = u[o_sites, mu]
+            Ub = np.conj(np.swapaxes(u[bw, mu], -1, -2))
+            t[1 + 2 * mu] = sf[None, :, None, None] * np.einsum("nij,bnsj->bnsi", Uf, x[:, pos(fw)])
+            t[2 + 2 * mu] = sb[None, :, None, None] * np.einsum("nij,bnsj->bnsi", Ub, x[:, pos(bw)])
+        x = np.einsum("pabst,pbntc->ansc", W, t)
+        x_sites = o_sites
+    return x[0][np.searchsorted(x_sites, out_sites)]
+
+
 def nn_identity_weights(channels=(1, 8, 8, 1), seed=None, scale=0.0):
     """Weights whose network is the identity map: layer l maps channel 0 to channel 0
     through the identity path with the 4x4 unit spin matrix; optional small noise."""

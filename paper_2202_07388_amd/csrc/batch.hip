@@ -1,5 +1,5 @@
-// batch.hip -- many SAP-GCR solves at once, over lattices of different volumes, with one
-// GCR cycle of the whole batch captured as a single HIP graph.
+// batch.hip -- many SAP-GCR solves at once, over lattices of different volumes, with
+// several GCR restart cycles of the whole batch captured once as a single HIP graph.
 //
 // The solves follow the flexible GCR of the paper (Sec. 3.1, settings of Table 2) step for
 // step, exactly as sap_gcr_solve runs them for one right-hand side; what changes is who
@@ -8,9 +8,11 @@
 // end of the solve) is taken here by small device kernels that read the per-right-hand-side
 // scalars and set per-right-hand-side flags. Every kernel of a step checks its right-hand
 // side's flag on entry and returns at once when that solve has left the cycle, so the
-// same captured sequence serves every right-hand side whatever its progress: the host
-// replays the graph once per cycle (nkv steps + the restart step) and waits once per
-// replay, to read the flags.
+// same captured sequence serves every right-hand side whatever its progress. A batch plan
+// (qdw_batch) captures `cycles` restart cycles (nkv steps + the restart step each) once;
+// a solve launches that graph on the caller's stream and waits once per launch, to read
+// the flags, so a batch that finishes within `cycles` cycles takes one launch and one
+// host wait, and the plan is reused by every later solve of the same batch shape.
 //
 // Right-hand sides that share an operator form a group. A group's fields are stored
 // right-hand-side-fastest at a fixed byte stride and every kernel covers all of them
@@ -20,6 +22,7 @@
 // lattice fill the machine next to those of a large one.
 #include <chrono>
 #include <cmath>
+#include <memory>
 #include <vector>
 
 #include "sap.h"
@@ -587,30 +590,35 @@ int check_params(const qdw_sap_gcr_params* p)
     return QDW_OK;
 }
 
-struct Resources {
-    hipStream_t cs = nullptr;
-    std::vector<hipStream_t> side;
-    std::vector<hipEvent_t> ev;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    int* host_flags = nullptr;
-    double* host_sc = nullptr;
-    ~Resources()
-    {
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
-        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
-        for (hipStream_t s : side) (void)hipStreamDestroy(s);
-        if (cs) (void)hipStreamDestroy(cs);
-        if (host_flags) (void)hipHostFree(host_flags);
-        if (host_sc) (void)hipHostFree(host_sc);
-    }
-};
-
 }  // namespace
 }  // namespace qdw
 
 using namespace qdw;
+
+// A captured batch: its groups carved out of the caller's workspace, the HIP streams and
+// events used to capture the groups as parallel branches, and the instantiated graph of
+// `cycles` restart cycles of every group.
+struct qdw_batch {
+    std::vector<Group> gs;
+    qdw_sap_gcr_params p;
+    std::vector<qdw_op*> ops;
+    int n = 0, cycles = 0, device = 0, nflags = 0;
+    int* fl0 = nullptr;             // the flags of all groups form one array starting here
+    hipStream_t cs = nullptr;       // capture stream
+    std::vector<hipStream_t> side;  // one per group (capture only)
+    std::vector<hipEvent_t> ev;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    double capture_ms = 0.0;
+    ~qdw_batch()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        for (hipStream_t x : side) (void)hipStreamDestroy(x);
+        if (cs) (void)hipStreamDestroy(cs);
+    }
+};
 
 extern "C" size_t qdw_sap_gcr_batched_workspace_bytes(qdw_op* const* ops, int n,
                                                       const qdw_sap_gcr_params* p)
@@ -620,6 +628,158 @@ extern "C" size_t qdw_sap_gcr_batched_workspace_bytes(qdw_op* const* ops, int n,
     size_t bytes = 0;
     if (plan(ops, n, *p, nullptr, &gs, &bytes)) return 0;
     return bytes;
+}
+
+extern "C" int qdw_batch_create(qdw_op* const* ops, int n, const qdw_sap_gcr_params* p,
+                                int cycles, void* work, size_t work_bytes, qdw_batch** out)
+{
+    QDW_CHECK(ops && p && work && out, QDW_EINVAL, "qdw_batch_create: null argument");
+    *out = nullptr;
+    QDW_CHECK(n >= 1, QDW_EINVAL, "qdw_batch_create: need n >= 1");
+    QDW_CHECK(cycles >= 1 && cycles <= 64, QDW_EINVAL, "qdw_batch_create: need 1 <= cycles <= 64");
+    int rc = check_params(p);
+    if (rc) return rc;
+    for (int j = 0; j < n; ++j)
+        QDW_CHECK(ops[j] && ops[j]->device == ops[0]->device, QDW_EINVAL,
+                  "qdw_batch_create: all operators must live on one device");
+    std::vector<Group> gs;
+    size_t need = 0;
+    if ((rc = plan(ops, n, *p, nullptr, &gs, &need))) return rc;
+    QDW_CHECK(work_bytes >= need, QDW_EWORKSPACE,
+              "qdw_batch_create: workspace smaller than qdw_sap_gcr_batched_workspace_bytes()");
+    char* wk = (char*)(((uintptr_t)work + 255) & ~(uintptr_t)255);
+
+    qdw_batch* b = new qdw_batch();
+    std::unique_ptr<qdw_batch> guard(b);
+    if ((rc = plan(ops, n, *p, wk, &b->gs, &need))) return rc;
+    b->p = *p;
+    b->n = n;
+    b->cycles = cycles;
+    b->device = ops[0]->device;
+    b->ops.assign(ops, ops + n);
+    b->nflags = n * F_SIZE;
+    b->fl0 = b->gs[0].fl;
+    for (const Group& G : b->gs) b->fl0 = std::min(b->fl0, G.fl);
+
+    const auto tg0 = std::chrono::steady_clock::now();
+    QDW_HIP(hipStreamCreateWithFlags(&b->cs, hipStreamNonBlocking));
+    b->ev.resize(b->gs.size() + 1);
+    for (hipEvent_t& e : b->ev) QDW_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    b->side.resize(b->gs.size());
+    for (size_t q = 0; q < b->gs.size(); ++q) {
+        QDW_HIP(hipStreamCreateWithFlags(&b->side[q], hipStreamNonBlocking));
+        b->gs[q].s = b->side[q];
+    }
+    // every group is one branch of the graph: `cycles` restart cycles one after another
+    // (the groups are independent, so they meet only at the end)
+    QDW_HIP(hipStreamBeginCapture(b->cs, hipStreamCaptureModeThreadLocal));
+    int crc = QDW_OK;
+    if (hipEventRecord(b->ev[0], b->cs) != hipSuccess) crc = QDW_EDEVICE;
+    for (size_t q = 0; q < b->gs.size() && !crc; ++q) {
+        if (hipStreamWaitEvent(b->gs[q].s, b->ev[0], 0) != hipSuccess) {
+            crc = QDW_EDEVICE;
+            break;
+        }
+        for (int c = 0; c < cycles && !crc; ++c) crc = cycle(b->gs[q], *p, b->gs[q].s);
+        if (!crc && hipEventRecord(b->ev[1 + q], b->gs[q].s) != hipSuccess) crc = QDW_EDEVICE;
+        if (!crc && hipStreamWaitEvent(b->cs, b->ev[1 + q], 0) != hipSuccess) crc = QDW_EDEVICE;
+    }
+    const hipError_t ce = hipStreamEndCapture(b->cs, &b->graph);
+    if (crc) return crc;
+    QDW_HIP(ce);
+    QDW_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    b->capture_ms = 1e3 * std::chrono::duration<double>(std::chrono::steady_clock::now() - tg0).count();
+    *out = guard.release();
+    return QDW_OK;
+}
+
+extern "C" double qdw_batch_capture_ms(const qdw_batch* b) { return b ? b->capture_ms : 0.0; }
+
+extern "C" int qdw_batch_destroy(qdw_batch* b)
+{
+    if (!b) return QDW_OK;
+    if (b->cs) (void)hipStreamSynchronize(b->cs);
+    delete b;
+    return QDW_OK;
+}
+
+extern "C" int qdw_batch_solve(qdw_batch* b, const void* const* etas, void* const* psis,
+                               qdw_info* infos, int* launches, void* stream)
+{
+    QDW_CHECK(b && etas && psis && infos, QDW_EINVAL, "qdw_batch_solve: null argument");
+    const int n = b->n;
+    for (int j = 0; j < n; ++j) {
+        QDW_CHECK(etas[j] && psis[j], QDW_EINVAL, "qdw_batch_solve: null field");
+        for (int q = 0; q < n; ++q)
+            QDW_CHECK(psis[j] != etas[q] && (q == j || psis[j] != psis[q]), QDW_EINVAL,
+                      "qdw_batch_solve: solution fields must be distinct from each other and "
+                      "from every source");
+    }
+    int rc;
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t st = (hipStream_t)stream;
+    // set-up: gather the sources, x = 0, rho = eta, |eta|^2, tolerances and flags
+    for (const Group& G : b->gs) {
+        for (int r = 0; r < G.nr; ++r)
+            if ((rc = run_map(G.op, Axpby<F64, F64>{etas[G.prob[r]], G.eta + r * G.fb, 1.0, 0.0,
+                                                    G.op->g.Vh},
+                              st)))
+                return rc;
+        if ((rc = brun(G, Init{{G.eta, G.fb}, {G.x, G.fb}, {G.rho, G.fb}, G.op->g.Vh}, -1, st,
+                       B_ETA2)))
+            return rc;
+        init_ctrl_kernel<<<1, 64, 0, st>>>(G.fl, G.sc, G.nr, b->p.res);
+        QDW_LAUNCH_CHECK();
+    }
+    // the captured cycles, launched on the caller's stream until every solve has finished:
+    // one launch (and one host wait) when `cycles` cycles suffice
+    std::vector<int> flags(b->nflags);
+    int nl = 0;
+    const int max_launches = b->p.nmx / (b->cycles * 1) + 2;
+    for (;;) {
+        QDW_HIP(hipGraphLaunch(b->exec, st));
+        ++nl;
+        QDW_HIP(hipMemcpyAsync(flags.data(), b->fl0, sizeof(int) * b->nflags,
+                               hipMemcpyDeviceToHost, st));
+        QDW_HIP(hipStreamSynchronize(st));
+        bool any = false;
+        for (int q = 0; q < n; ++q) any = any || flags[q * F_SIZE + F_ACTIVE];
+        if (!any) break;
+        // every cycle either takes a step of each active solve or ends it
+        QDW_CHECK(nl <= max_launches, QDW_EDEVICE, "qdw_batch_solve: solve did not terminate");
+    }
+    // results: copy the solutions out, read the per-solve outcome
+    std::vector<double> hsc;
+    for (const Group& G : b->gs) {
+        for (int r = 0; r < G.nr; ++r)
+            if ((rc = run_map(G.op, Axpby<F64, F64>{G.x + r * G.fb, psis[G.prob[r]], 1.0, 0.0,
+                                                    G.op->g.Vh},
+                              st)))
+                return rc;
+    }
+    const bool sap = sap_precond(b->p);
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (const Group& G : b->gs) {
+        hsc.resize((size_t)B_SIZE * G.nr);
+        QDW_HIP(hipMemcpyAsync(hsc.data(), G.sc, sizeof(double) * B_SIZE * G.nr,
+                               hipMemcpyDeviceToHost, st));
+        QDW_HIP(hipStreamSynchronize(st));
+        for (int r = 0; r < G.nr; ++r) {
+            const int j = G.prob[r];
+            const int* f = flags.data() + (G.fl - b->fl0) + r * F_SIZE;
+            const double* sr = hsc.data() + (size_t)r * B_SIZE;
+            qdw_info& in = infos[j];
+            in.status = f[F_STATUS];
+            in.n_steps = f[F_STEPS];
+            in.nreset = f[F_NRESET];
+            in.n_dw_hi = f[F_STEPS] + f[F_NRESET];
+            in.n_dw_lo = sap ? (long)f[F_STEPS] * b->p.ncy * b->p.nmr : 0;
+            in.rel_res_true = sr[B_ETA2] > 0.0 ? std::sqrt(sr[G_NORM] / sr[B_ETA2]) : 0.0;
+            in.t_sec = secs;
+        }
+    }
+    if (launches) *launches = nl;
+    return QDW_OK;
 }
 
 extern "C" int sap_gcr_solve_batched(qdw_op* const* ops, const void* const* etas,
@@ -632,127 +792,10 @@ extern "C" int sap_gcr_solve_batched(qdw_op* const* ops, const void* const* etas
     QDW_CHECK(n >= 1, QDW_EINVAL, "sap_gcr_solve_batched: need n >= 1");
     int rc = check_params(p);
     if (rc) return rc;
-    for (int j = 0; j < n; ++j) {
-        QDW_CHECK(etas[j] && psis[j], QDW_EINVAL, "sap_gcr_solve_batched: null field");
-        QDW_CHECK(ops[j] && ops[j]->device == ops[0]->device, QDW_EINVAL,
-                  "sap_gcr_solve_batched: all operators must live on one device");
-        for (int q = 0; q < n; ++q)
-            QDW_CHECK(psis[j] != etas[q] && (q == j || psis[j] != psis[q]), QDW_EINVAL,
-                      "sap_gcr_solve_batched: solution fields must be distinct from each other "
-                      "and from every source");
-    }
-    std::vector<Group> gs;
-    size_t need = 0;
-    if ((rc = plan(ops, n, *p, nullptr, &gs, &need))) return rc;
-    QDW_CHECK(work_bytes >= need, QDW_EWORKSPACE,
-              "sap_gcr_solve_batched: workspace smaller than qdw_sap_gcr_batched_workspace_bytes()");
-    char* wk = (char*)(((uintptr_t)work + 255) & ~(uintptr_t)255);
-    if ((rc = plan(ops, n, *p, wk, &gs, &need))) return rc;
-
-    const auto t0 = std::chrono::steady_clock::now();
-    hipStream_t st = (hipStream_t)stream;
-    Resources res;
-    QDW_HIP(hipStreamCreateWithFlags(&res.cs, hipStreamNonBlocking));
-    res.ev.resize(gs.size() + 2);
-    for (hipEvent_t& e : res.ev) QDW_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    res.side.resize(gs.size());
-    for (size_t q = 0; q < gs.size(); ++q) {
-        QDW_HIP(hipStreamCreateWithFlags(&res.side[q], hipStreamNonBlocking));
-        gs[q].s = res.side[q];
-    }
-    const int nflags = n * F_SIZE;
-    QDW_HIP(hipHostMalloc((void**)&res.host_flags, sizeof(int) * nflags));
-    int ntot_sc = 0;
-    for (const Group& G : gs) ntot_sc += G.nr;
-    QDW_HIP(hipHostMalloc((void**)&res.host_sc, sizeof(double) * B_SIZE * ntot_sc));
-
-    // the work starts after whatever the caller queued on its stream
-    QDW_HIP(hipEventRecord(res.ev[0], st));
-    QDW_HIP(hipStreamWaitEvent(res.cs, res.ev[0], 0));
-    // set-up (eager): gather the sources, x = 0, rho = eta, |eta|^2, tolerances and flags
-    for (const Group& G : gs) {
-        for (int r = 0; r < G.nr; ++r)
-            if ((rc = run_map(G.op, Axpby<F64, F64>{etas[G.prob[r]], G.eta + r * G.fb, 1.0, 0.0,
-                                                    G.op->g.Vh},
-                              res.cs)))
-                return rc;
-        if ((rc = brun(G, Init{{G.eta, G.fb}, {G.x, G.fb}, {G.rho, G.fb}, G.op->g.Vh}, -1, res.cs,
-                       B_ETA2)))
-            return rc;
-        init_ctrl_kernel<<<1, 64, 0, res.cs>>>(G.fl, G.sc, G.nr, p->res);
-        QDW_LAUNCH_CHECK();
-    }
-
-    // capture one cycle of every group, each group a branch of the graph
-    const auto tg0 = std::chrono::steady_clock::now();
-    QDW_HIP(hipStreamBeginCapture(res.cs, hipStreamCaptureModeThreadLocal));
-    int crc = QDW_OK;
-    if (hipEventRecord(res.ev[1], res.cs) != hipSuccess) crc = QDW_EDEVICE;
-    for (size_t q = 0; q < gs.size() && !crc; ++q) {
-        if (hipStreamWaitEvent(gs[q].s, res.ev[1], 0) != hipSuccess) {
-            crc = QDW_EDEVICE;
-            break;
-        }
-        crc = cycle(gs[q], *p, gs[q].s);
-        if (!crc && hipEventRecord(res.ev[2 + q], gs[q].s) != hipSuccess) crc = QDW_EDEVICE;
-        if (!crc && hipStreamWaitEvent(res.cs, res.ev[2 + q], 0) != hipSuccess) crc = QDW_EDEVICE;
-    }
-    const hipError_t ce = hipStreamEndCapture(res.cs, &res.graph);
-    if (crc) return crc;
-    QDW_HIP(ce);
-    QDW_HIP(hipGraphInstantiate(&res.exec, res.graph, nullptr, nullptr, 0));
-    if (graph_ms)
-        *graph_ms = 1e3 * std::chrono::duration<double>(std::chrono::steady_clock::now() - tg0).count();
-
-    // replay one cycle at a time until every solve has finished
-    int* fl0 = gs[0].fl;  // the flags of all groups form one array starting here
-    for (const Group& G : gs) fl0 = std::min(fl0, G.fl);
-    for (int cyc = 0;; ++cyc) {
-        QDW_HIP(hipGraphLaunch(res.exec, res.cs));
-        QDW_HIP(hipMemcpyAsync(res.host_flags, fl0, sizeof(int) * nflags, hipMemcpyDeviceToHost,
-                               res.cs));
-        QDW_HIP(hipStreamSynchronize(res.cs));
-        bool any = false;
-        for (int q = 0; q < n; ++q) any = any || res.host_flags[q * F_SIZE + F_ACTIVE];
-        // every replay either takes a step of each active solve or ends it
-        QDW_CHECK(cyc <= p->nmx, QDW_EDEVICE, "sap_gcr_solve_batched: solve did not terminate");
-        if (!any) break;
-    }
-
-    // results: copy the solutions out, read the per-solve outcome
-    int so = 0;
-    for (const Group& G : gs) {
-        for (int r = 0; r < G.nr; ++r)
-            if ((rc = run_map(G.op, Axpby<F64, F64>{G.x + r * G.fb, psis[G.prob[r]], 1.0, 0.0,
-                                                    G.op->g.Vh},
-                              res.cs)))
-                return rc;
-        QDW_HIP(hipMemcpyAsync(res.host_sc + (size_t)so * B_SIZE, G.sc,
-                               sizeof(double) * B_SIZE * G.nr, hipMemcpyDeviceToHost, res.cs));
-        so += G.nr;
-    }
-    QDW_HIP(hipStreamSynchronize(res.cs));
-    const bool sap = sap_precond(*p);
-    so = 0;
-    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    for (const Group& G : gs) {
-        for (int r = 0; r < G.nr; ++r) {
-            const int j = G.prob[r];
-            const int* f = res.host_flags + (G.fl - fl0) + r * F_SIZE;
-            const double* s = res.host_sc + (size_t)(so + r) * B_SIZE;
-            qdw_info& in = infos[j];
-            in.status = f[F_STATUS];
-            in.n_steps = f[F_STEPS];
-            in.nreset = f[F_NRESET];
-            in.n_dw_hi = f[F_STEPS] + f[F_NRESET];
-            in.n_dw_lo = sap ? (long)f[F_STEPS] * p->ncy * p->nmr : 0;
-            in.rel_res_true = s[B_ETA2] > 0.0 ? std::sqrt(s[G_NORM] / s[B_ETA2]) : 0.0;
-            in.t_sec = secs;
-        }
-        so += G.nr;
-    }
-    // the caller's stream continues after the solutions are written
-    QDW_HIP(hipEventRecord(res.ev[0], res.cs));
-    QDW_HIP(hipStreamWaitEvent(st, res.ev[0], 0));
-    return QDW_OK;
+    qdw_batch* b = nullptr;
+    if ((rc = qdw_batch_create(ops, n, p, 1, work, work_bytes, &b))) return rc;
+    if (graph_ms) *graph_ms = b->capture_ms;
+    rc = qdw_batch_solve(b, etas, psis, infos, nullptr, stream);
+    qdw_batch_destroy(b);
+    return rc;
 }

@@ -281,17 +281,21 @@ struct CgStep {
     {
         using R = typename Traits<P>::real;
         const R a = (R)sc[S_ALPHA];
+        // a zero or non-finite step length leaves the iterate as it was, so that a solve that
+        // runs into a non-finite value still holds its last finite iterate
+        const bool move = a != (R)0 && isfinite(a);
         cx<R> vx[4], vp[4], vr[4], vw[4];
-        ld4<PX, R>(x, Vh, u.par, u.g, u.i, vx);
         ld4<P, R>(p, Vh, u.par, u.g, u.i, vp);
         ld4<P, R>(r, Vh, u.par, u.g, u.i, vr);
         ld4<P, R>(w, Vh, u.par, u.g, u.i, vw);
+        if (move) {
+            ld4<PX, R>(x, Vh, u.par, u.g, u.i, vx);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            vx[k] = vx[k] + scale(vp[k], a);
-            vr[k] = vr[k] - scale(vw[k], a);
+            for (int k = 0; k < 4; ++k) vx[k] = vx[k] + scale(vp[k], a);
+            st4<PX, R>(x, Vh, u.par, u.g, u.i, vx);
         }
-        st4<PX, R>(x, Vh, u.par, u.g, u.i, vx);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) vr[k] = vr[k] - scale(vw[k], a);
         st4<P, R>(r, Vh, u.par, u.g, u.i, vr);
         // reduce what is stored (rounded to P), in FP64; FP64 stores the values as they are
         cx<double> back[4];

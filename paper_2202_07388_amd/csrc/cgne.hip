@@ -140,10 +140,18 @@ int cgne_impl(qdw_op* op, const void* eta, void* psi, const qdw_cgne_params& prm
         return QDW_OK;
     };
 
-    // psi += x_lo / s ; r_hi = eta - D^+ D psi ; returns |r_hi| / |eta| in *rel
-    auto true_residual = [&](double* rel) -> int {
+    // psi += x_lo / s ; r_hi = eta - D^+ D psi ; returns |r_hi| / |eta| in *rel. With
+    // checked, x_lo is added only when it is finite (after a non-finite step).
+    auto true_residual = [&](double* rel, bool checked = false) -> int {
         int e;
-        if (PL != F64)
+        bool add = PL != F64;
+        if (add && checked) {
+            if ((e = run_map(op, Norm2<PX>{xlo, Vh}, st, op->scalars + S_TMP, FIN_STORE, 0, nu))) return e;
+            double x2;
+            if ((e = read_scalars(op, S_TMP, 1, &x2, st))) return e;
+            add = std::isfinite(x2);
+        }
+        if (add)
             if ((e = run_map(op, Accumulate<PX>{psi, xlo, 1.0 / s, Vh}, st, nullptr, FIN_STORE, 0, nu))) return e;
         if ((e = apply(psi, t1, F64, false))) return e;
         if ((e = apply(t1, t2, F64, true))) return e;
@@ -193,7 +201,7 @@ int cgne_impl(qdw_op* op, const void* eta, void* psi, const qdw_cgne_params& prm
         const double v = slot[k];
         if (!std::isfinite(v)) {
             QDW_HIP(hipStreamSynchronize(st));
-            TRY(true_residual(&rel_true));
+            TRY(true_residual(&rel_true, true));
             status = -3;
             break;
         }

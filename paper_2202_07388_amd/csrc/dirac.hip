@@ -625,17 +625,25 @@ extern "C" int qdw_get_dw_shape(const qdw_op* op, qdw_prec prec, int* shape5)
     return QDW_OK;
 }
 
-extern "C" int qdw_autotune(qdw_op* op, qdw_prec prec, int nrhs, char* report, size_t report_len,
-                            void* stream)
+extern "C" size_t qdw_autotune_workspace_bytes(const qdw_op* op, qdw_prec prec, int nrhs)
+{
+    if (!op || prec < QDW_F64 || prec > QDW_BF16S || nrhs < 1 || nrhs > kMaxRhs) return 0;
+    return 2 * spinor_bytes(op->g, prec) * nrhs + 256;
+}
+
+extern "C" int qdw_autotune(qdw_op* op, qdw_prec prec, int nrhs, void* work, size_t work_bytes,
+                            char* report, size_t report_len, void* stream)
 {
     QDW_CHECK(op, QDW_EINVAL, "qdw_autotune: null operator");
     QDW_CHECK(prec >= QDW_F64 && prec <= QDW_BF16S, QDW_EINVAL, "qdw_autotune: bad precision");
     QDW_CHECK(nrhs >= 1 && nrhs <= kMaxRhs, QDW_EINVAL, "qdw_autotune: need 1 <= nrhs <= 64");
+    QDW_CHECK(work, QDW_EINVAL, "qdw_autotune: null workspace");
+    QDW_CHECK(work_bytes >= qdw_autotune_workspace_bytes(op, prec, nrhs), QDW_EWORKSPACE,
+              "qdw_autotune: workspace smaller than qdw_autotune_workspace_bytes()");
     hipStream_t st = (hipStream_t)stream;
     const Geom& g = op->g;
     const size_t fb = spinor_bytes(g, prec);
-    char* buf = nullptr;
-    QDW_HIP(hipMalloc((void**)&buf, 2 * fb * nrhs));
+    char* buf = (char*)(((uintptr_t)work + 255) & ~(uintptr_t)255);
     RhsTable tab{};
     for (int r = 0; r < nrhs; ++r) {
         tab.in[r] = buf + (size_t)r * fb;
@@ -681,7 +689,6 @@ extern "C" int qdw_autotune(qdw_op* op, qdw_prec prec, int nrhs, char* report, s
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     (void)hipStreamSynchronize(st);
-    (void)hipFree(buf);
     if (rc) {
         op->dw_shape[prec] = keep;
         return rc;

@@ -225,6 +225,7 @@ int gcr_impl(qdw_op* op, const void* eta, void* psi, const qdw_sap_gcr_params& p
     std::vector<double> hs(G_SIZE);
     while (true) {
         int k = 0;
+        bool dropped = false;
         while (k < p.nkv && steps < p.nmx && rn > tol) {
             // phi_k = M(rho)
             const double rn_before = rn;
@@ -263,18 +264,24 @@ int gcr_impl(qdw_op* op, const void* eta, void* psi, const qdw_sap_gcr_params& p
             TRY(run_map(op, GcrUpdate{L.chi[k], L.rho, L.gsc + G_COEF, Vh}, st, L.gsc + G_NORM));
             double r2;
             TRY(read_device(op, L.gsc + G_NORM, 1, &r2, st));
-            ++k;
-            ++steps;
             if (!std::isfinite(r2)) {
-                status = -3;
+                // a non-finite preconditioner output (or step): the column is dropped, and the
+                // restart below builds psi from the finite columns 0..k-1 and recomputes rho
+                // from it. The network hands the rest of the solve to SAP; otherwise the
+                // solve ends with status -3 and that psi.
+                dropped = true;
+                if (use_nn && p.precond == QDW_PRECOND_NN_SAP) nn_ok = false;
+                else status = -3;
                 break;
             }
+            ++k;
+            ++steps;
             rn = std::sqrt(r2);
             // the learned preconditioner is judged by the GCR residual itself: a step that
             // reduces |rho| by less than 1 % hands the rest of the solve to SAP
             if (use_nn && p.precond == QDW_PRECOND_NN_SAP && rn > 0.99 * rn_before) nn_ok = false;
         }
-        if (k > 0) {
+        if (k > 0 || dropped) {
             // restart step: R alpha = c, psi += sum alpha_l phi_l, rho = eta - D psi
             TRY(read_device(op, L.gsc, G_SIZE, hs.data(), st));
             std::vector<std::complex<double>> al(k);
@@ -290,7 +297,7 @@ int gcr_impl(qdw_op* op, const void* eta, void* psi, const qdw_sap_gcr_params& p
                 // (b_i = 0, then also c_i = 0) contributes nothing
                 al[i] = hs[G_B + i] > 0.0 ? s / hs[G_B + i] : std::complex<double>(0.0, 0.0);
             }
-            TRY(dispatch_k<MultiAxpy>(k, op, st, [&](auto& f) {
+            if (k > 0) TRY(dispatch_k<MultiAxpy>(k, op, st, [&](auto& f) {
                 f.psi = psi;
                 for (int l = 0; l < k; ++l) {
                     f.phi[l] = L.phi[l];

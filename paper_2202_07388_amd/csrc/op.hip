@@ -92,6 +92,9 @@ __device__ inline long shifted(const Geom& g, const int x[4], int mu, int dmu, i
 
 // ------------------------------------------------------------------ unitarity check
 
+// *p = 0 (a kernel, not a memset node, so the set-up can be captured)
+__global__ void zero_u64_kernel(unsigned long long* p) { *p = 0ull; }
+
 __global__ void unitarity_kernel(const double* su3, long nlinks, unsigned long long* worst)
 {
     __shared__ double red[256];
@@ -426,27 +429,45 @@ __global__ void pack_kernel<F64>(Geom g, const double* can, void* eo)
         ((double2*)eo)[chunk_at(g.Vh, 12, par, k, i)] = double2{p[2 * k], p[2 * k + 1]};
 }
 
-void free_op(qdw_op* op)
+// Byte offsets of the operator's arrays inside the caller's device block (each 256-byte
+// aligned): compressed links and their determinants, clover blocks and their inverses in
+// every precision, then the reduction scratch.
+struct OpLayout {
+    size_t links[4], det[4], clover[4], cloverinv[4], partials, scalars, worst, total;
+};
+
+OpLayout op_layout(int Vh)
 {
-    for (int p = 0; p < 4; ++p) {
-        if (op->links[p]) (void)hipFree(op->links[p]);
-        if (op->det[p]) (void)hipFree(op->det[p]);
-        if (op->clover[p]) (void)hipFree(op->clover[p]);
-        if (op->cloverinv[p]) (void)hipFree(op->cloverinv[p]);
-    }
-    if (op->partials) (void)hipFree(op->partials);
-    if (op->scalars) (void)hipFree(op->scalars);
-    if (op->host_scalars) (void)hipHostFree(op->host_scalars);
-    delete op;
+    OpLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t n) {
+        const size_t at = off;
+        off += (n + 255) & ~(size_t)255;
+        return at;
+    };
+    const size_t nl = (size_t)padded(Vh) * 8;  // link slots per array (2 parities x 4 dirs)
+    const size_t ns = (size_t)padded(Vh) * 2;  // site slots of both parities
+    L.links[F64] = take(nl * 6 * 16);
+    L.det[F64] = take(nl * 16);
+    L.links[F32] = take(nl * 3 * 16);
+    L.det[F32] = take(nl * 8);
+    L.links[F16S] = take(nl * 2 * 16);
+    L.links[BF16S] = take(nl * 2 * 16);
+    L.det[F16S] = L.det[BF16S] = (size_t)-1;  // kept inside the 16-bit link chunks
+    const size_t creal[4] = {8, 4, 2, 2};
+    for (int p = 0; p < 4; ++p) L.clover[p] = take(ns * 72 * creal[p]);
+    for (int p = 0; p < 4; ++p) L.cloverinv[p] = take(ns * 72 * creal[p]);
+    L.partials = take(sizeof(double) * kMaxPartials * kMaxScalars);
+    L.scalars = take(sizeof(double) * kMaxScalars);
+    L.worst = take(sizeof(unsigned long long));
+    L.total = off + 256;  // room to align the caller's pointer
+    return L;
 }
 
-}  // namespace
-
-extern "C" int qdw_create(const qdw_lattice* lat, const double* su3, const double* theta,
-                          double m0, double csw, void* stream, qdw_op** out)
+// lattice checks shared by the size query and qdw_create
+int check_lattice(const qdw_lattice* lat)
 {
-    QDW_CHECK(lat && su3 && theta && out, QDW_EINVAL, "qdw_create: null argument");
-    *out = nullptr;
+    QDW_CHECK(lat, QDW_EINVAL, "qdw_create: null lattice");
     const int L[4] = {lat->T, lat->L1, lat->L2, lat->L3};
     for (int mu = 0; mu < 4; ++mu)
         QDW_CHECK(L[mu] >= 2 && L[mu] % 2 == 0, QDW_EINVAL,
@@ -454,6 +475,35 @@ extern "C" int qdw_create(const qdw_lattice* lat, const double* su3, const doubl
     QDW_CHECK(lat->bc_t == 1 || lat->bc_t == -1, QDW_EINVAL, "qdw_create: bc_t must be +1 or -1");
     const long V = (long)L[0] * L[1] * L[2] * L[3];
     QDW_CHECK(V <= (1L << 30), QDW_EINVAL, "qdw_create: volume above 2^30 sites");
+    return QDW_OK;
+}
+
+}  // namespace
+
+extern "C" size_t qdw_op_device_bytes(const qdw_lattice* lat)
+{
+    if (check_lattice(lat)) return 0;
+    const long V = (long)lat->T * lat->L1 * lat->L2 * lat->L3;
+    return op_layout((int)(V / 2)).total;
+}
+
+extern "C" size_t qdw_op_host_bytes(void) { return sizeof(double) * kHostScalars; }
+
+extern "C" int qdw_create(const qdw_lattice* lat, const double* su3, const double* theta,
+                          double m0, double csw, void* dev_mem, size_t dev_bytes, void* host_mem,
+                          size_t host_bytes, void* stream, qdw_op** out)
+{
+    QDW_CHECK(lat && su3 && theta && out && dev_mem && host_mem, QDW_EINVAL,
+              "qdw_create: null argument");
+    *out = nullptr;
+    if (const int rc = check_lattice(lat)) return rc;
+    const int L[4] = {lat->T, lat->L1, lat->L2, lat->L3};
+    const long V = (long)L[0] * L[1] * L[2] * L[3];
+    const OpLayout lay = op_layout((int)(V / 2));
+    QDW_CHECK(dev_bytes >= lay.total, QDW_EWORKSPACE,
+              "qdw_create: device block smaller than qdw_op_device_bytes()");
+    QDW_CHECK(host_bytes >= qdw_op_host_bytes(), QDW_EWORKSPACE,
+              "qdw_create: host block smaller than qdw_op_host_bytes()");
     hipStream_t st = (hipStream_t)stream;
 
     qdw_op* op = new qdw_op();
@@ -497,44 +547,48 @@ extern "C" int qdw_create(const qdw_lattice* lat, const double* su3, const doubl
     op->csw = csw;
     (void)hipGetDevice(&op->device);
 
+    // every array lives in the caller's blocks
+    char* base = (char*)(((uintptr_t)dev_mem + 255) & ~(uintptr_t)255);
+    for (int p = 0; p < 4; ++p) {
+        op->links[p] = base + lay.links[p];
+        op->det[p] = lay.det[p] == (size_t)-1 ? nullptr : base + lay.det[p];
+        op->clover[p] = base + lay.clover[p];
+        op->cloverinv[p] = base + lay.cloverinv[p];
+    }
+    op->partials = (double*)(base + lay.partials);
+    op->scalars = (double*)(base + lay.scalars);
+    op->host_scalars = (double*)host_mem;
+
     auto fail = [&](int code, const std::string& msg) {
         set_error(msg);
-        free_op(op);
+        delete op;
         return code;
     };
 #define CREATE_HIP(call)                                                               \
     do {                                                                               \
         hipError_t e_ = (call);                                                        \
         if (e_ != hipSuccess)                                                          \
-            return fail(e_ == hipErrorOutOfMemory ? QDW_ENOMEM : QDW_EDEVICE,          \
-                        std::string(#call) + ": " + hipGetErrorString(e_));            \
+            return fail(QDW_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-    // 1. unitarity of the SU(3) parts
-    unsigned long long* worst = nullptr;
-    CREATE_HIP(hipMallocAsync((void**)&worst, sizeof(unsigned long long), st));
-    CREATE_HIP(hipMemsetAsync(worst, 0, sizeof(unsigned long long), st));
+    // 1. unitarity of the SU(3) parts (the worst deviation as the bits of a non-negative
+    //    double, so an integer maximum orders them)
+    unsigned long long* worst = (unsigned long long*)(base + lay.worst);
+    zero_u64_kernel<<<1, 1, 0, st>>>(worst);
+    CREATE_HIP(hipGetLastError());
     const long nlinks = V * 4;
     unitarity_kernel<<<(unsigned)((nlinks + 255) / 256), 256, 0, st>>>(su3, nlinks, worst);
     CREATE_HIP(hipGetLastError());
-    unsigned long long wbits = 0;
-    CREATE_HIP(hipMemcpyAsync(&wbits, worst, sizeof(wbits), hipMemcpyDeviceToHost, st));
+    CREATE_HIP(hipMemcpyAsync(op->host_scalars, worst, sizeof(unsigned long long),
+                              hipMemcpyDeviceToHost, st));
     CREATE_HIP(hipStreamSynchronize(st));
-    CREATE_HIP(hipFreeAsync(worst, st));
     double wdev;
-    std::memcpy(&wdev, &wbits, sizeof(wdev));
+    std::memcpy(&wdev, op->host_scalars, sizeof(wdev));
     if (!(wdev <= 1e-10))
         return fail(QDW_ENOTUNITARY, "qdw_create: a link deviates from SU(3) by " +
                                          std::to_string(wdev));
 
     // 2. compressed links in every precision
-    const size_t nl = (size_t)padded(g.Vh) * 8;  // link slots per array (2 parities x 4 dirs)
-    CREATE_HIP(hipMalloc(&op->links[F64], nl * 6 * 16));
-    CREATE_HIP(hipMalloc(&op->det[F64], nl * 16));
-    CREATE_HIP(hipMalloc(&op->links[F32], nl * 3 * 16));
-    CREATE_HIP(hipMalloc(&op->det[F32], nl * 8));
-    CREATE_HIP(hipMalloc(&op->links[F16S], nl * 2 * 16));
-    CREATE_HIP(hipMalloc(&op->links[BF16S], nl * 2 * 16));
     dim3 gl((g.Vh + 255) / 256, 2, 4);
     pack_links_kernel<<<gl, 256, 0, st>>>(g, su3, theta, op->links[F64], op->det[F64],
                                           op->links[F32], op->det[F32], op->links[F16S],
@@ -542,11 +596,6 @@ extern "C" int qdw_create(const qdw_lattice* lat, const double* su3, const doubl
     CREATE_HIP(hipGetLastError());
 
     // 3. clover blocks (FP64) and their lower-precision copies
-    const size_t ns = (size_t)padded(g.Vh) * 2;  // site slots of both parities
-    CREATE_HIP(hipMalloc(&op->clover[F64], ns * 72 * 8));
-    CREATE_HIP(hipMalloc(&op->clover[F32], ns * 72 * 4));
-    CREATE_HIP(hipMalloc(&op->clover[F16S], ns * 72 * 2));
-    CREATE_HIP(hipMalloc(&op->clover[BF16S], ns * 72 * 2));
     dim3 gs((g.Vh + 127) / 128, 2);
     clover_kernel<<<gs, 128, 0, st>>>(g, su3, theta, m0, csw, (double2*)op->clover[F64]);
     CREATE_HIP(hipGetLastError());
@@ -555,10 +604,6 @@ extern "C" int qdw_create(const qdw_lattice* lat, const double* su3, const doubl
                                            (uint16_t*)op->clover[BF16S]);
     CREATE_HIP(hipGetLastError());
     // their inverses (the even-odd reduced operator divides by the odd-site blocks)
-    CREATE_HIP(hipMalloc(&op->cloverinv[F64], ns * 72 * 8));
-    CREATE_HIP(hipMalloc(&op->cloverinv[F32], ns * 72 * 4));
-    CREATE_HIP(hipMalloc(&op->cloverinv[F16S], ns * 72 * 2));
-    CREATE_HIP(hipMalloc(&op->cloverinv[BF16S], ns * 72 * 2));
     clover_inv_kernel<<<gs, 128, 0, st>>>(g, (const double2*)op->clover[F64],
                                           (double2*)op->cloverinv[F64]);
     CREATE_HIP(hipGetLastError());
@@ -567,11 +612,6 @@ extern "C" int qdw_create(const qdw_lattice* lat, const double* su3, const doubl
                                            (_Float16*)op->cloverinv[F16S],
                                            (uint16_t*)op->cloverinv[BF16S]);
     CREATE_HIP(hipGetLastError());
-
-    // 4. reduction scratch
-    CREATE_HIP(hipMalloc((void**)&op->partials, sizeof(double) * kMaxPartials * kMaxScalars));
-    CREATE_HIP(hipMalloc((void**)&op->scalars, sizeof(double) * kMaxScalars));
-    CREATE_HIP(hipHostMalloc((void**)&op->host_scalars, sizeof(double) * kHostScalars));
     CREATE_HIP(hipStreamSynchronize(st));
 #undef CREATE_HIP
     *out = op;
@@ -582,7 +622,7 @@ extern "C" int qdw_destroy(qdw_op* op)
 {
     if (!op) return QDW_OK;
     (void)hipDeviceSynchronize();
-    free_op(op);
+    delete op;  // the device and host blocks stay with the caller
     return QDW_OK;
 }
 

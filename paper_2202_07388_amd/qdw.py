@@ -45,8 +45,13 @@ def load():
                        "python -m paper_2202_07388_amd.build)")
     L = ctypes.CDLL(LIB_PATH)
     L.qdw_last_error.restype = ctypes.c_char_p
+    L.qdw_op_device_bytes.argtypes = [ctypes.POINTER(Lattice)]
+    L.qdw_op_device_bytes.restype = ctypes.c_size_t
+    L.qdw_op_host_bytes.argtypes = []
+    L.qdw_op_host_bytes.restype = ctypes.c_size_t
     L.qdw_create.argtypes = [ctypes.POINTER(Lattice), _P, _P, ctypes.c_double,
-                             ctypes.c_double, _P, ctypes.POINTER(_P)]
+                             ctypes.c_double, _P, ctypes.c_size_t, _P, ctypes.c_size_t, _P,
+                             ctypes.POINTER(_P)]
     L.qdw_destroy.argtypes = [_P]
     L.qdw_volume.argtypes = [_P]
     L.qdw_volume.restype = ctypes.c_long
@@ -124,8 +129,9 @@ _OPTIONAL: list = [
                        ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double), _P,
                        ctypes.c_size_t, _P], ctypes.c_int),
     ("dw_apply_multi", [_P, _P, _P, ctypes.c_int, ctypes.c_int, _P], ctypes.c_int),
-    ("qdw_autotune", [_P, ctypes.c_int, ctypes.c_int, ctypes.c_char_p, ctypes.c_size_t, _P],
-     ctypes.c_int),
+    ("qdw_autotune_workspace_bytes", [_P, ctypes.c_int, ctypes.c_int], ctypes.c_size_t),
+    ("qdw_autotune", [_P, ctypes.c_int, ctypes.c_int, _P, ctypes.c_size_t, ctypes.c_char_p,
+                      ctypes.c_size_t, _P], ctypes.c_int),
     ("qdw_set_dw_shape", [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                           ctypes.c_int, ctypes.c_int], ctypes.c_int),
     ("qdw_get_dw_shape", [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int * 5)], ctypes.c_int),
@@ -134,6 +140,11 @@ _OPTIONAL: list = [
     ("sap_gcr_solve_batched", [_P, _P, _P, ctypes.c_int, ctypes.POINTER(SapGcrParams), _P,
                                ctypes.c_size_t, _P, ctypes.POINTER(ctypes.c_double), _P],
      ctypes.c_int),
+    ("qdw_batch_create", [_P, ctypes.c_int, ctypes.POINTER(SapGcrParams), ctypes.c_int, _P,
+                          ctypes.c_size_t, ctypes.POINTER(_P)], ctypes.c_int),
+    ("qdw_batch_solve", [_P, _P, _P, _P, ctypes.POINTER(ctypes.c_int), _P], ctypes.c_int),
+    ("qdw_batch_capture_ms", [_P], ctypes.c_double),
+    ("qdw_batch_destroy", [_P], ctypes.c_int),
     ("qdw_cgne_workspace_bytes", [_P, ctypes.POINTER(CgneParams)], ctypes.c_size_t),
     ("cgne_solve", [_P, _P, _P, ctypes.POINTER(CgneParams), _P, ctypes.c_size_t,
                     ctypes.POINTER(Info), _P], ctypes.c_int),
@@ -185,9 +196,17 @@ class Op:
         if su3_d.numel() != self.V * 4 * 9 * 2 or th_d.numel() != self.V * 4:
             raise QdwError("gauge field shape does not match the lattice")
         lat = Lattice(*self.dims, self.bc_t)
+        nd = int(L.qdw_op_device_bytes(ctypes.byref(lat)))
+        if nd == 0:
+            raise QdwError("qdw_create: invalid lattice %s" % (self.dims,))
+        # the operator's device and host blocks are torch tensors: PyTorch owns the memory
+        self._dev_mem = torch.empty(nd, dtype=torch.uint8, device=dev)
+        self._host_mem = torch.empty(int(L.qdw_op_host_bytes()), dtype=torch.uint8,
+                                     pin_memory=True)
         h = _P()
         _check(L.qdw_create(ctypes.byref(lat), _ptr(su3_d), _ptr(th_d), self.m0, self.csw,
-                            _stream(), ctypes.byref(h)), "qdw_create")
+                            _ptr(self._dev_mem), nd, ctypes.c_void_p(self._host_mem.data_ptr()),
+                            self._host_mem.numel(), _stream(), ctypes.byref(h)), "qdw_create")
         self._h = h
         self.device = dev
 
@@ -195,10 +214,17 @@ class Op:
     def handle(self):
         return self._h
 
+    @property
+    def device_bytes(self) -> int:
+        """Bytes of the caller-owned device block the operator lives in."""
+        return self._dev_mem.numel()
+
     def close(self):
         if getattr(self, "_h", None):
             load().qdw_destroy(self._h)
             self._h = None
+        self._dev_mem = None
+        self._host_mem = None
 
     def __del__(self):
         try:
@@ -349,9 +375,16 @@ def dw_apply_multi(op: Op, xs, outs, prec: str = "f64"):
 
 def autotune(op: Op, prec: str = "f64", nrhs: int = 1) -> str:
     """Pick the fastest D-kernel shape for this operator; returns the tuner's report."""
+    torch = _torch()
+    L = load()
+    nb = int(L.qdw_autotune_workspace_bytes(op.handle, PREC[prec], nrhs))
+    if nb == 0:
+        raise QdwError("qdw_autotune: bad arguments")
+    work = torch.empty(nb, dtype=torch.uint8, device=op.device)
     buf = ctypes.create_string_buffer(4096)
-    _check(load().qdw_autotune(op.handle, PREC[prec], nrhs, buf, len(buf), _stream()),
+    _check(L.qdw_autotune(op.handle, PREC[prec], nrhs, _ptr(work), nb, buf, len(buf), _stream()),
            "qdw_autotune")
+    del work
     return buf.value.decode()
 
 
@@ -392,6 +425,55 @@ def sap_gcr_solve_batched(ops, etas, psis, res: float = 1e-10, nmx: int = 2000, 
                                    _ptr(work), work.numel(), infos, ctypes.byref(gms),
                                    _stream()), "sap_gcr_solve_batched")
     return [i.as_dict() for i in infos], gms.value
+
+
+class Batch:
+    """A captured batch of flexible-GCR solves (qdw_batch): the graph of `cycles` restart
+    cycles is built once over the operators `ops` (which may repeat and differ in volume)
+    and replayed by every solve; the workspace is a torch tensor owned by the plan."""
+
+    def __init__(self, ops, res: float = 1e-10, nmx: int = 2000, nkv: int = 16, ncy: int = 5,
+                 nmr: int = 4, bs=(4, 4, 4, 4), sdtype: str = "f16", precond: str = "sap",
+                 cycles: int = 1):
+        L = load()
+        torch = _torch()
+        self.ops = list(ops)
+        self.n = len(self.ops)
+        self._prm = SapGcrParams(res, nmx, nkv, ncy, nmr, (ctypes.c_int * 4)(*bs), PREC[sdtype],
+                                 PRECOND[precond], None, 0.9)
+        self._hs = (ctypes.c_void_p * self.n)(*[o.handle for o in self.ops])
+        nb = int(L.qdw_sap_gcr_batched_workspace_bytes(self._hs, self.n, ctypes.byref(self._prm)))
+        if nb == 0:
+            raise QdwError("bad batched SAP-GCR settings")
+        self.work = torch.empty(nb, dtype=torch.uint8, device=self.ops[0].device)
+        h = _P()
+        _check(L.qdw_batch_create(self._hs, self.n, ctypes.byref(self._prm), cycles,
+                                  _ptr(self.work), nb, ctypes.byref(h)), "qdw_batch_create")
+        self._h = h
+        self.cycles = cycles
+        self.capture_ms = float(L.qdw_batch_capture_ms(h))
+
+    def solve(self, etas, psis):
+        """Solve every problem; returns (per-solve result dicts, graph launches)."""
+        if not (len(etas) == self.n and len(psis) == self.n):
+            raise QdwError("Batch.solve: one source and one solution per operator")
+        infos = (Info * self.n)()
+        nl = ctypes.c_int(0)
+        _check(load().qdw_batch_solve(self._h, _ptr_array(etas), _ptr_array(psis), infos,
+                                      ctypes.byref(nl), _stream()), "qdw_batch_solve")
+        return [i.as_dict() for i in infos], nl.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().qdw_batch_destroy(self._h)
+            self._h = None
+        self.work = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def sap_adaptive_apply(op: Op, rho, phi, ncy_max: int = 20, nmr_max: int = 20,

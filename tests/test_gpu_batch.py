@@ -252,3 +252,39 @@ def test_batched_matches_oracle_fgcr(batch):
     xo, st = oracle.fgcr(oop, eta, 1e-11, 3000, 16)
     assert st > 0
     assert rel(gop.unpack(psis[1], "f64").cpu().numpy(), xo) <= 1e-7
+
+
+def test_batch_plan_reused_across_solves(batch):
+    """A captured plan serves several solves: each equals the single solves of its systems
+    (same status and restarts, solutions to 1e-9); a plan of several cycles per launch
+    gives bit-identical solutions to a plan of one cycle, and finishes in
+    ceil(cycles needed / cycles per launch) launches -- one when they suffice."""
+    import torch
+    ops, probs = batch
+    gops = [ops[d][0] for d, _ in probs]
+    kw = dict(KW, precond="sap", sdtype="f16")
+    one_cycle = qdw.Batch(gops, cycles=1, **kw)
+    four = qdw.Batch(gops, cycles=4, **kw)
+    assert one_cycle.capture_ms > 0 and four.capture_ms > 0
+    try:
+        for shift in (0, 1):
+            srcs = [(d, e if shift == 0 else np.roll(e, 3, axis=0)) for d, e in probs]
+            etas = [ops[d][0].pack(e, "f64") for d, e in srcs]
+            pa = [ops[d][0].new_field("f64") for d, _ in srcs]
+            pb = [ops[d][0].new_field("f64") for d, _ in srcs]
+            ia, na = one_cycle.solve(etas, pa)
+            ib, nb = four.solve(etas, pb)
+            need = max(i["nreset"] for i in ia)
+            assert na == need and nb == -(-need // 4)
+            for (d, eta), x, y, i, j, e in zip(srcs, pa, pb, ia, ib, etas):
+                gop, oop = ops[d]
+                assert torch.equal(x, y) and i["status"] == j["status"] > 0
+                ref_psi = gop.new_field("f64")
+                ref = qdw.sap_gcr_solve(gop, e, ref_psi, **kw)
+                assert i["status"] == ref["status"] and i["nreset"] == ref["nreset"]
+                xs = gop.unpack(x, "f64").cpu().numpy()
+                assert rel(xs, gop.unpack(ref_psi, "f64").cpu().numpy()) <= 1e-9
+                assert np.linalg.norm(eta - oop.dw(xs)) <= 1.01e-10 * np.linalg.norm(eta)
+    finally:
+        one_cycle.close()
+        four.close()

@@ -109,12 +109,12 @@ def test_rejects_odd_extent():
         qdw.Op(dims, su3, th, 0.0, 1.0)
 
 
-def test_full_size_sampled_sites():
+def test_full_size_sampled_sites(gauge32):
     """32^3 x 64 in the launch configurations the benchmark times (its pinned shapes) and
     in the one-workgroup-per-slice form, D and D^+, checked on sampled sites that the
     oracle computes one by one (FP64 to 1e-13, FP32 to 2e-6, FP16 storage to 2e-2)."""
     dims = (64, 32, 32, 32)
-    su3, th = syn.gauge_field(dims, 0.3, 0.1, 7388 + 10)
+    su3, th = gauge32  # eps 0.3, U(1) 0.1, seed 7388 + 10
     m0, csw = -0.05, 1.7
     gop = qdw.Op(dims, su3, th, m0, csw)
     psi = syn.gaussian_spinor(dims, 7388 + 10 + 1000)

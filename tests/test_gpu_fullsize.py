@@ -5,7 +5,8 @@ The oracle cannot solve at these sizes, so the checks are properties that hold a
 size: every solve must reach the FP64 true residual 1e-10, recomputed here independently
 with the library's FP64 operators (which test_gpu_dirac pins against the oracle on sampled
 sites at 32^3 x 64, in these shapes), and with identity weights the network must return
-its input exactly.
+its input exactly. The network with random weights, in the benchmark's bf16 mixing and in
+FP32 mixing, is compared with the oracle on sampled sites (oracle.nn_at_sites).
 """
 import numpy as np
 import pytest
@@ -32,11 +33,10 @@ def _even_mask(dims, device):
 
 
 @pytest.fixture(scope="module")
-def op32():
-    from bench import CSW, DIMS, EPS, EPS_U1, M0, PINNED_SHAPES, SEED
-    su3, th = syn.gauge_field(DIMS, EPS, EPS_U1, SEED)
+def op32(gauge32):
+    from bench import CSW, DIMS, M0, PINNED_SHAPES, SEED
+    su3, th = gauge32
     op = qdw.Op(DIMS, su3, th, M0, CSW, -1)
-    del su3, th
     for p, shape in PINNED_SHAPES.items():
         qdw.set_dw_shape(op, p, *shape)
     eta = op.pack(syn.gaussian_spinor(DIMS, SEED + 1000))
@@ -111,3 +111,27 @@ def test_network_identity_full_size(op32):
                            + 1j * src.imag.astype(np.float32).astype(np.float64),
                            device=op.device)
     assert torch.equal(got, want)
+
+
+@pytest.mark.parametrize("f32,tol", [(False, 1e-2), (True, 1e-5)])
+def test_network_random_weights_sampled_sites(op32, gauge32, f32, tol):
+    """The network at 32^3 x 64 with random (non-identity) weights, as the benchmark
+    evaluates it (bf16 operands on the matrix cores, FP32 accumulation) and with FP32
+    mixing, against the oracle on 256 sampled sites including the time boundary and the
+    lattice corners. Tolerances as in test_gpu_nn (bf16 rounding u = 2^-9 of the operands)."""
+    dims, op, _ = op32
+    su3, th = gauge32
+    u = oracle.u3_links(su3, th)
+    W = oracle.nn_identity_weights(seed=5, scale=0.3)
+    src = syn.gaussian_spinor(dims, 4322)
+    rng = np.random.default_rng(7)
+    V = int(np.prod(dims))
+    x = np.array([[0, 0, 0, 0], [63, 31, 31, 31], [63, 0, 31, 0], [0, 31, 0, 31]])
+    lex = list(((x[:, 0] * 32 + x[:, 1]) * 32 + x[:, 2]) * 32 + x[:, 3])
+    sites = np.array(lex + list(rng.integers(0, V, 252)))
+    want = oracle.nn_at_sites(dims, -1, u, W, src, sites)
+    y = op.new_field()
+    qdw.nn_forward(op, qdw.nn_weights_tensor(W), op.pack(src), y, f32_mixing=f32)
+    got = op.unpack(y)[sites].cpu().numpy()
+    err = np.linalg.norm(got - want) / np.linalg.norm(want)
+    assert err <= tol, err

@@ -190,3 +190,70 @@ def test_bad_network_falls_back_to_sap(trained):
                              ncy=5, nmr=4, sdtype="f16")
     assert info["status"] > 0 and info["rel_res_true"] <= 1e-10
     assert info["n_dw_lo"] > 0  # SAP did the work
+
+
+def _dirac_weights(m0):
+    """Layer 2 multiplies by D at c_sw = 0 (W_0 = (4 + m0), W_{+-mu} = -1/2 (1 -+ gamma_mu)),
+    routed through channels 3 and 5; layers 1 and 3 copy (the oracle test of the same
+    weights pins them against oracle.c's operator)."""
+    g = oracle.gamma()
+    W1 = np.zeros((9, 8, 1, 4, 4), dtype=np.complex128)
+    W2 = np.zeros((9, 8, 8, 4, 4), dtype=np.complex128)
+    W3 = np.zeros((9, 1, 8, 4, 4), dtype=np.complex128)
+    W1[0, 3, 0] = np.eye(4)
+    W2[0, 5, 3] = (4.0 + m0) * np.eye(4)
+    for mu in range(4):
+        W2[1 + 2 * mu, 5, 3] = -0.5 * (np.eye(4) - g[mu])
+        W2[2 + 2 * mu, 5, 3] = -0.5 * (np.eye(4) + g[mu])
+    W3[0, 0, 5] = np.eye(4)
+    return [W1, W2, W3]
+
+
+@pytest.mark.parametrize("dims", [(6, 4, 4, 6), (16, 8, 8, 8)])
+@pytest.mark.parametrize("f32,tol", [(True, 1e-5), (False, 1e-2)])
+def test_dirac_weights_give_the_operator(dims, f32, tol):
+    """Through the C ABI, the network with Dirac weights equals the oracle's D at c_sw = 0
+    (m0 = -0.5, so every weight is exact in bf16): the GPU's spin, channel and path
+    conventions are those of the operator itself."""
+    gop, oop, _, _ = make_pair(dims, -0.5, 0.0, 0.3, seed=35)
+    r = syn.gaussian_spinor(dims, 36)
+    y = gop.new_field()
+    qdw.nn_forward(gop, qdw.nn_weights_tensor(_dirac_weights(-0.5)), gop.pack(r), y,
+                   f32_mixing=f32)
+    got = gop.unpack(y).cpu().numpy()
+    want = oop.dw(r)
+    assert rel(got, want) <= tol, rel(got, want)
+    gop.close()
+
+
+@pytest.fixture(scope="module")
+def net16():
+    """16 x 8^3 (8192 sites, several 64-site tiles per time slice) with random weights: the
+    oracle's forward pass, loss gradient and backward pass, computed once."""
+    dims = (16, 8, 8, 8)
+    gop, oop, _, _ = make_pair(dims, -0.05, 1.7, 0.3, seed=37)
+    W = oracle.nn_identity_weights(seed=8, scale=0.3)
+    r = syn.gaussian_spinor(dims, 38)
+    e = syn.gaussian_spinor(dims, 39)
+    out, _ = oracle.nn_forward(oop, W, r)
+    L, g, acts = oracle.nn_loss(oop, W, r, e)
+    grads, gin = oracle.nn_backward(oop, W, acts, g)
+    yield gop, W, r, out, g, grads, gin
+    gop.close()
+
+
+@pytest.mark.parametrize("f32,tol,gtol", [(True, 1e-5, 1e-4), (False, 1e-2, 3e-2)])
+def test_random_weights_16x8c3(net16, f32, tol, gtol):
+    import torch
+    gop, W, r, out, g, grads, gin = net16
+    w = qdw.nn_weights_tensor(W)
+    y = gop.new_field()
+    qdw.nn_forward(gop, w, gop.pack(r), y, f32_mixing=f32)
+    assert rel(gop.unpack(y).cpu().numpy(), out) <= tol
+    dW = torch.zeros_like(w)
+    gi = gop.new_field()
+    qdw.nn_backward(gop, w, gop.pack(r), gop.pack(2.0 * g), dW, gi, f32_mixing=f32)
+    got_w = qdw.nn_weights_layers(dW)
+    for l in range(3):
+        assert rel(got_w[l], grads[l]) <= gtol, (l, rel(got_w[l], grads[l]))
+    assert rel(gop.unpack(gi).cpu().numpy(), 2.0 * gin) <= gtol

@@ -253,3 +253,43 @@ def test_gcr_sap_eo_reaches_fp64_residual(lat8, solved, sdtype):
     r = eta - oop.dw(x)
     assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(eta)
     assert rel(x, solved) <= 1e-7
+
+
+# ---------------------------------------------------------------- 16^3 x 32: 2048 blocks
+
+@pytest.fixture(scope="module")
+def lat16():
+    """32 x 16^3 with the benchmark's SAP field recipe (eps 0.35, m0 -0.08): 2048 4^4 blocks,
+    1024 of each colour -- many workgroups per colour sweep, as at 24^3 x 48."""
+    dims = (32, 16, 16, 16)
+    gop, oop, _, _ = make_pair(dims, -0.08, 1.7, 0.35, seed=7388 + 21)
+    rho = syn.gaussian_spinor(dims, 7388 + 21 + 1000)
+    yield dims, gop, oop, rho
+    gop.close()
+
+
+@pytest.mark.parametrize("eo", [False, True])
+def test_sap_2048_blocks_matches_oracle(lat16, eo):
+    dims, gop, oop, rho = lat16
+    bs = (4, 4, 4, 4)
+    r = gop.pack(rho, "f64")
+    phi = gop.new_field("f64")
+    qdw.sap_apply(gop, r, phi, 2, 4, bs, "f32", eo=eo)
+    got = gop.unpack(phi, "f64").cpu().numpy()
+    want = (oracle.sap_eo if eo else oracle.sap)(oop, rho, bs, 2, 4)
+    assert rel(got, want) <= SAP_TOL["f32"], (eo, rel(got, want))
+
+
+def test_adaptive_sap_2048_blocks_matches_oracle(lat16):
+    dims, gop, oop, rho = lat16
+    bs = (4, 4, 4, 4)
+    tol = 1e-3 * np.linalg.norm(rho) / 2048
+    got, cyc, st = _adaptive_gpu(gop, rho, bs, 3, 8, 0.45, tol, "f32")
+    want, ocyc, osteps = oracle.sap_adaptive(oop, rho, bs, 3, 8, 0.45, tol)
+    assert cyc == ocyc, (cyc, ocyc)
+    ost = np.array(osteps).reshape(ocyc, 2, -1)
+    same = np.mean(st[:cyc] == ost)
+    if same == 1.0:
+        assert rel(got, want) <= 1e-4, rel(got, want)
+    else:
+        assert same >= 0.95 and rel(got, want) <= 5e-2, (same, rel(got, want))

@@ -621,6 +621,22 @@ def test_nn_with_dirac_weights_is_the_operator(bc):
     assert np.abs(out - want).max() <= 1e-13 * np.abs(want).max()
 
 
+@pytest.mark.parametrize("dims, bc", [((4, 2, 4, 6), -1), ((6, 4, 4, 4), 1)])
+def test_nn_at_sites_equals_full_forward(dims, bc):
+    """The per-site network evaluation (its own transport code, limited to the receptive
+    field) agrees with the full forward pass at every site and on a scrambled subset."""
+    su3, th = syn.gauge_field(dims, 0.3, 0.1, 47)
+    op = oracle.Operator(dims, su3, th, -0.05, 1.7, bc)
+    W = _rand_weights(3)
+    r = syn.gaussian_spinor(dims, 11)
+    want, _ = oracle.nn_forward(op, W, r)
+    got = oracle.nn_at_sites(dims, bc, op.u, W, r, np.arange(op.V))
+    assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max()
+    sub = np.random.default_rng(2).permutation(op.V)[:29]
+    got = oracle.nn_at_sites(dims, bc, op.u, W, r, sub)
+    assert np.abs(got - want[sub]).max() <= 1e-13 * np.abs(want).max()
+
+
 def test_nn_linear_and_equivariant():
     dims = (4, 2, 2, 4)
     su3, th = syn.gauge_field(dims, 0.3, 0.1, 45)
@@ -804,3 +820,48 @@ def test_sap_eo_fewer_steps_than_plain_blocks(op44):
     a = np.linalg.norm(rho - op44.dw(oracle.sap_eo(op44, rho, BS2, 2, 3)))
     b = np.linalg.norm(rho - op44.dw(oracle.sap(op44, rho, BS2, 2, 3)))
     assert a < b, (a, b)
+
+
+# ---------------------------------------------------------------- rounding bound of D^
+
+def _round_to(x, mant):
+    """Round to `mant` fraction bits, to nearest (the 16-bit formats' significands)."""
+    if np.iscomplexobj(x):
+        return _round_to(x.real, mant) + 1j * _round_to(x.imag, mant)
+    m, e = np.frexp(x)
+    return np.ldexp(np.round(m * 2.0 ** (mant + 1)) / 2.0 ** (mant + 1), e)
+
+
+@pytest.mark.parametrize("mant", [10, 7])
+def test_schur_rounding_bound_holds_for_emulated_storage(mant):
+    """The first-order bound the GPU test of the reduced operator uses (schur_bound.py)
+    covers the errors of the same computation with every stored number rounded to a
+    16-bit significand (10 fraction bits: binary16, 7: bfloat16), emulated here in FP64."""
+    import sys, os
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from schur_bound import schur_error_bound
+    dims = (6, 4, 6, 10)
+    su3, th = syn.gauge_field(dims, 0.3, 0.1, 61)
+    op = oracle.Operator(dims, su3, th, -0.05, 1.7, -1)
+    sc = oracle.Schur(op)
+    v = syn.gaussian_spinor(dims, 62)
+    u = 2.0 ** -(mant + 1)
+    for dag in (False, True):
+        bound, out = schur_error_bound(op, sc, v, u, dag=dag)
+        em = oracle.Operator(dims, su3, th, -0.05, 1.7, -1)
+        r0, r1 = _round_to(op.u[..., 0, :], mant), _round_to(op.u[..., 1, :], mant)
+        d = _round_to(np.linalg.det(op.u), mant)
+        em.u = np.ascontiguousarray(np.stack([r0, r1, d[..., None] * np.conj(np.cross(r0, r1))],
+                                             axis=-2))
+        em.A = np.ascontiguousarray(_round_to(op.A, mant))
+        esc = oracle.Schur(em)
+        esc.Ainv = _round_to(sc.Ainv, mant)
+        pe = _round_to(np.where(sc.even, v, 0), mant)
+        fwd = em.dw_dag if dag else em.dw
+        y = fwd(pe)
+        t = _round_to(np.where(sc.odd, esc._ainv(np.where(sc.odd, y, 0)), 0), mant)
+        got = _round_to(np.where(sc.even, y - fwd(t), 0), mant)
+        err = np.abs(got - out)[sc.even[:, 0, 0]]
+        b = bound[sc.even[:, 0, 0]]
+        assert np.all(err <= b), float((err / np.maximum(b, 1e-300)).max())
+        assert (err / np.maximum(b, 1e-300)).max() > 0.02  # and it is not vacuous
