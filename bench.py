@@ -24,10 +24,12 @@ Also reported, each timed on its own outside the K steps:
   * a batch of 40 right-hand sides over three lattices of different volumes (16^3 x 32
     with 12 point sources, one per spin and colour; 24^3 x 48 with 4 Gaussian sources;
     8^3 x 16 with 24 Gaussian sources; three independent fields, eps = 0.3, m0 = -0.05),
-    mixed-precision SAP-GCR to 1e-10 as one graph-replayed batch against the same 40
-    solves one after another, with plain and with even-odd reduced SAP blocks, and the
-    D-kernel shape the autotuner picked per lattice;
-  * the FP64 oracle timed on the host on a bounded sample (cpu_baseline).
+    mixed-precision SAP-GCR to 1e-10 as one captured batch plan (one or two GCR restart
+    cycles per graph launch, one host wait per launch) against the same 40 solves one
+    after another, with plain and with even-odd reduced SAP blocks, and the D-kernel
+    shape the autotuner picked per lattice;
+  * the FP64 oracle timed on the host (cpu_baseline): D at 32^3 x 64 on all host cores and
+    on one core, and CGNE / GCR / SAP-GCR solves at small lattices beside the GPU's.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-solves]
                        [--legs multi,cgne,nn,gcr,batch] [--autotune] [--calibrate]
@@ -102,26 +104,80 @@ def time_launches(fn, n):
     return e0.elapsed_time(e1) / 1e3 / n
 
 
-def cpu_baseline():
-    """The FP64 oracle's D on a bounded sample: an 8 x 32^3 slab (1/8 of the volume) of
-    the same field recipe, 3 applications, clover build excluded."""
+CPU_CGNE_DIMS, CPU_SAP_DIMS = (16, 8, 8, 8), (8, 8, 8, 8)
+
+
+def cpu_baseline(su3, th, psi):
+    """The FP64 oracle (C site loops with OpenMP, -O3 -march=native, built on this host),
+    timed on this host: D at the full 32^3 x 64 on all host cores (median of 5) and on one
+    core (one application), clover build excluded; and two solves to rel. residual 1e-10
+    at smaller lattices of the same recipes, with the GPU timed on the same solves:
+    CGNE on D^+ D at 16 x 8^3 (eps 0.3, m0 -0.05) and flexible GCR at 8^4 (eps 0.35,
+    m0 -0.08), plain and with SAP (4^4 blocks, 5 cycles, 4 MR steps)."""
     import oracle
+    from paper_2202_07388_amd import qdw
     from paper_2202_07388_amd import synthetic as syn
-    dims = (8, 32, 32, 32)
-    su3, th = syn.gauge_field(dims, EPS, EPS_U1, SEED)
-    op = oracle.Operator(dims, su3, th, M0, CSW, -1)
-    psi = syn.gaussian_spinor(dims, SEED + 1000)
+    oracle.use_native_build()
+    nproc = len(os.sched_getaffinity(0))
+    oracle.set_threads(nproc)
+    cores = oracle.max_threads()
+    V = int(np.prod(DIMS))
+    op = oracle.Operator(DIMS, su3, th, M0, CSW, -1)
     op.dw(psi)
-    n = 3
-    t0 = time.perf_counter()
-    for _ in range(n):
+    ts = []
+    for _ in range(5):
+        t0 = time.perf_counter()
         op.dw(psi)
-    dt = (time.perf_counter() - t0) / n
-    V = int(np.prod(dims))
-    return {"value": round(BYTES_PER_SITE["f64"] * V / dt / 1e9, 3), "unit": "GB/s",
-            "cores": 1, "kind": "oracle",
-            "sample": "oracle D (FP64, one thread) on an 8x32^3 slab of the same recipe, "
-                      "mean of 3 applications, clover build excluded; %.3f s each" % dt}
+        ts.append(time.perf_counter() - t0)
+    d_all = float(np.median(ts))
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    op.dw(psi)
+    d_one = time.perf_counter() - t0
+    oracle.set_threads(cores)
+    del op
+    solves = {}
+    # CGNE, FP64, host and GPU
+    su3c, thc = syn.gauge_field(CPU_CGNE_DIMS, EPS, EPS_U1, SEED + 5)
+    eta = syn.gaussian_spinor(CPU_CGNE_DIMS, SEED + 5 + 1000)
+    oc = oracle.Operator(CPU_CGNE_DIMS, su3c, thc, M0, CSW, -1)
+    t0 = time.perf_counter()
+    _, st = oracle.cgne(oc, eta, 1e-10, 5000)
+    solves["cgne_f64_16x8c3"] = {"host_s": round(time.perf_counter() - t0, 3), "host_steps": st}
+    gc = qdw.Op(CPU_CGNE_DIMS, su3c, thc, M0, CSW, -1)
+    e = gc.pack(eta)
+    for inner in ("f64", "f16"):
+        info = qdw.cgne_solve(gc, e, gc.new_field(), res=1e-10, nmx=5000, inner=inner)
+        solves["cgne_f64_16x8c3"]["gpu_%s_inner_s" % inner] = round(info["t_sec"], 4)
+        solves["cgne_f64_16x8c3"]["gpu_%s_inner_steps" % inner] = info["n_steps"]
+    gc.close()
+    # flexible GCR, plain and SAP-preconditioned
+    su3s, ths = syn.gauge_field(CPU_SAP_DIMS, SAP_EPS, EPS_U1, SEED + 15)
+    eta = syn.gaussian_spinor(CPU_SAP_DIMS, SEED + 15 + 1000)
+    os_ = oracle.Operator(CPU_SAP_DIMS, su3s, ths, SAP_M0, CSW, -1)
+    gs = qdw.Op(CPU_SAP_DIMS, su3s, ths, SAP_M0, CSW, -1)
+    e = gs.pack(eta)
+    bs = (4, 4, 4, 4)
+    for name, M, kw in (("gcr_plain_8c4", None, dict(precond="none")),
+                        ("sap_gcr_8c4", lambda v: oracle.sap(os_, v, bs, 5, 4),
+                         dict(precond="sap", sdtype="f32", ncy=5, nmr=4, bs=bs))):
+        t0 = time.perf_counter()
+        _, st = oracle.fgcr(os_, eta, 1e-10, 5000, 16, M)
+        rec = {"host_s": round(time.perf_counter() - t0, 3), "host_steps": st}
+        info = qdw.sap_gcr_solve(gs, e, gs.new_field(), res=1e-10, nmx=5000, nkv=16, **kw)
+        rec.update(gpu_s=round(info["t_sec"], 4), gpu_steps=info["n_steps"])
+        solves[name] = rec
+    gs.close()
+    return {"value": round(BYTES_PER_SITE["f64"] * V / d_all / 1e9, 3), "unit": "GB/s",
+            "cores": cores, "kind": "oracle",
+            "sample": "oracle D (FP64, C with OpenMP over sites, -O3 -march=native) at the full "
+                      "32^3x64 on %d threads, median of 5 applications (%.3f s each), clover "
+                      "build excluded; solves at 16x8^3 (CGNE) and 8^4 (GCR) as listed"
+                      % (cores, d_all),
+            "one_core_GB_s": round(BYTES_PER_SITE["f64"] * V / d_one / 1e9, 3),
+            "one_core_s": round(d_one, 3),
+            "host_nproc": nproc,
+            "solves": solves}
 
 
 def solve_record(info):
@@ -155,11 +211,17 @@ def multi_rhs(op, qdw, psi, n=4):
 
 
 def cgne_solves(op, qdw, psi):
-    """Plain FP64 CG against mixed precision, D^+ D psi = eta to 1e-10 (32^3 x 64)."""
+    """Plain FP64 CG against mixed precision, D^+ D psi = eta to 1e-10 (32^3 x 64). The
+    mixed legs keep the search direction across resets (reliable updates after a drop of
+    10); the *_paper_reset legs restart CG at every reset, triggered after a drop of
+    10 eps of the working type (Sec. 2, Fig. 1)."""
     eta = op.pack(psi, "f64")
     out = {}
     for name, kw in (("f64", dict(inner="f64")), ("f32", dict(inner="f32")),
                      ("f16", dict(inner="f16")), ("bf16", dict(inner="bf16")),
+                     ("f32_paper_reset", dict(inner="f32", keep_p=False)),
+                     ("f16_paper_reset", dict(inner="f16", keep_p=False)),
+                     ("bf16_paper_reset", dict(inner="bf16", keep_p=False)),
                      ("cascade_bf16_f32_f64", dict(cascade=True)),
                      ("schur_f64", dict(inner="f64", schur=True)),
                      ("schur_f32", dict(inner="f32", schur=True)),
@@ -281,16 +343,24 @@ def batched_solves(qdw, syn):
 
 
 def batched_run(qdw, ops, etas, shapes, precond):
+    """The batch as captured plans (qdw.Batch) of 1 and 2 restart cycles per graph launch:
+    capture time, a warm-up solve, then one timed solve each; against the same solves one
+    after another."""
     import torch
     kw = dict(res=1e-10, nmx=2000, nkv=16, ncy=5, nmr=4, bs=(4, 4, 4, 4), sdtype="f16",
               precond=precond)
-    psis = [o.new_field("f64") for o in ops]
-    qdw.sap_gcr_solve_batched(ops[:2], etas[:2], psis[:2], **kw)  # warm-up (code objects)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    infos, graph_ms = qdw.sap_gcr_solve_batched(ops, etas, psis, **kw)
-    torch.cuda.synchronize()
-    t_batch = time.perf_counter() - t0
+    plans = {}
+    for cycles in (1, 2):
+        plan = qdw.Batch(ops, cycles=cycles, **kw)
+        psis = [o.new_field("f64") for o in ops]
+        plan.solve(etas, psis)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos, launches = plan.solve(etas, psis)
+        torch.cuda.synchronize()
+        plans[cycles] = (time.perf_counter() - t0, launches, plan.capture_ms, infos)
+        plan.close()
+        del psis
     t0 = time.perf_counter()
     single = []
     for o, e in zip(ops, etas):
@@ -299,6 +369,8 @@ def batched_run(qdw, ops, etas, shapes, precond):
         del x
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
+    best = min(plans, key=lambda c: plans[c][0])
+    t_batch, _, _, infos = plans[best]
     per = {}
     i = 0
     for dims, kind, n, seed in BATCH:
@@ -314,10 +386,13 @@ def batched_run(qdw, ops, etas, shapes, precond):
         i += n
     site_rhs = sum(int(np.prod(d)) * n for d, _, n, _ in BATCH)
     rec = {"rhs": len(ops), "site_rhs": site_rhs, "s_batched": round(t_batch, 4),
-           "graph_setup_ms": round(graph_ms, 2), "s_sequential_single": round(t_seq, 4),
+           "cycles_per_launch": best,
+           "plans": {str(c): {"s": round(v[0], 4), "graph_launches": v[1],
+                              "capture_ms": round(v[2], 2)} for c, v in plans.items()},
+           "s_sequential_single": round(t_seq, 4),
            "speedup": round(t_seq / t_batch, 3), "lattices": per,
            "settings": "SAP-GCR nkv 16, 4^4 blocks, ncy 5, nmr 4, FP16 SAP storage, res 1e-10, "
-                       "precond %s" % precond}
+                       "precond %s; one host wait per graph launch" % precond}
     log("  batched %s: %s" % (precond, json.dumps(rec)))
     return rec
 
@@ -360,7 +435,8 @@ def main():
     psi = syn.gaussian_spinor(DIMS, SEED + 1000)
     log("  %.1f s; creating the operator" % (time.time() - t0))
     op = qdw.Op(DIMS, su3, th, M0, CSW, -1)
-    del su3, th
+    if args.no_cpu_baseline:
+        del su3, th
     V = op.V
     if args.autotune:
         log("autotuning the D kernel ...")
@@ -380,19 +456,8 @@ def main():
     torch.cuda.synchronize()
 
     x64, y64 = fields["f64"]
-    step = lambda: qdw.dw_apply(op, x64, y64, "f64")
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    log("timing %d FP64 applications" % args.steps)
-    # timed region: exactly K steps, bracketed by synchronisation
-    torch.cuda.synchronize()
-    t_wall0 = time.perf_counter()
-    dt = time_launches(step, args.steps)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_wall0
-    gbs = BYTES_PER_SITE["f64"] * V / dt / 1e9
-
+    # the other precisions and D^+ first: the timed FP64 launches then run on a GPU in its
+    # steady state (the first launches after the operator's set-up run up to 7 % slower)
     other = {}
     for prec in ("f32", "f16"):
         x, y = fields[prec]
@@ -406,6 +471,19 @@ def main():
     d_dag = time_launches(lambda: qdw.dw_dag_apply(op, x64, y64, "f64"), 50)
     other["f64_dag"] = {"ms": round(d_dag * 1e3, 4),
                         "GB_s": round(BYTES_PER_SITE["f64"] * V / d_dag / 1e9, 1)}
+
+    step = lambda: qdw.dw_apply(op, x64, y64, "f64")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log("timing %d FP64 applications" % args.steps)
+    # timed region: exactly K steps, bracketed by synchronisation
+    torch.cuda.synchronize()
+    t_wall0 = time.perf_counter()
+    dt = time_launches(step, args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall0
+    gbs = BYTES_PER_SITE["f64"] * V / dt / 1e9
     del fields
 
     if args.calibrate:
@@ -459,7 +537,7 @@ def main():
         out["batched_40rhs"] = batched_solves(qdw, syn)
     if not args.no_cpu_baseline:
         log("timing the oracle on the host (bounded sample) ...")
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline(su3, th, psi)
     print(json.dumps(out), flush=True)
 
 

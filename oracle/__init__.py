@@ -39,21 +39,52 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
-def build(force: bool = False) -> str:
-    """Compile oracle.c into liboracle.so with gcc (plain C99, -O2)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", _SRC,
-                               "-o", tmp, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+_NATIVE = os.path.join(_HERE, "liboracle_native.so")
+
+
+def build(force: bool = False, native: bool = False) -> str:
+    """Compile oracle.c with gcc (C99, -O3, OpenMP over sites): liboracle.so for any
+    x86-64 host, or with native=True liboracle_native.so tuned for the host that builds
+    it (-march=native; built and used on the machine that times the oracle)."""
+    out = _NATIVE if native else _LIB
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+        tmp = out + ".tmp%d" % os.getpid()
+        flags = ["-O3", "-std=gnu99", "-fopenmp", "-fPIC", "-shared"]
+        if native:
+            flags.append("-march=native")
+        subprocess.check_call(["gcc", *flags, _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, out)
+    return out
+
+
+def use_native_build():
+    """Switch this process's oracle to the -march=native build (before first use)."""
+    global _lib, _LIB
+    if _lib is not None and _LIB == _NATIVE:
+        return
+    if _lib is not None:
+        raise RuntimeError("oracle already loaded; switch before the first call")
+    build(force=True, native=True)  # always for the host at hand
+    _LIB = _NATIVE
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the oracle's site loops."""
+    lib().oracle_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(lib().oracle_max_threads())
 
 
 def lib():
     global _lib
     if _lib is None:
-        build()
+        if _LIB != _NATIVE:
+            build()
         L = ctypes.CDLL(_LIB)
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
+        L.oracle_max_threads.restype = ctypes.c_int
         P = ctypes.c_void_p
         L.oracle_gamma.argtypes = [P]
         L.oracle_neighbours.argtypes = [P, P]

@@ -31,6 +31,9 @@
  * spin projection, no compression, no even-odd ordering: sites are visited in canonical
  * order ((x0*L1 + x1)*L2 + x2)*L3 + x3 with time slowest.
  *
+ * Site loops are OpenMP parallel loops (each iteration writes only its own site, so the
+ * result does not depend on the thread count); oracle_set_threads sets the count.
+ *
  * Layouts (all complex numbers are interleaved (re, im) doubles):
  *   u    [V][4][3][3]   links U_mu(x) (the full U(3) link: SU(3) part times U(1) phase)
  *   A    [V][12][12]    clover matrix per site, index (spin*3 + colour)
@@ -38,6 +41,7 @@
  */
 #include <complex.h>
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -72,6 +76,10 @@ static void init_gamma(void)
 }
 
 /* Export of the basis so that tests can check the Clifford algebra on it. */
+void oracle_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+
+int oracle_max_threads(void) { return omp_get_max_threads(); }
+
 void oracle_gamma(double *out /* [4][4][4] complex */)
 {
     init_gamma();
@@ -199,6 +207,7 @@ void oracle_clover(const int d[4], const double *u_, double m0, double csw, doub
                     sig[mu][nu][a][b] = 0.5 * I * z;
                 }
 
+#pragma omp parallel for schedule(static)
     for (long x = 0; x < V; ++x) {
         cplx *Ax = A + x * 144;
         for (int i = 0; i < 144; ++i) Ax[i] = 0;
@@ -282,6 +291,7 @@ static void dirac(const int d[4], const int *bs, int bc_t, const cplx *u, const 
                 Pm[mu][a][b] = one - G[mu][a][b];
                 Pp[mu][a][b] = one + G[mu][a][b];
             }
+#pragma omp parallel for schedule(static)
     for (long x = 0; x < V; ++x) {
         cplx *o = out + x * 12;
         const cplx *Ax = A + x * 144;
@@ -330,6 +340,7 @@ void oracle_u3_links(long V, const double *su3_, const double *theta, double *u_
 {
     const cplx *su3 = (const cplx *)su3_;
     cplx *u = (cplx *)u_;
+#pragma omp parallel for schedule(static)
     for (long l = 0; l < V * 4; ++l) {
         cplx ph = cexp(I * theta[l]);
         for (int i = 0; i < 9; ++i) u[l * 9 + i] = ph * su3[l * 9 + i];
@@ -365,6 +376,7 @@ void oracle_dw_at(const int d[4], int bc_t, const double *u_, double m0, double 
                 Pm[mu][a][b] = one - G[mu][a][b];
                 Pp[mu][a][b] = one + G[mu][a][b];
             }
+#pragma omp parallel for schedule(static)
     for (long k = 0; k < n; ++k) {
         long x = sites[k];
         cplx Ax[144];

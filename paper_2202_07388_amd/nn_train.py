@@ -1,7 +1,7 @@
 """Training pipeline of the learned preconditioner (library calls only).
 
-Pairs come from the solver itself: for a source eta, plain FP64 flexible GCR is run for
-k = 1, 2, ... steps; its iterate psi_k gives the residual rho_k = eta - D psi_k and the
+Pairs come from the solver itself: for a source eta, the iterates psi_k of plain FP64
+flexible GCR after k = 1, 2, ... steps give the residual rho_k = eta - D psi_k and the
 error e_k = x* - psi_k = D^-1 rho_k, with x* the solution to 1e-12. The network is then
 fitted to rho_k -> e_k by Adam on the GPU (nn_train_step: forward, loss, backward and
 update all in the library's kernels), with the error measured in the D-norm by default.
@@ -30,38 +30,67 @@ def init_weights(m0: float, seed: int, noise: float = 1e-3):
 
 def solver_pairs(op: "qdw.Op", etas, steps: int, store: str = "bf16", nkv: int = 16,
                  log=None):
-    """Residual/error pairs from plain FP64 GCR runs on the given FP64 sources."""
+    """Residual/error pairs from plain FP64 GCR (restart nkv) on the given FP64 sources.
+
+    The iterate after m full cycles and j more steps is psi_{m nkv} plus the iterate of a
+    GCR run of j steps from zero on the residual eta - D psi_{m nkv} (a restart is exactly
+    such a fresh start), so the pairs of one cycle come from runs of 1..nkv steps on that
+    cycle's residual: sum_j j = nkv (nkv + 1) / 2 applications of D per cycle, instead of
+    rerunning the whole solve from zero for every k."""
     rhos, errs = [], []
     xs = op.new_field("f64")
+    delta = op.new_field("f64")
+    base = op.new_field("f64")
+    src = op.new_field("f64")
     psi = op.new_field("f64")
     t = op.new_field("f64")
+
+    def keep(rho, err):
+        if store == "f64":
+            rhos.append(rho)
+            errs.append(err)
+            return
+        r_s, e_s = op.new_field(store), op.new_field(store)
+        n2 = qdw.norm2(op, rho)
+        s = np.sqrt(24.0 * op.V / n2)           # unit component size for storage
+        qdw.convert(op, rho, "f64", r_s, store, s)
+        qdw.convert(op, err, "f64", e_s, store, s)
+        rhos.append(r_s)
+        errs.append(e_s)
+
     for n, eta in enumerate(etas):
         info = qdw.sap_gcr_solve(op, eta, xs, res=1e-12, nmx=20000, nkv=nkv, precond="none")
         if info["status"] <= 0:
             raise qdw.QdwError("pair generation: reference solve failed: %s" % info)
-        for k in range(1, steps + 1):
-            inf = qdw.sap_gcr_solve(op, eta, psi, res=1e-14, nmx=k, nkv=nkv, precond="none")
-            if inf["status"] >= 0:
-                break  # converged: no further useful pairs from this source
-            qdw.dw_apply(op, psi, t, "f64")
-            rho = op.new_field("f64")
-            qdw.axpby(op, 1.0, eta, 0.0, rho)
-            qdw.axpby(op, -1.0, t, 1.0, rho)          # rho = eta - D psi
-            err = op.new_field("f64")
-            qdw.axpby(op, 1.0, xs, 0.0, err)
-            qdw.axpby(op, -1.0, psi, 1.0, err)        # e = x* - psi
-            if store == "f64":
-                rhos.append(rho)
-                errs.append(err)
-            else:
-                r_s, e_s = op.new_field(store), op.new_field(store)
-                n2 = qdw.norm2(op, rho)
-                s = np.sqrt(24.0 * op.V / n2)           # unit component size for storage
-                qdw.convert(op, rho, "f64", r_s, store, s)
-                qdw.convert(op, err, "f64", e_s, store, s)
-                rhos.append(r_s)
-                errs.append(e_s)
+        qdw.axpby(op, 0.0, eta, 0.0, base)           # psi_0 = 0
+        qdw.axpby(op, 1.0, eta, 0.0, src)            # its residual
+        k, done = 0, False
+        while k < steps and not done:
+            for j in range(1, nkv + 1):
+                inf = qdw.sap_gcr_solve(op, src, delta, res=1e-14, nmx=j, nkv=nkv,
+                                        precond="none")
+                qdw.axpby(op, 1.0, base, 0.0, psi)
+                qdw.axpby(op, 1.0, delta, 1.0, psi)  # psi_k = psi_base + delta
+                if inf["status"] >= 0:
+                    done = True                     # converged: no further useful pairs
+                    break
+                qdw.dw_apply(op, psi, t, "f64")
+                rho = op.new_field("f64")
+                qdw.axpby(op, 1.0, eta, 0.0, rho)
+                qdw.axpby(op, -1.0, t, 1.0, rho)      # rho = eta - D psi
+                err = op.new_field("f64")
+                qdw.axpby(op, 1.0, xs, 0.0, err)
+                qdw.axpby(op, -1.0, psi, 1.0, err)    # e = x* - psi
+                keep(rho, err)
                 del rho, err
+                k += 1
+                if k >= steps:
+                    break
+            # next cycle: from the iterate after nkv steps
+            qdw.axpby(op, 1.0, psi, 0.0, base)
+            qdw.dw_apply(op, base, t, "f64")
+            qdw.axpby(op, 1.0, eta, 0.0, src)
+            qdw.axpby(op, -1.0, t, 1.0, src)
         if log:
             log("pairs: source %d done, %d pairs" % (n, len(rhos)))
     return rhos, errs

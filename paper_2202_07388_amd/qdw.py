@@ -198,7 +198,7 @@ class Op:
         lat = Lattice(*self.dims, self.bc_t)
         nd = int(L.qdw_op_device_bytes(ctypes.byref(lat)))
         if nd == 0:
-            raise QdwError("qdw_create: invalid lattice %s" % (self.dims,))
+            raise QdwError("qdw_create: %s" % L.qdw_last_error().decode(errors="replace"))
         # the operator's device and host blocks are torch tensors: PyTorch owns the memory
         self._dev_mem = torch.empty(nd, dtype=torch.uint8, device=dev)
         self._host_mem = torch.empty(int(L.qdw_op_host_bytes()), dtype=torch.uint8,
