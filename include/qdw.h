@@ -388,6 +388,21 @@ size_t qdw_sap_workspace_bytes(const qdw_op* op, qdw_prec sdtype);
 int sap_apply(qdw_op* op, const void* rho, void* phi, int ncy, int nmr, const int bs[4],
               qdw_prec sdtype, void* work, size_t work_bytes, void* stream);
 
+/* sap_apply without a workspace argument, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the SAP fields live in a static device array of qdw_sap_noalloc_max_bytes() bytes
+ * (24 MiB) that each GPU the library runs on holds until the process ends; its device
+ * address is looked up on the first call on each device. Same kernels and results as
+ * sap_apply; no allocation of any kind. QDW_EWORKSPACE when the lattice needs more than
+ * the maximum (qdw_sap_workspace_bytes > 24 MiB: above about 174,000 sites with FP16/BF16
+ * storage, 87,000 with FP32). Every call on one GPU shares that GPU's array (its contents
+ * are whatever the last call left; everything the application reads is written first):
+ * calls that overlap on one GPU, from several streams or threads, race. Like sap_apply
+ * it reads |rho| back to the host (synchronises the stream). */
+size_t qdw_sap_noalloc_max_bytes(void);
+int sap_apply_noalloc(qdw_op* op, const void* rho, void* phi, int ncy, int nmr, const int bs[4],
+                      qdw_prec sdtype, void* stream);
+
 /* As sap_apply, with every block problem D_b chi = r_b solved through its even-odd
  * reduction (the site-diagonal clover term A, the in-block hops between the parities):
  * r^_e = r_e - D_eo A_oo^-1 r_o; nmr MR steps from 0 on the reduced block operator

@@ -15,6 +15,9 @@
 // After a colour's block solves, the block residuals r_b are exactly the new residual
 // on that colour; the other colour's residual loses the hops from the block corrections
 // that cross into it (D_partial chi, Fig. 3 right), applied by a second kernel.
+#include <map>
+#include <mutex>
+
 #include "sap.h"
 
 #include "dirac_core.h"
@@ -988,4 +991,54 @@ extern "C" int sap_adaptive_apply(qdw_op* op, const void* rho, void* phi, int nc
         *cycles = *(const int*)op->host_scalars;
     }
     return QDW_OK;
+}
+
+// ------------------------------------------------------------------ allocation-free SAP
+//
+// For callers that cannot allocate device memory: the three storage-precision fields of
+// the SAP application live in a file-scope device array. Its host-side name is only a
+// stand-in; the device address is looked up once per device (with that device current)
+// and kept.
+
+namespace {
+constexpr size_t kStaticScratchBytes = (size_t)24 << 20;
+__device__ __align__(256) char scratch[kStaticScratchBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, char*> g_scratch_ptr;  // device -> address of that device's copy
+
+int scratch_on_current_device(char** out)
+{
+    int dev = -1;
+    QDW_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it == g_scratch_ptr.end()) {
+        void* p = nullptr;
+        QDW_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        QDW_CHECK(p, QDW_EDEVICE, "sap_apply_noalloc: no device address for the static scratch");
+        it = g_scratch_ptr.emplace(dev, (char*)p).first;
+    }
+    *out = it->second;
+    return QDW_OK;
+}
+}  // namespace
+
+extern "C" size_t qdw_sap_noalloc_max_bytes(void) { return kStaticScratchBytes; }
+
+extern "C" int sap_apply_noalloc(qdw_op* op, const void* rho, void* phi, int ncy, int nmr,
+                                 const int bs[4], qdw_prec sdtype, void* stream)
+{
+    QDW_CHECK(op, QDW_EINVAL, "sap_apply_noalloc: null argument");
+    QDW_CHECK(sdtype >= QDW_F32 && sdtype <= QDW_BF16S, QDW_EINVAL,
+              "sap_apply_noalloc: sdtype must be QDW_F32, QDW_F16S or QDW_BF16S");
+    const size_t need = sap_workspace(op, sdtype);
+    QDW_CHECK(need <= kStaticScratchBytes, QDW_EWORKSPACE,
+              "sap_apply_noalloc: this lattice needs " + std::to_string(need) +
+                  " bytes of SAP scratch, above the static maximum of " +
+                  std::to_string(kStaticScratchBytes) + " (use sap_apply with a workspace)");
+    char* p = nullptr;
+    if (const int rc = scratch_on_current_device(&p)) return rc;
+    return sap_apply_impl("sap_apply_noalloc", op, rho, phi, ncy, nmr, bs, sdtype, p,
+                          kStaticScratchBytes, stream, false);
 }

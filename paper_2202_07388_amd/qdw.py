@@ -114,6 +114,9 @@ _OPTIONAL: list = [
                    ctypes.c_int, _P, ctypes.c_size_t, _P], ctypes.c_int),
     ("sap_eo_apply", [_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int * 4),
                       ctypes.c_int, _P, ctypes.c_size_t, _P], ctypes.c_int),
+    ("qdw_sap_noalloc_max_bytes", [], ctypes.c_size_t),
+    ("sap_apply_noalloc", [_P, _P, _P, ctypes.c_int, ctypes.c_int,
+                           ctypes.POINTER(ctypes.c_int * 4), ctypes.c_int, _P], ctypes.c_int),
     ("qdw_axpby", [_P, ctypes.c_double, _P, ctypes.c_double, _P, ctypes.c_int, _P], ctypes.c_int),
     ("qdw_norm2", [_P, _P, ctypes.c_int, ctypes.POINTER(ctypes.c_double), _P], ctypes.c_int),
     ("qdw_cdot", [_P, _P, _P, ctypes.c_int, ctypes.POINTER(ctypes.c_double * 2), _P],
@@ -507,6 +510,16 @@ def sap_apply(op: Op, rho, phi, ncy: int = 5, nmr: int = 4, bs=(4, 4, 4, 4),
     fn, name = (L.sap_eo_apply, "sap_eo_apply") if eo else (L.sap_apply, "sap_apply")
     _check(fn(op.handle, _ptr(rho), _ptr(phi), ncy, nmr, ctypes.byref(b), PREC[sdtype],
               _ptr(ws), ws.numel(), _stream()), name)
+    return phi
+
+
+def sap_apply_noalloc(op: Op, rho, phi, ncy: int = 5, nmr: int = 4, bs=(4, 4, 4, 4),
+                      sdtype: str = "f16"):
+    """phi = M_SAP rho with the library's static device scratch: no workspace, no
+    allocation (lattices whose SAP fields fit qdw_sap_noalloc_max_bytes())."""
+    b = (ctypes.c_int * 4)(*bs)
+    _check(load().sap_apply_noalloc(op.handle, _ptr(rho), _ptr(phi), ncy, nmr, ctypes.byref(b),
+                                    PREC[sdtype], _stream()), "sap_apply_noalloc")
     return phi
 
 
