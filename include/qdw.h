@@ -76,9 +76,9 @@ typedef struct qdw_op qdw_op; /* opaque: compressed links and clover, all precis
 const char* qdw_last_error(void);
 
 /* Device and host bytes an operator on lattice `lat` keeps: qdw_op_device_bytes(lat) for
- * the compressed links and clover blocks (and their inverses) in all four precisions and
- * the reduction scratch, about 3.2 kB per site (6.8 GB at 32^3 x 64); 0 for an invalid
- * lattice.
+ * the compressed links, the clover blocks (their inverses, and the compact form the D
+ * kernels read) in all four precisions and the reduction scratch, about 4.1 kB per site
+ * (8.6 GB at 32^3 x 64); 0 for an invalid lattice.
  * qdw_op_host_bytes() for the scalars the host reads back (8 kB). */
 size_t qdw_op_device_bytes(const qdw_lattice* lat);
 size_t qdw_op_host_bytes(void);

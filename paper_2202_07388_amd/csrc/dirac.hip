@@ -66,8 +66,8 @@ __device__ __forceinline__ void hop_load(const Geom& g, const void* in, const vo
 }
 
 // acc += U (1 -+ gamma) psi(x + mu)  or  U^+ (1 +- gamma) psi(x - mu), times the boundary
-// sign (the -1/2 comes later)
-template <int P, int MU, bool FWD, bool DAG>
+// sign; with HALF the term is scaled by -1/2 (the hopping term's factor) before it is added
+template <int P, int MU, bool FWD, bool DAG, bool HALF = false>
 __device__ __forceinline__ void hop_compute(const Geom& g, const int x[4], const HopIn<P>& b,
                                             cx<typename Traits<P>::real> acc[12])
 {
@@ -75,9 +75,14 @@ __device__ __forceinline__ void hop_compute(const Geom& g, const int x[4], const
     constexpr int SG = (FWD != DAG) ? -1 : +1;  // projector 1 + SG gamma_mu
     cx<R> h[6], w[6];
     project<R, MU, SG>(b.s, h);
-    if (MU == 0 && g.bc_t < 0 && x[0] == (FWD ? g.L[0] - 1 : 0)) {
+    const bool flip = MU == 0 && g.bc_t < 0 && x[0] == (FWD ? g.L[0] - 1 : 0);
+    if (HALF) {
+        const R f = flip ? (R)0.5 : (R)-0.5;
 #pragma unroll
-        for (int c = 0; c < 6; ++c) h[c] = {-h[c].re, -h[c].im};
+        for (int c = 0; c < 6; ++c) h[c] = scale(h[c], f);
+    } else if (flip) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) h[c] = -h[c];
     }
     su3_mul<R, !FWD>(b.u, b.d, h, w);
     expand_add<R, MU, SG>(w, acc);
@@ -100,19 +105,19 @@ __device__ __forceinline__ void load_k(int k, const Geom& g, const void* in, con
     }
 }
 
-template <int P, bool DAG>
+template <int P, bool DAG, bool HALF = false>
 __device__ __forceinline__ void compute_k(int k, const Geom& g, const int x[4], const HopIn<P>& b,
                                           cx<typename Traits<P>::real> acc[12])
 {
     switch (k) {
-    case 0: hop_compute<P, 0, true, DAG>(g, x, b, acc); break;
-    case 1: hop_compute<P, 0, false, DAG>(g, x, b, acc); break;
-    case 2: hop_compute<P, 1, true, DAG>(g, x, b, acc); break;
-    case 3: hop_compute<P, 1, false, DAG>(g, x, b, acc); break;
-    case 4: hop_compute<P, 2, true, DAG>(g, x, b, acc); break;
-    case 5: hop_compute<P, 2, false, DAG>(g, x, b, acc); break;
-    case 6: hop_compute<P, 3, true, DAG>(g, x, b, acc); break;
-    default: hop_compute<P, 3, false, DAG>(g, x, b, acc); break;
+    case 0: hop_compute<P, 0, true, DAG, HALF>(g, x, b, acc); break;
+    case 1: hop_compute<P, 0, false, DAG, HALF>(g, x, b, acc); break;
+    case 2: hop_compute<P, 1, true, DAG, HALF>(g, x, b, acc); break;
+    case 3: hop_compute<P, 1, false, DAG, HALF>(g, x, b, acc); break;
+    case 4: hop_compute<P, 2, true, DAG, HALF>(g, x, b, acc); break;
+    case 5: hop_compute<P, 2, false, DAG, HALF>(g, x, b, acc); break;
+    case 6: hop_compute<P, 3, true, DAG, HALF>(g, x, b, acc); break;
+    default: hop_compute<P, 3, false, DAG, HALF>(g, x, b, acc); break;
     }
 }
 
@@ -162,7 +167,7 @@ void dw_kernel(Geom g, RhsTable tab, int nrhs, const void* __restrict__ links,
     }
     cx<R> s[12], acc[12];
     load_spinor<P>(in, g.Vh, par, i, s);
-    clover_apply<P>(clover, g.Vh, par, i, s, acc);
+    clover54_apply<P>(clover, g.Vh, par, i, (R)g.cdiag, s, acc);
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc[c] = acc[c] - scale(hop[c], (R)0.5);
     store_spinor<P>(out, g.Vh, par, i, acc);
@@ -186,7 +191,7 @@ void dw_kernel(Geom g, RhsTable tab, int nrhs, const void* __restrict__ links,
 template <int P, bool DAG, bool PIPE>
 __device__ __forceinline__ void march_site_hops(const Geom& g, const void* in, const void* links,
                                                 const void* dets, int par, int i, const int x[4],
-                                                int lex, cx<typename Traits<P>::real> hop[12])
+                                                int lex, cx<typename Traits<P>::real> acc[12])
 {
     if constexpr (!PIPE) {
         // the six spatial hops (loop steps 2..7 of dw_kernel), one register buffer
@@ -196,7 +201,7 @@ __device__ __forceinline__ void march_site_hops(const Geom& g, const void* in, c
             int ii = i, ll = lex, xx[4] = {x[0], x[1], x[2], x[3]};
             asm volatile("" : "+v"(ii), "+v"(ll), "+v"(xx[0]), "+v"(xx[1]), "+v"(xx[2]), "+v"(xx[3]));
             load_k<P>(k, g, in, links, dets, par, ii, xx, ll, A);
-            compute_k<P, DAG>(k, g, xx, A, hop);
+            compute_k<P, DAG, true>(k, g, xx, A, acc);
         }
         return;
     }
@@ -208,9 +213,9 @@ __device__ __forceinline__ void march_site_hops(const Geom& g, const void* in, c
         int ii = i, ll = lex, xx[4] = {x[0], x[1], x[2], x[3]};
         asm volatile("" : "+v"(ii), "+v"(ll), "+v"(xx[0]), "+v"(xx[1]), "+v"(xx[2]), "+v"(xx[3]));
         load_k<P>(k + 1, g, in, links, dets, par, ii, xx, ll, B);
-        compute_k<P, DAG>(k, g, xx, A, hop);
+        compute_k<P, DAG, true>(k, g, xx, A, acc);
         if (k + 2 < 8) load_k<P>(k + 2, g, in, links, dets, par, ii, xx, ll, A);
-        compute_k<P, DAG>(k + 1, g, xx, B, hop);
+        compute_k<P, DAG, true>(k + 1, g, xx, B, acc);
     }
 }
 
@@ -301,34 +306,33 @@ __global__ __launch_bounds__(256) void dw_march_kernel(Geom g, RhsTable tab, int
             const int i = t * g.S + k;
             int x[4], lex;
             eo_coords(g, par, i, x, lex);
-            cx<R> hop[12];
-#pragma unroll
-            for (int q = 0; q < 12; ++q) hop[q] = {(R)0, (R)0};
-            cx<R> u0[6], d0;  // the site's forward t link, also used for the push below
+            // the site's forward t link serves the +t hop and the hand-over below
+            cx<R> u0[6], d0;
+            load_link<P>(links, dets, g.Vh, par, i, 0, u0, d0);
+            // (2) the partner's -t hop at t+1; slot (t+1)&1 was read one step ago, before
+            //     this step's barrier. Done first, so that the lane's own spinor is dead once
+            //     the clover term has used it (the accumulator then starts from A psi and the
+            //     hops are added scaled by -1/2: one 12-complex array fewer live)
+            if (step + 1 < g.nt) push(t, (t + 1) & 1, own, u0, d0);
+            cx<R> acc[12];
+            clover54_apply<P>(clover, g.Vh, par, i, (R)g.cdiag, own, acc);
             {
                 // +t: U_0(x) times the projected neighbour from the partner
                 cx<R> h[6], w[6];
                 get6(hp, (t + 1) & 1, h);
-                if (g.bc_t < 0 && x[0] == g.L[0] - 1) {
+                const R f = (g.bc_t < 0 && x[0] == g.L[0] - 1) ? (R)0.5 : (R)-0.5;
 #pragma unroll
-                    for (int q = 0; q < 6; ++q) h[q] = {-h[q].re, -h[q].im};
-                }
-                load_link<P>(links, dets, g.Vh, par, i, 0, u0, d0);
+                for (int q = 0; q < 6; ++q) h[q] = scale(h[q], f);
                 su3_mul<R, false>(u0, d0, h, w);
-                expand_add<R, 0, SGF>(w, hop);
+                expand_add<R, 0, SGF>(w, acc);
                 // -t: already transported by the partner
                 get6(pw, t & 1, w);
-                expand_add<R, 0, SGB>(w, hop);
-            }
-            march_site_hops<P, DAG, PIPE>(g, in, links, dets, par, i, x, lex, hop);
-            cx<R> acc[12];
-            clover_apply<P>(clover, g.Vh, par, i, own, acc);
 #pragma unroll
-            for (int q = 0; q < 12; ++q) acc[q] = acc[q] - scale(hop[q], (R)0.5);
+                for (int q = 0; q < 6; ++q) w[q] = scale(w[q], (R)-0.5);
+                expand_add<R, 0, SGB>(w, acc);
+            }
+            march_site_hops<P, DAG, PIPE>(g, in, links, dets, par, i, x, lex, acc);
             store_spinor<P>(out, g.Vh, par, i, acc);
-            // (2) the partner's -t hop at t+1; slot (t+1)&1 was read one step ago, before
-            //     this step's barrier
-            if (step + 1 < g.nt) push(t, (t + 1) & 1, own, u0, d0);
 #pragma unroll
             for (int q = 0; q < 12; ++q) own[q] = nxt[q];
         }
@@ -439,20 +443,20 @@ int launch(qdw_op* op, const RhsTable& tab, int nrhs, hipStream_t st)
         static_assert(sizeof(R) == 8 || sizeof(R) == 4, "real type");
         if (op->dw_shape[P].pipe)
             dw_march_kernel<P, DAG, true><<<nblk, 2 * g.ts, lds, st>>>(g, tab, nrhs, op->links[P],
-                                                                       op->det[P], op->clover[P]);
+                                                                       op->det[P], op->clover54[P]);
         else
             dw_march_kernel<P, DAG, false><<<nblk, 2 * g.ts, lds, st>>>(g, tab, nrhs, op->links[P],
-                                                                        op->det[P], op->clover[P]);
+                                                                        op->det[P], op->clover54[P]);
         QDW_LAUNCH_CHECK();
         return QDW_OK;
     }
     const int nblk = walk_blocks(g) * nrhs;
     if (op->dw_shape[P].pipe)
         dw_kernel<P, DAG, true><<<nblk, 2 * g.ts, 0, st>>>(g, tab, nrhs, op->links[P], op->det[P],
-                                                           op->clover[P]);
+                                                           op->clover54[P]);
     else
         dw_kernel<P, DAG, false><<<nblk, 2 * g.ts, 0, st>>>(g, tab, nrhs, op->links[P], op->det[P],
-                                                            op->clover[P]);
+                                                            op->clover54[P]);
     QDW_LAUNCH_CHECK();
     return QDW_OK;
 }

@@ -458,9 +458,9 @@ __device__ __forceinline__ void nn_path_setup(const Geom& g, int par, int i, con
 __device__ __forceinline__ void nn_link_matrix(const cx<float> u[6], cx<float> d, float sg,
                                                cx<float> m[9])
 {
-    m[6] = d * conj_(u[1] * u[5] - u[2] * u[4]);
-    m[7] = d * conj_(u[2] * u[3] - u[0] * u[5]);
-    m[8] = d * conj_(u[0] * u[4] - u[1] * u[3]);
+    m[6] = d * conj_(cmadd(u[1] * u[5], -u[2], u[4]));
+    m[7] = d * conj_(cmadd(u[2] * u[3], -u[0], u[5]));
+    m[8] = d * conj_(cmadd(u[0] * u[4], -u[1], u[3]));
 #pragma unroll
     for (int k = 0; k < 6; ++k) m[k] = u[k];
 #pragma unroll
@@ -476,9 +476,9 @@ __device__ __forceinline__ void nn_apply_m(bool fwd, const cx<float> m[9], const
         const cx<float> h0 = sp[3 * sd], h1 = sp[3 * sd + 1], h2 = sp[3 * sd + 2];
 #pragma unroll
         for (int r = 0; r < 3; ++r)
-            w[3 * sd + r] = fwd ? m[3 * r] * h0 + m[3 * r + 1] * h1 + m[3 * r + 2] * h2
-                                : cmul_conj(m[r], h0) + cmul_conj(m[3 + r], h1) +
-                                      cmul_conj(m[6 + r], h2);
+            w[3 * sd + r] = fwd ? cmadd(cmadd(m[3 * r] * h0, m[3 * r + 1], h1), m[3 * r + 2], h2)
+                                : cmadd_conj(cmadd_conj(cmul_conj(m[r], h0), m[3 + r], h1),
+                                             m[6 + r], h2);
     }
 }
 

@@ -7,6 +7,7 @@
 #include <string>
 
 #include "qdw_host.h"
+#include "dirac_core.h"
 
 using namespace qdw;
 
@@ -159,12 +160,12 @@ __global__ void pack_links_kernel(Geom g, const double* su3, const double* theta
         r[2 * k] = c1 * a - s1 * b;
         r[2 * k + 1] = c1 * b + s1 * a;
     }
-    // FP64: 6 chunks of one complex each, d as a double2 array
+    // FP64: 6 chunks of one complex each, d in one double (encode_phase)
     for (int k = 0; k < 6; ++k) {
         double2 v = {r[2 * k], r[2 * k + 1]};
         ((double2*)l64)[chunk_at(g.Vh, 6, (int)row, k, i)] = v;
     }
-    ((double2*)d64)[row * g.Vh + i] = double2{c3, s3};
+    ((double*)d64)[row * g.Vh + i] = encode_phase(c3, s3);
     // FP32: 3 chunks of two complex each, d as a float2 array
     for (int k = 0; k < 3; ++k) {
         float4 v = {(float)r[4 * k], (float)r[4 * k + 1], (float)r[4 * k + 2], (float)r[4 * k + 3]};
@@ -365,6 +366,52 @@ __global__ void convert_site_reals(Geom g, int nr, const double* src, float* f32
     }
 }
 
+// The compact form of the clover blocks that the D kernels read (see clover54_apply):
+// per chirality block, H = (a - d) / 2 and b, where a, d are the colour blocks of its two
+// spins on the diagonal (a + d = 2 (4 + m0) 1 in the chiral basis) and b the colour block
+// between them; then rounded to the lower precisions.
+__global__ void compact_clover_kernel(Geom g, const double2* cl, double2* c64, float* c32,
+                                      _Float16* c16, uint16_t* cb16)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int par = blockIdx.y;
+    if (i >= g.Vh) return;
+    double a[72];
+    for (int k = 0; k < 36; ++k) {
+        const double2 v = cl[chunk_at(g.Vh, 36, par, k, i)];
+        a[2 * k] = v.x;
+        a[2 * k + 1] = v.y;
+    }
+    // entry (r, q), r < q, of the 6x6 block starting at a + 36 blk (row-major upper triangle)
+    auto up = [&](int blk, int r, int q, int part) {
+        const int n = r * 6 - r * (r + 1) / 2 + (q - r - 1);
+        return a[36 * blk + 6 + 2 * n + part];
+    };
+    double o[56];
+    for (int blk = 0; blk < 2; ++blk) {
+        double* hd = o + 3 * blk;
+        double* hu = o + (blk ? 30 : 6);
+        double* b = o + (blk ? 36 : 12);
+        for (int r = 0; r < 3; ++r) hd[r] = 0.5 * (a[36 * blk + r] - a[36 * blk + 3 + r]);
+        const int pr[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+        for (int e = 0; e < 3; ++e)
+            for (int part = 0; part < 2; ++part)
+                hu[2 * e + part] = 0.5 * (up(blk, pr[e][0], pr[e][1], part) -
+                                          up(blk, 3 + pr[e][0], 3 + pr[e][1], part));
+        for (int r = 0; r < 3; ++r)
+            for (int q = 0; q < 3; ++q)
+                for (int part = 0; part < 2; ++part) b[2 * (3 * r + q) + part] = up(blk, r, 3 + q, part);
+    }
+    o[54] = o[55] = 0.0;
+    for (int k = 0; k < 27; ++k) c64[chunk_at(g.Vh, 27, par, k, i)] = double2{o[2 * k], o[2 * k + 1]};
+    for (int q = 0; q < 56; ++q) {
+        c32[chunk_at(g.Vh, 14, par, q / 4, i) * 4 + q % 4] = (float)o[q];
+        const long a16 = chunk_at(g.Vh, 7, par, q / 8, i) * 8 + q % 8;
+        c16[a16] = (_Float16)o[q];
+        cb16[a16] = float_to_bf16((float)o[q]);
+    }
+}
+
 // ------------------------------------------------------------------ spinor pack
 
 template <int P>
@@ -433,7 +480,8 @@ __global__ void pack_kernel<F64>(Geom g, const double* can, void* eo)
 // aligned): compressed links and their determinants, clover blocks and their inverses in
 // every precision, then the reduction scratch.
 struct OpLayout {
-    size_t links[4], det[4], clover[4], cloverinv[4], partials, scalars, worst, total;
+    size_t links[4], det[4], clover[4], cloverinv[4], clover54[4], partials, scalars, worst,
+        total;
 };
 
 OpLayout op_layout(int Vh)
@@ -448,7 +496,7 @@ OpLayout op_layout(int Vh)
     const size_t nl = (size_t)padded(Vh) * 8;  // link slots per array (2 parities x 4 dirs)
     const size_t ns = (size_t)padded(Vh) * 2;  // site slots of both parities
     L.links[F64] = take(nl * 6 * 16);
-    L.det[F64] = take(nl * 16);
+    L.det[F64] = take(nl * 8);
     L.links[F32] = take(nl * 3 * 16);
     L.det[F32] = take(nl * 8);
     L.links[F16S] = take(nl * 2 * 16);
@@ -457,6 +505,8 @@ OpLayout op_layout(int Vh)
     const size_t creal[4] = {8, 4, 2, 2};
     for (int p = 0; p < 4; ++p) L.clover[p] = take(ns * 72 * creal[p]);
     for (int p = 0; p < 4; ++p) L.cloverinv[p] = take(ns * 72 * creal[p]);
+    const size_t c54[4] = {27 * 16, 14 * 16, 7 * 16, 7 * 16};  // compact clover, bytes per site
+    for (int p = 0; p < 4; ++p) L.clover54[p] = take(ns * c54[p]);
     L.partials = take(sizeof(double) * kMaxPartials * kMaxScalars);
     L.scalars = take(sizeof(double) * kMaxScalars);
     L.worst = take(sizeof(unsigned long long));
@@ -517,6 +567,7 @@ extern "C" int qdw_create(const qdw_lattice* lat, const double* su3, const doubl
     g.V = (int)V;
     g.Vh = (int)(V / 2);
     g.bc_t = lat->bc_t;
+    g.cdiag = 4.0 + m0;
     g.S = L[1] * L[2] * L[3] / 2;
     {
         int nt = 1;
@@ -554,6 +605,7 @@ extern "C" int qdw_create(const qdw_lattice* lat, const double* su3, const doubl
         op->det[p] = lay.det[p] == (size_t)-1 ? nullptr : base + lay.det[p];
         op->clover[p] = base + lay.clover[p];
         op->cloverinv[p] = base + lay.cloverinv[p];
+        op->clover54[p] = base + lay.clover54[p];
     }
     op->partials = (double*)(base + lay.partials);
     op->scalars = (double*)(base + lay.scalars);
@@ -602,6 +654,11 @@ extern "C" int qdw_create(const qdw_lattice* lat, const double* su3, const doubl
     convert_site_reals<<<gs, 128, 0, st>>>(g, 72, (const double*)op->clover[F64],
                                            (float*)op->clover[F32], (_Float16*)op->clover[F16S],
                                            (uint16_t*)op->clover[BF16S]);
+    CREATE_HIP(hipGetLastError());
+    compact_clover_kernel<<<gs, 128, 0, st>>>(g, (const double2*)op->clover[F64],
+                                              (double2*)op->clover54[F64], (float*)op->clover54[F32],
+                                              (_Float16*)op->clover54[F16S],
+                                              (uint16_t*)op->clover54[BF16S]);
     CREATE_HIP(hipGetLastError());
     // their inverses (the even-odd reduced operator divides by the odd-site blocks)
     clover_inv_kernel<<<gs, 128, 0, st>>>(g, (const double2*)op->clover[F64],

@@ -13,12 +13,13 @@ struct qdw_op {
     double m0, csw;
     int device;
     // per precision (index = qdw::Prec): compressed links (rows 0, 1 of the U(3) link),
-    // link phases exp(3 i theta) (F64: double2, F32: float2 arrays; the 16-bit formats
-    // keep them inside the link chunks), clover blocks
+    // link determinants exp(3 i theta) (F64: one double each, see encode_phase; F32: float2
+    // arrays; the 16-bit formats keep them inside the link chunks), clover blocks
     void* links[4];
     void* det[4];
     void* clover[4];
     void* cloverinv[4];    // per precision: inverses of the clover blocks (same format)
+    void* clover54[4];     // per precision: the compact clover form the D kernels read
     // per precision: shape of the D kernel (sites per parity of a workgroup, time slices
     // per walk chunk, software-pipelined hop loop, walk order, marching form); other site
     // kernels use g

@@ -8,12 +8,15 @@
 //
 //   spinor  24 reals/site  (12 complex, index spin*3 + colour)
 //           F64: 12 chunks (1 complex each), F32: 6 (2 complex), F16/BF16: 3 (4 complex)
-//   link    rows 0 and 1 of the SU(3) part (6 complex) + U(1) phase, per direction mu
-//           F64: 6 chunks + angle array, F32: 3 chunks + angle array,
-//           F16/BF16: 2 chunks = 6 complex + (cos, sin) of the angle
-//           The third row is rebuilt in registers as conj(row0 x row1).
+//   link    rows 0 and 1 of the U(3) link U = exp(i theta) V (6 complex) and its
+//           determinant d = exp(3 i theta), per direction mu
+//           F64: 6 chunks + a separate array of d (8 B, encode_phase), F32: 3 chunks +
+//           d array (8 B),
+//           F16/BF16: 2 chunks = the 6 complex and d
+//           The third row is rebuilt in registers as d conj(row0 x row1).
 //   clover  2 chirality blocks x 36 reals (6 real diagonal, 15 complex upper triangle,
 //           row-major), (4 + m0) included. F64: 36 chunks, F32: 18, F16/BF16: 9.
+//           The D kernels read the compact form instead (54 reals, dirac_core.h).
 //
 // The even-odd index of a site is lex/2 with lex = ((x0*L1 + x1)*L2 + x2)*L3 + x3;
 // this is a bijection per parity because L3 is even.
@@ -32,6 +35,7 @@ struct Geom {
     int stride[4]; // lexicographic strides
     int V, Vh;
     int bc_t;      // -1 antiperiodic, +1 periodic in time
+    double cdiag;  // 4 + m0, the constant diagonal of the clover term
     int S;         // even-odd sites per time slice and parity (L1*L2*L3/2)
     int ts;        // sites per parity of a site-kernel workgroup (64 or 128; 2*ts lanes)
     int ntile;     // workgroups per time slice
@@ -178,6 +182,22 @@ template <typename R> __device__ __forceinline__ cx<R> cmul_conj(cx<R> a, cx<R> 
     return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
 }
 template <typename R> __device__ __forceinline__ cx<R> conj_(cx<R> a) { return {a.re, -a.im}; }
+template <typename R> __device__ __forceinline__ cx<R> operator-(cx<R> a) { return {-a.re, -a.im}; }
+
+// Fused multiply-adds, written out so that every complex multiply-accumulate is four FMA
+// instructions (a product followed by an addition otherwise often stays a multiply and an
+// add): c + a b and c + conj(a) b.
+template <typename R> __device__ __forceinline__ R fmar(R a, R b, R c);
+template <> __device__ __forceinline__ float fmar<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <> __device__ __forceinline__ double fmar<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
+template <typename R> __device__ __forceinline__ cx<R> cmadd(cx<R> c, cx<R> a, cx<R> b)
+{
+    return {fmar(a.re, b.re, fmar(-a.im, b.im, c.re)), fmar(a.re, b.im, fmar(a.im, b.re, c.im))};
+}
+template <typename R> __device__ __forceinline__ cx<R> cmadd_conj(cx<R> c, cx<R> a, cx<R> b)
+{
+    return {fmar(a.re, b.re, fmar(a.im, b.im, c.re)), fmar(a.re, b.im, fmar(-a.im, b.re, c.im))};
+}
 template <typename R> __device__ __forceinline__ cx<R> times_i(cx<R> a) { return {-a.im, a.re}; }
 template <typename R> __device__ __forceinline__ cx<R> scale(cx<R> a, R s) { return {a.re * s, a.im * s}; }
 

@@ -207,9 +207,9 @@ __device__ __forceinline__ void mat_mul(const cx<float> m[9], const cx<float> h[
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
             if (!DAGGER)
-                w[3 * a + r] = m[3 * r] * h0 + m[3 * r + 1] * h1 + m[3 * r + 2] * h2;
+                w[3 * a + r] = cmadd(cmadd(m[3 * r] * h0, m[3 * r + 1], h1), m[3 * r + 2], h2);
             else
-                w[3 * a + r] = cmul_conj(m[r], h0) + cmul_conj(m[3 + r], h1) + cmul_conj(m[6 + r], h2);
+                w[3 * a + r] = cmadd_conj(cmadd_conj(cmul_conj(m[r], h0), m[3 + r], h1), m[6 + r], h2);
         }
     }
 }
@@ -226,9 +226,9 @@ __device__ __forceinline__ void push_and_forward(float (*hb)[12][kBMax], float (
     if (l[MU] < B.bs[MU] - 1) {
         cx<float> u[6], d, m[9];
         so.template link<MU>(u, d);
-        m[6] = d * conj_(u[1] * u[5] - u[2] * u[4]);
-        m[7] = d * conj_(u[2] * u[3] - u[0] * u[5]);
-        m[8] = d * conj_(u[0] * u[4] - u[1] * u[3]);
+        m[6] = d * conj_(cmadd(u[1] * u[5], -u[2], u[4]));
+        m[7] = d * conj_(cmadd(u[2] * u[3], -u[0], u[5]));
+        m[8] = d * conj_(cmadd(u[0] * u[4], -u[1], u[3]));
 #pragma unroll
         for (int c = 0; c < 6; ++c) m[c] = u[c];
         const int nb = t + B.lstride[MU];
@@ -389,10 +389,10 @@ void sap_mr_kernel(Geom g, BlockGeom B, int colour, int nmr,
         float nre = 0.f, nim = 0.f, den = 0.f;
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
-            const cx<float> z = cmul_conj(v[c], r[c]);
-            nre += z.re;
-            nim += z.im;
-            den += v[c].re * v[c].re + v[c].im * v[c].im;
+            const cx<float> z = cmadd_conj(cx<float>{nre, nim}, v[c], r[c]);
+            nre = z.re;
+            nim = z.im;
+            den = fmar(v[c].re, v[c].re, fmar(v[c].im, v[c].im, den));
         }
         double a0 = nre, a1 = nim, a2 = den;
 #pragma unroll
@@ -628,10 +628,10 @@ void sap_mr_eo_kernel(Geom g, BlockGeom B, int colour, int nmr,
         float nre = 0.f, nim = 0.f, den = 0.f;
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
-            const cx<float> q = cmul_conj(v[c], res[c]);
-            nre += q.re;
-            nim += q.im;
-            den += v[c].re * v[c].re + v[c].im * v[c].im;
+            const cx<float> q = cmadd_conj(cx<float>{nre, nim}, v[c], res[c]);
+            nre = q.re;
+            nim = q.im;
+            den = fmar(v[c].re, v[c].re, fmar(v[c].im, v[c].im, den));
         }
         double a0 = nre, a1 = nim, a2 = den;
 #pragma unroll

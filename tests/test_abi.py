@@ -140,16 +140,17 @@ def test_traffic_record_is_consistent_and_current():
 
 def test_operator_memory_comes_from_the_caller(lib):
     """qdw_create takes its device and host blocks from the caller: the size query works
-    without a GPU, scales with the volume (about 3.2 kB per site), rejects bad lattices, and
+    without a GPU, scales with the volume (about 4.1 kB per site), rejects bad lattices, and
     create refuses missing or short blocks before touching the device."""
     import ctypes
     small = qdw.Lattice(4, 4, 4, 4, -1)
     big = qdw.Lattice(8, 8, 8, 8, -1)
     ns, nb = lib.qdw_op_device_bytes(ctypes.byref(small)), lib.qdw_op_device_bytes(ctypes.byref(big))
     assert 0 < ns < nb
-    # per site: links 4 x (112 + 56 + 32 + 32) B, clover blocks and inverses 2 x (576 + 288
-    # + 144 + 144) B; the rest is a fixed reduction scratch
-    assert (nb - ns) == (8 ** 4 - 4 ** 4) * (4 * 232 + 2 * 1152)
+    # per site: links 4 x (104 + 56 + 32 + 32) B, clover blocks and inverses 2 x (576 + 288
+    # + 144 + 144) B, the compact clover 432 + 224 + 112 + 112 B; the rest is a fixed
+    # reduction scratch
+    assert (nb - ns) == (8 ** 4 - 4 ** 4) * (4 * 224 + 2 * 1152 + 880)
     assert lib.qdw_op_device_bytes(ctypes.byref(qdw.Lattice(4, 4, 4, 3, -1))) == 0
     assert lib.qdw_op_host_bytes() >= 8 * 1024
     h = ctypes.c_void_p()

@@ -109,7 +109,7 @@ def test_operator_memory_is_a_torch_allocation():
     torch.cuda.synchronize()
     grown = torch.cuda.memory_allocated() - before
     V = int(np.prod(dims))
-    assert op.device_bytes >= V * (4 * 232 + 2 * 1152)
+    assert op.device_bytes >= V * (4 * 224 + 2 * 1152 + 880)
     assert op.device_bytes <= grown <= op.device_bytes + 4096
     op.close()
     torch.cuda.synchronize()
