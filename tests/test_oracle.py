@@ -188,6 +188,27 @@ def test_clover_hermitian_chiral_trace(op44):
     assert np.abs(A - 4.1 * np.eye(12)).max() > 0.1
 
 
+@pytest.mark.parametrize("csw, m0", [(1.5, 0.1), (1.7, -0.3)])
+def test_clover_chirality_block_structure(csw, m0):
+    """In the chiral basis each sigma_{mu nu} acts on the two spins of a chirality as a
+    traceless 2x2 matrix, so the colour blocks of the clover term on a chirality's two spins
+    sum to 2 (4 + m0) 1: every chirality block is (4 + m0) 1 + [[H, b], [b^+, -H]] with H
+    Hermitian, 27 reals instead of 36 (the compact form the D kernels read). Also with rough
+    U(3) links, where the field strength is not traceless."""
+    dims = (4, 4, 4, 6)
+    su3, th = syn.gauge_field(dims, 0.5, 0.3, 3)
+    op = oracle.Operator(dims, su3, th, m0, csw, -1)
+    A = op.A
+    for blk in (0, 6):
+        a = A[:, blk:blk + 3, blk:blk + 3]
+        d = A[:, blk + 3:blk + 6, blk + 3:blk + 6]
+        assert np.abs(a + d - 2.0 * (4.0 + m0) * np.eye(3)).max() < 1e-14
+        H = 0.5 * (a - d)
+        assert np.abs(H - np.conj(np.swapaxes(H, 1, 2))).max() < 1e-14
+        assert np.abs(a - (4.0 + m0) * np.eye(3)).max() > 0.1  # H itself is not small
+    assert np.abs(A[:, 0:6, 6:12]).max() == 0.0
+
+
 def test_clover_unit_field():
     su3, th = syn.unit_gauge_field(D44)
     op = oracle.Operator(D44, su3, th, -0.05, 1.7, -1)
