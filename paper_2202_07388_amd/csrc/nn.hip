@@ -36,6 +36,7 @@ constexpr int kMaxN = 64;       // 8 channels x 4 spins x 2
 
 typedef short s4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 inline int layer_K(int l) { return (kPaths * kCh[l] * 8 + 15) & ~15; }
 inline int layer_N(int l) { return std::max(16, kCh[l + 1] * 8); }
@@ -467,6 +468,65 @@ __device__ __forceinline__ void nn_link_matrix(const cx<float> u[6], cx<float> d
     for (int k = 0; k < 9; ++k) m[k] = scale(m[k], sg);
 }
 
+// A path's link matrix as bf16 pairs for the dot-product instruction that multiplies two
+// bf16 pairs and adds both products to an FP32 sum (v_dot2_f32_bf16): the hidden channels are
+// stored as (re, im) bf16 pairs, so with a = (e.re, -e.im), b = (e.im, e.re) one complex
+// product e v adds dot(a, v) to the real and dot(b, v) to the imaginary part -- two
+// instructions instead of four FMAs, and no widening of the stored spinor. Entry r * 3 + k is
+// the coefficient of v_k in w_r: M[r][k] for a forward path, conj(M[k][r]) for a backward one.
+// The link is rounded to bf16 like the operands of the mixing that follows.
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+struct LinkBF {
+    uint32_t a[9], b[9];
+};
+
+__device__ __forceinline__ void nn_link_bf16(bool fwd, const cx<float> m[9], LinkBF& L)
+{
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const cx<float> e = fwd ? m[3 * r + k] : conj_(m[3 * k + r]);
+            L.a[3 * r + k] = pack_bf16x2(e.re, -e.im);
+            L.b[3 * r + k] = pack_bf16x2(e.im, e.re);
+        }
+}
+
+__device__ __forceinline__ float dot2_bf16(uint32_t a, uint32_t b, float c)
+{
+    bf16x2v x, y;
+    __builtin_memcpy(&x, &a, 4);
+    __builtin_memcpy(&y, &b, 4);
+    return __builtin_amdgcn_fdot2_f32_bf16(x, y, c, false);
+}
+
+// w = (M or M^+) v (ACC: w += ...) for the four spins of a spinor stored as 12 (re, im)
+// bf16 pairs (three 16-byte chunks as loaded), FP32 sums
+template <bool ACC = false>
+__device__ __forceinline__ void nn_transport_dot2(const LinkBF& L, const u32x4 raw[3], cx<float> w[12])
+{
+    uint32_t v[12];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        v[4 * k] = raw[k].x;
+        v[4 * k + 1] = raw[k].y;
+        v[4 * k + 2] = raw[k].z;
+        v[4 * k + 3] = raw[k].w;
+    }
+#pragma unroll
+    for (int sd = 0; sd < 4; ++sd)
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            float re = ACC ? w[3 * sd + r].re : 0.f, im = ACC ? w[3 * sd + r].im : 0.f;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                re = dot2_bf16(L.a[3 * r + k], v[3 * sd + k], re);
+                im = dot2_bf16(L.b[3 * r + k], v[3 * sd + k], im);
+            }
+            w[3 * sd + r] = {re, im};
+        }
+}
+
 // w = M sp (forward path) or M^+ sp (backward path) for the four spins
 __device__ __forceinline__ void nn_apply_m(bool fwd, const cx<float> m[9], const cx<float> sp[12],
                                            cx<float> w[12])
@@ -495,8 +555,8 @@ __global__ void nn_embed_lds_kernel(const uint16_t* Bt, int Kpad, uint16_t* Bl)
 {
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
     if (tid >= kPaths * 64 * 64) return;
-    const int e = tid & 3, n = (tid >> 2) & 63, kq = (tid >> 8) & 15, p = tid >> 12;
-    Bl[tid] = Bt[(long)n * Kpad + p * 64 + kq * 4 + e];
+    const int e = tid & 7, n = (tid >> 3) & 63, kq = (tid >> 9) & 7, p = tid >> 12;
+    Bl[tid] = Bt[(long)n * Kpad + p * 64 + kq * 8 + e];
 }
 
 // LDS row stride (in bf16 halves) of a tile with KB columns: at least KB + 8, rows 16-byte
@@ -527,6 +587,22 @@ __device__ __forceinline__ long nn_block_q0(int Vp)
 {
     const int w = xcd_tile(blockIdx.x, gridDim.x);
     return (long)(w & 1) * Vp + (long)(w >> 1) * 64;
+}
+
+// the same rows straight from a spinor stored as bf16 pairs (the identity path)
+template <int LS>
+__device__ __forceinline__ void nn_put_rows_raw(uint16_t* tile, int sl, int k0, const u32x4 raw[3])
+{
+    uint32_t v[12];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        v[4 * k] = raw[k].x;
+        v[4 * k + 1] = raw[k].y;
+        v[4 * k + 2] = raw[k].z;
+        v[4 * k + 3] = raw[k].w;
+    }
+    for (int c = 0; c < 3; ++c)
+        *(uint4*)&tile[(sl * 3 + c) * LS + k0] = uint4{v[c], v[3 + c], v[6 + c], v[9 + c]};
 }
 
 // the three rows (site sl, colour c) of one (path, channel) group, as bf16, into the tile
@@ -568,7 +644,7 @@ __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, c
     __shared__ __attribute__((aligned(16))) char lds[TILE_B + W_B > OUT_B ? TILE_B + W_B : OUT_B];
     uint16_t* tile = (uint16_t*)lds;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    // Cin = 8: the weight block of path p is in buffer p & 1, as [k/4][n][k%4] (bf16)
+    // Cin = 8: the weight block of path p is in buffer p & 1, as [k/8][n][k%8] (bf16)
     uint16_t* const wbuf = (uint16_t*)(lds + TILE_B);
     const uint16_t* wb = wbuf;
     const int Vp = padded(g.Vh);
@@ -591,17 +667,32 @@ __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, c
         for (int j = 0; j < NT; ++j) acc[r][j] = f4{0.f, 0.f, 0.f, 0.f};
     // rows 48*wave .. +48 of the tile times B[kglob .. +KB][0 .. 16 NT] on the matrix cores
     auto mix = [&](long kglob) {
-        for (int kk = 0; kk < KB; kk += 16) {
-            const int kl = kk + 4 * (lane >> 4);
-            s4 bf[NT];
-            for (int j = 0; j < NT; ++j)
-                bf[j] = CIN == 8
-                            ? *(const s4*)&wb[((kl >> 2) * 64 + j * 16 + (lane & 15)) * 4]
-                            : *(const s4*)((const uint16_t*)Bt + (long)(j * 16 + (lane & 15)) * Kpad + kglob + kl);
-            for (int r = 0; r < 3; ++r) {
-                const s4 a = *(const s4*)&tile[(wave * 48 + r * 16 + (lane & 15)) * LS + kl];
+        if constexpr (CIN == 8) {
+            // K = 64 per path in two steps of gfx950's doubled-K bf16 product (16 x 16 x 32):
+            // each lane reads 8 consecutive k of its row of the tile and of its column of the
+            // path's weight block ([k/8][n][k%8] in LDS)
+            for (int kk = 0; kk < KB; kk += 32) {
+                const int kl = kk + 8 * (lane >> 4);
+                bf16x8 bf[NT];
                 for (int j = 0; j < NT; ++j)
-                    acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bf[j], acc[r][j], 0, 0, 0);
+                    bf[j] = *(const bf16x8*)&wb[((kl >> 3) * 64 + j * 16 + (lane & 15)) * 8];
+                for (int r = 0; r < 3; ++r) {
+                    const bf16x8 a = *(const bf16x8*)&tile[(wave * 48 + r * 16 + (lane & 15)) * LS + kl];
+                    for (int j = 0; j < NT; ++j)
+                        acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bf[j], acc[r][j], 0, 0, 0);
+                }
+            }
+        } else {
+            for (int kk = 0; kk < KB; kk += 16) {
+                const int kl = kk + 4 * (lane >> 4);
+                s4 bf[NT];
+                for (int j = 0; j < NT; ++j)
+                    bf[j] = *(const s4*)((const uint16_t*)Bt + (long)(j * 16 + (lane & 15)) * Kpad + kglob + kl);
+                for (int r = 0; r < 3; ++r) {
+                    const s4 a = *(const s4*)&tile[(wave * 48 + r * 16 + (lane & 15)) * LS + kl];
+                    for (int j = 0; j < NT; ++j)
+                        acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bf[j], acc[r][j], 0, 0, 0);
+                }
             }
         }
     };
@@ -633,16 +724,6 @@ __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, c
             for (int k = 0; k < 3; ++k) {
                 S.s0[k] = c0[b0 + (long)k * kSB];
                 S.s1[k] = c1[b0 + (long)k * kSB];
-            }
-        };
-        auto widen = [](const u32x4 raw[3], cx<float> s[12]) {
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const uint32_t w[4] = {raw[k].x, raw[k].y, raw[k].z, raw[k].w};
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    s[4 * k + q] = {bf16_to_float((uint16_t)(w[q] & 0xFFFFu)),
-                                    bf16_to_float((uint16_t)(w[q] >> 16))};
             }
         };
         // the weight block of path p: each of the 256 lanes loads 32 contiguous bytes of it
@@ -677,24 +758,19 @@ __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, c
             if (!real) {
                 nn_put_rows<LS>(tile, sl, cg * 8, zero12);
                 nn_put_rows<LS>(tile, sl, (cg + 4) * 8, zero12);
+            } else if (p0 == 0) {
+                nn_put_rows_raw<LS>(tile, sl, cg * 8, cur.s0);
+                nn_put_rows_raw<LS>(tile, sl, (cg + 4) * 8, cur.s1);
             } else {
-                cx<float> a[12];
-                if (p0 == 0) {
-                    widen(cur.s0, a);
-                    nn_put_rows<LS>(tile, sl, cg * 8, a);
-                    widen(cur.s1, a);
-                    nn_put_rows<LS>(tile, sl, (cg + 4) * 8, a);
-                } else {
-                    const bool fwd = ((p0 - 1) & 1) == 0;
-                    cx<float> w[12], m[9];
-                    nn_link_matrix(cur.u, cur.d, cur.sg, m);
-                    widen(cur.s0, a);
-                    nn_apply_m(fwd, m, a, w);
-                    nn_put_rows<LS>(tile, sl, cg * 8, w);
-                    widen(cur.s1, a);
-                    nn_apply_m(fwd, m, a, w);
-                    nn_put_rows<LS>(tile, sl, (cg + 4) * 8, w);
-                }
+                const bool fwd = ((p0 - 1) & 1) == 0;
+                cx<float> w[12], m[9];
+                LinkBF lb;
+                nn_link_matrix(cur.u, cur.d, cur.sg, m);
+                nn_link_bf16(fwd, m, lb);
+                nn_transport_dot2(lb, cur.s0, w);
+                nn_put_rows<LS>(tile, sl, cg * 8, w);
+                nn_transport_dot2(lb, cur.s1, w);
+                nn_put_rows<LS>(tile, sl, (cg + 4) * 8, w);
             }
             wave_sync();  // the wave's own rows, by its other lanes
             wb = wbuf + (p0 & 1) * (kWBlock / 2);
@@ -890,14 +966,17 @@ __global__ __launch_bounds__(256) void nn_transport_sum_kernel(Geom g, const voi
     for (int p = 1; p < kPaths; ++p) {
         int j;
         float sg;
-        cx<float> u[6], d, sp[12], w[12];
+        cx<float> u[6], d;
         nn_path_setup(g, par, i, x, lex, p, links, dets, j, sg, u, d);
-        load_spinor<BF16S>(mix[p], g.Vh, 1 - par, j, sp);
-        cx<float> m[9];
-        nn_link_matrix(u, d, sg, m);
-        nn_apply_m(((p - 1) & 1) == 0, m, sp, w);
+        u32x4 raw[3];
+        const long b0 = chunk_at(g.Vh, 3, 1 - par, 0, j);
 #pragma unroll
-        for (int k = 0; k < 12; ++k) acc[k] = acc[k] + w[k];
+        for (int k = 0; k < 3; ++k) raw[k] = ((const u32x4*)mix[p])[b0 + (long)k * kSB];
+        cx<float> m[9];
+        LinkBF lb;
+        nn_link_matrix(u, d, sg, m);
+        nn_link_bf16(((p - 1) & 1) == 0, m, lb);
+        nn_transport_dot2<true>(lb, raw, acc);
     }
     store_spinor<F32>(out, g.Vh, par, i, acc);
 }
