@@ -16,7 +16,8 @@ Also reported, each timed on its own outside the K steps:
   * the 24^3 x 48 solve of D psi = eta to 1e-10 (eps = 0.35, m0 = -0.08): plain FP64 GCR
     against SAP-preconditioned GCR (4^4 blocks, 5 cycles, 4 MR steps, FP16 and FP32), the
     same with even-odd reduced block solves (FP16) and adaptive SAP (at most 20 cycles and
-    20 MR steps, alpha 0.9 and 0.7, FP16);
+    20 MR steps, alpha 0.9 and 0.7, FP16), and SAP applications alone (plain and with
+    even-odd reduced blocks, FP16 and FP32 storage);
   * the learned preconditioner: trained on the GPU on 2000 residual/error pairs from
     plain FP64 GCR solves on four 16^3 x 32 fields (eps = 0.3, m0 = -0.05), then used as
     the flexible-GCR preconditioner on the 32^3 x 64 field against SAP-GCR (plain and with
@@ -32,7 +33,7 @@ Also reported, each timed on its own outside the K steps:
     on one core, and CGNE / GCR / SAP-GCR solves at small lattices beside the GPU's.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-solves]
-                       [--legs multi,cgne,nn,gcr,batch] [--autotune] [--calibrate]
+                       [--legs multi,cgne,nn,gcr,sap,batch] [--autotune] [--calibrate]
 """
 from __future__ import annotations
 
@@ -257,6 +258,34 @@ def gcr_solves(qdw, syn):
     return out
 
 
+def sap_sweeps(qdw, syn):
+    """SAP applications at 24^3 x 48 (eps 0.35, m0 -0.08; 4^4 blocks, 5 cycles, 4 MR steps):
+    plain and even-odd reduced block solves, FP16 and FP32 storage, each timed over 10
+    applications after 3 warm-up ones (a kernel trace of this leg holds only these)."""
+    import torch
+    su3, th = syn.gauge_field(SAP_DIMS, SAP_EPS, EPS_U1, SAP_SEED)
+    op = qdw.Op(SAP_DIMS, su3, th, SAP_M0, CSW, -1)
+    del su3, th
+    rho = op.pack(syn.gaussian_spinor(SAP_DIMS, SAP_SEED + 1000), "f64")
+    phi = op.new_field("f64")
+    out = {}
+    for eo in (False, True):
+        for prec in ("f16", "f32"):
+            f = lambda: qdw.sap_apply(op, rho, phi, 5, 4, (4, 4, 4, 4), prec, eo=eo)
+            for _ in range(3):
+                f()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(10):
+                f()
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / 10 * 1e3
+            out["%s_%s" % ("eo" if eo else "plain", prec)] = {"ms_per_application": round(ms, 4)}
+            log("  sap %s %s: %.3f ms per application" % ("eo" if eo else "plain", prec, ms))
+    op.close()
+    return out
+
+
 NN_DIMS = (32, 16, 16, 16)
 NN_FIELDS, NN_SOURCES, NN_STEPS, NN_PAIRS = 4, 6, 100, 2000
 
@@ -405,10 +434,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solves", action="store_true")
     ap.add_argument("--no-nn", action="store_true", help="skip training the learned preconditioner")
-    ap.add_argument("--legs", default="multi,cgne,nn,gcr,batch",
+    ap.add_argument("--legs", default="multi,cgne,nn,gcr,sap,batch",
                     help="comma-separated legs to run after the D timing (multi: D on 4 "
-                         "fields in one launch; cgne, nn, gcr, batch: solves); kernel "
-                         "traces of one leg use this")
+                         "fields in one launch; cgne, nn, gcr, batch: solves; sap: SAP "
+                         "applications); kernel traces of one leg use this")
     ap.add_argument("--autotune", action="store_true",
                     help="pick the 32^3x64 D-kernel shapes with the autotuner instead of the "
                          "pinned ones (its own launches then join any kernel trace)")
@@ -533,6 +562,8 @@ def main():
     op.close()
     if "gcr" in legs:
         out["sap_gcr_24c48"] = gcr_solves(qdw, syn)
+    if "sap" in legs:
+        out["sap_apply_24c48"] = sap_sweeps(qdw, syn)
     if "batch" in legs:
         out["batched_40rhs"] = batched_solves(qdw, syn)
     if not args.no_cpu_baseline:
