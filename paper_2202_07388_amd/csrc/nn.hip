@@ -578,35 +578,15 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// (x1, t) tile of the forward kernels' block order: kNnB1 x1 planes by kNnBT time slices
-constexpr int kNnB1 = 4, kNnBT = 4;
-
 // first row q (site) of the 64-site block of this workgroup in the forward kernels, whose
-// grid is one workgroup per block of either parity. Blocks of the two parities alternate
-// (the even and odd sites of one index range are lexicographic neighbours along x3), then
-// the blocks of one x1 plane of a time slice (x2 rows), and these (x1, t) planes go in
-// tiles of kNnB1 x kNnBT, time fastest within a tile and tiles in time order first; each
-// XCD takes one contiguous range of the order. A block's neighbours in x1 and t are then
-// a few tens of workgroups away and mostly still in the XCD's L2 when it gathers them
-// (in plain index order the time neighbours are a whole slice of blocks away). Lattices
-// whose planes or extents do not tile this way keep the plain index order.
-__device__ __forceinline__ long nn_block_q0(const Geom& g, int Vp)
+// grid is one workgroup per block of either parity: blocks of the two parities alternate
+// (the even and odd sites of one index range are lexicographic neighbours along x3), and
+// each XCD takes one contiguous range of blocks, so that the neighbour windows a workgroup
+// gathers were mostly loaded into its XCD's L2 by workgroups running beside it
+__device__ __forceinline__ long nn_block_q0(int Vp)
 {
     const int w = xcd_tile(blockIdx.x, gridDim.x);
-    int b = w >> 1;
-    if (g.slab % 64 == 0 && g.L[1] % kNnB1 == 0 && g.L[0] % kNnBT == 0) {
-        const int nbx = g.slab / 64;  // blocks per x1 plane of a slice
-        const int xg = b % nbx;
-        int u = b / nbx;
-        const int tt = u % kNnBT;
-        u /= kNnBT;
-        const int xi = u % kNnB1;
-        u /= kNnB1;
-        const int ntt = g.L[0] / kNnBT;
-        const int t = (u % ntt) * kNnBT + tt, x1 = (u / ntt) * kNnB1 + xi;
-        b = (t * g.L[1] + x1) * nbx + xg;
-    }
-    return (long)(w & 1) * Vp + (long)b * 64;
+    return (long)(w & 1) * Vp + (long)(w >> 1) * 64;
 }
 
 // the same rows straight from a spinor stored as bf16 pairs (the identity path)
@@ -668,7 +648,7 @@ __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, c
     uint16_t* const wbuf = (uint16_t*)(lds + TILE_B);
     const uint16_t* wb = wbuf;
     const int Vp = padded(g.Vh);
-    const long q0 = nn_block_q0(g, Vp);
+    const long q0 = nn_block_q0(Vp);
     // this lane's transport site: Cin = 8, the wave's own 16 sites (the rows its matrix-core
     // products read), four lanes per site, channels cg and cg + 4 per lane, so a wave's
     // transport and products need no other wave (the workgroup meets once per path, for
@@ -913,7 +893,7 @@ __global__ __launch_bounds__(256) void nn_mix_paths_kernel(Geom g, const void* c
     uint16_t* tile = (uint16_t*)lds;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int Vp = padded(g.Vh);
-    const long q0 = nn_block_q0(g, Vp);
+    const long q0 = nn_block_q0(Vp);
     const int par = (int)(q0 / Vp), i0 = (int)(q0 - (long)par * Vp);
     const int i = i0 + lane;
     const cx<float> zero12[12] = {};
