@@ -619,11 +619,18 @@ __device__ __forceinline__ void nn_put_rows(uint16_t* tile, int sl, int k0, cons
     }
 }
 
-template <int CIN, int COUT, int PIN, int POUT>
+// MIXOUT (inference passes of the 8 -> 8 layer only): instead of storing the layer's eight
+// output channels, the kernel goes on with the last layer's path mixing on them (the
+// product nn_mix_paths_kernel forms, with the mixing matrix Bm) and stores the nine m_p
+// fields to out[0..8]; the A operand is the outputs rounded to bf16, as the stored hidden
+// channels would be, and the product runs in the same instruction order, so the m_p are
+// bit for bit those of the two-kernel form.
+template <int CIN, int COUT, int PIN, int POUT, bool MIXOUT = false>
 __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, const void* const* in,
                                                              const void* Bt, const void* Bl,
                                                              void* const* out, const void* links,
-                                                             const void* dets)
+                                                             const void* dets,
+                                                             const uint16_t* Bm = nullptr)
 {
     constexpr int PB = CIN == 1 ? kPaths : 1;          // paths per batch
     constexpr int KB = (PB * CIN * 8 + 15) & ~15;      // columns per batch (80 or 64)
@@ -639,7 +646,8 @@ __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, c
     // padded by one chunk so that consecutive rows start 4 banks apart
     static_assert(POUT == BF16S, "the layers' outputs are bf16 hidden channels");
     constexpr int OROW = 64 * 8 + 8;
-    constexpr int OUT_B = COUT * 3 * OROW * 2;
+    constexpr int OUT_B = (MIXOUT ? kPaths : COUT) * 3 * OROW * 2;
+    static_assert(!MIXOUT || (CIN == 8 && COUT == 8), "the path mixing follows the 8 -> 8 layer");
     static_assert(TILE_B % 16 == 0, "weight blocks 16-byte aligned");
     __shared__ __attribute__((aligned(16))) char lds[TILE_B + W_B > OUT_B ? TILE_B + W_B : OUT_B];
     uint16_t* tile = (uint16_t*)lds;
@@ -829,6 +837,54 @@ __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, c
         mix(0);
     }
     __syncthreads();  // the output block below reuses the tile
+    if constexpr (MIXOUT) {
+        // the wave's own 48 rows of the mixing's A operand: row 3 site + c, column
+        // (a * 4 + s) * 2 + re/im = (b * 4 + t) * 2 + re/im of the input of the mixing
+        for (int r = 0; r < 3; ++r)
+            for (int j = 0; j < NT; ++j)
+                for (int e = 0; e < 4; ++e)
+                    tile[(wave * 48 + r * 16 + 4 * (lane >> 4) + e) * LS + j * 16 + (lane & 15)] =
+                        (uint16_t)(pack_bf16x2(acc[r][j][e], 0.f) & 0xFFFFu);
+        wave_sync();
+        constexpr int NM = 5;  // 80 columns: 9 paths x 4 spins x re/im (72), padded
+        f4 am[3][NM];
+        for (int r = 0; r < 3; ++r)
+            for (int j = 0; j < NM; ++j) am[r][j] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int kk = 0; kk < 64; kk += 16) {
+            const int kl = kk + 4 * (lane >> 4);
+            s4 bf[NM];
+            for (int j = 0; j < NM; ++j)
+                bf[j] = *(const s4*)(Bm + (j * 16 + (lane & 15)) * 64 + kl);
+            for (int r = 0; r < 3; ++r) {
+                const s4 a = *(const s4*)&tile[(wave * 48 + r * 16 + (lane & 15)) * LS + kl];
+                for (int j = 0; j < NM; ++j)
+                    am[r][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bf[j], am[r][j], 0, 0, 0);
+            }
+        }
+        __syncthreads();  // every wave is done with the tile before the staging overwrites it
+        uint16_t* ob = (uint16_t*)lds;
+        for (int r = 0; r < 3; ++r)
+            for (int j = 0; j < NM; ++j)
+                for (int e = 0; e < 4; ++e) {
+                    const int m = wave * 48 + r * 16 + 4 * (lane >> 4) + e;
+                    const int n = j * 16 + (lane & 15);
+                    if (n >= 72) continue;
+                    const int ms = m / 3, c = m - ms * 3;
+                    const int p = n >> 3, sp = (n >> 1) & 3, ri = n & 1;
+                    const int k = (sp * 3 + c) * 2 + ri;
+                    ob[(p * 3 + (k >> 3)) * OROW + ms * 8 + (k & 7)] =
+                        (uint16_t)(pack_bf16x2(am[r][j][e], 0.f) & 0xFFFFu);
+                }
+        __syncthreads();
+        const int mpar = (int)(q0 / Vp), mi0 = (int)(q0 - (long)mpar * Vp);
+        for (int u = threadIdx.x; u < kPaths * 3 * 64; u += 256) {
+            const int p = u / 192, rem = u - p * 192, ch = rem >> 6, site = rem & 63;
+            if (mi0 + site >= g.Vh) continue;
+            const uint4 raw = *(const uint4*)&ob[(p * 3 + ch) * OROW + site * 8];
+            ((uint4*)out[p])[chunk_at(g.Vh, 3, mpar, ch, mi0 + site)] = raw;
+        }
+        return;
+    }
     // outputs: row m = 3 * site + c, column n = (a * 4 + s) * 2 + re/im, rounded to bf16
     // (the conversion instruction) and staged in LDS as [channel][chunk][site][8] (the 64
     // sites are one aligned block of one parity; rows padded as in the tile), then written
@@ -1088,8 +1144,11 @@ int zero_dev(void* p, size_t bytes, hipStream_t st)
 }
 
 // forward through all layers, input already in act[0][0]; keeps every layer's input
+// (keep_hidden, needed by the gradients), or, in bf16 inference passes without it, fuses
+// the last layer's path mixing into the 8 -> 8 layer so that the second hidden layer's
+// channels never go to memory
 template <bool F32M>
-int forward(qdw_op* op, const float* weights, NnWork& W, hipStream_t st)
+int forward(qdw_op* op, const float* weights, NnWork& W, hipStream_t st, bool keep_hidden = true)
 {
     const Geom& g = op->g;
     const long Mp = rows_padded(g);
@@ -1118,17 +1177,32 @@ int forward(qdw_op* op, const float* weights, NnWork& W, hipStream_t st)
                 nn_embed_lds_kernel<<<(kPaths * 64 * 64 + 255) / 256, 256, 0, st>>>(
                     (const uint16_t*)W.Bt, Kp, W.Bl);
                 QDW_LAUNCH_CHECK();
-                nn_layer_fused_kernel<8, 8, BF16S, BF16S><<<nb, 256, 0, st>>>(g, Kp, pin, W.Bt, W.Bl,
-                                                                              pout, L, D);
+                if (keep_hidden) {
+                    nn_layer_fused_kernel<8, 8, BF16S, BF16S><<<nb, 256, 0, st>>>(
+                        g, Kp, pin, W.Bt, W.Bl, pout, L, D);
+                } else {
+                    // the last layer's mixing matrix first: its product runs in this launch
+                    if ((rc = set_ptrs(W.ptrs, (float* const*)W.mix, kPaths, 3, st))) return rc;
+                    nn_embed_mix_kernel<<<(80 * 64 + 255) / 256, 256, 0, st>>>(
+                        weights + 2 * layer_w_offset(l + 1), W.Bm);
+                    QDW_LAUNCH_CHECK();
+                    nn_layer_fused_kernel<8, 8, BF16S, BF16S, true><<<nb, 256, 0, st>>>(
+                        g, Kp, pin, W.Bt, W.Bl, (void* const*)(W.ptrs + 24), L, D, W.Bm);
+                }
                 QDW_LAUNCH_CHECK();
             } else {
-                // one output channel: mix the paths first, then transport 9 fields
-                if ((rc = set_ptrs(W.ptrs, (float* const*)W.mix, kPaths, 3, st))) return rc;
-                nn_embed_mix_kernel<<<(80 * 64 + 255) / 256, 256, 0, st>>>(
-                    weights + 2 * layer_w_offset(l), W.Bm);
-                QDW_LAUNCH_CHECK();
-                nn_mix_paths_kernel<<<nb, 256, 0, st>>>(g, pin, W.Bm, (void* const*)(W.ptrs + 24));
-                QDW_LAUNCH_CHECK();
+                // one output channel: mix the paths first (already done by the 8 -> 8
+                // layer's launch when the hidden channels are not kept), then transport 9
+                // fields
+                if (keep_hidden) {
+                    if ((rc = set_ptrs(W.ptrs, (float* const*)W.mix, kPaths, 3, st))) return rc;
+                    nn_embed_mix_kernel<<<(80 * 64 + 255) / 256, 256, 0, st>>>(
+                        weights + 2 * layer_w_offset(l), W.Bm);
+                    QDW_LAUNCH_CHECK();
+                    nn_mix_paths_kernel<<<nb, 256, 0, st>>>(g, pin, W.Bm,
+                                                            (void* const*)(W.ptrs + 24));
+                    QDW_LAUNCH_CHECK();
+                }
                 nn_transport_sum_kernel<<<2 * ((g.Vh + 255) / 256), 256, 0, st>>>(
                     g, (const void* const*)(W.ptrs + 24), W.act[l + 1][0], L, D);
                 QDW_LAUNCH_CHECK();
@@ -1225,7 +1299,7 @@ int nn_precondition(qdw_op* op, const void* weights, const void* rho, void* phi,
     if ((rc = run_map(op, ScaleNorm<F64, F32>{rho, W.act[0][0], s, g.Vh}, st,
                       op->scalars + S_TMP + 2)))
         return rc;
-    if ((rc = forward<false>(op, (const float*)weights, W, st))) return rc;
+    if ((rc = forward<false>(op, (const float*)weights, W, st, false))) return rc;
     return run_map(op, Axpby<F32, F64>{W.act[kLayers][0], phi, 1.0 / s, 0.0, g.Vh}, st);
 }
 
@@ -1254,7 +1328,7 @@ extern "C" int nn_forward(qdw_op* op, const float* weights, const void* in, void
     const Geom& g = op->g;
     int rc;
     if ((rc = run_map(op, Axpby<F64, F32>{in, W.act[0][0], 1.0, 0.0, g.Vh}, st))) return rc;
-    rc = f32_mixing ? forward<true>(op, weights, W, st) : forward<false>(op, weights, W, st);
+    rc = f32_mixing ? forward<true>(op, weights, W, st) : forward<false>(op, weights, W, st, false);
     if (rc) return rc;
     return run_map(op, Axpby<F32, F64>{W.act[kLayers][0], out, 1.0, 0.0, g.Vh}, st);
 }
