@@ -294,6 +294,62 @@ __device__ __forceinline__ double block_sum(double v, double* slots, int t, int 
     return s;
 }
 
+// acc += the hops of D delta that enter x's block from outside (without the -1/2), for
+// a site x of a block of colour 1 - `colour` (delta lives on the colour blocks)
+template <int SP, int MU>
+__device__ __forceinline__ void cross_hops(const Geom& g, const BlockGeom& B, const void* delta,
+                                           const void* links, const void* dets, int par, int i,
+                                           const int x[4], int lex, cx<float> acc[12], bool& any)
+{
+    cx<float> s[12], h[6], w[6], u[6], d;
+    if (x[MU] % B.bs[MU] == B.bs[MU] - 1) {
+        const int j = lex_fwd(g, x, lex, MU) >> 1;
+        load_spinor<SP>(delta, g.Vh, 1 - par, j, s);
+        project<float, MU, -1>(s, h);
+        if (MU == 0 && g.bc_t < 0 && x[0] == g.L[0] - 1)
+            for (int c = 0; c < 6; ++c) h[c] = {-h[c].re, -h[c].im};
+        load_link<SP>(links, dets, g.Vh, par, i, MU, u, d);
+        su3_mul<float, false>(u, d, h, w);
+        expand_add<float, MU, -1>(w, acc);
+        any = true;
+    }
+    if (x[MU] % B.bs[MU] == 0) {
+        const int j = lex_bwd(g, x, lex, MU) >> 1;
+        load_spinor<SP>(delta, g.Vh, 1 - par, j, s);
+        project<float, MU, +1>(s, h);
+        if (MU == 0 && g.bc_t < 0 && x[0] == 0)
+            for (int c = 0; c < 6; ++c) h[c] = {-h[c].re, -h[c].im};
+        load_link<SP>(links, dets, g.Vh, 1 - par, j, MU, u, d);
+        su3_mul<float, true>(u, d, h, w);
+        expand_add<float, MU, +1>(w, acc);
+        any = true;
+    }
+}
+
+// r(x) -= (D delta)(x) over the hops that enter x's block from outside, applied to the
+// block residual as a block kernel loads it (delta: the corrections of the other colour's
+// blocks, from the launch before; nullptr: nothing to apply). This is the residual update
+// between the two colours (Fig. 3 right) done by the receiving blocks, in FP32 on the loaded
+// values, instead of a separate pass over the lattice (sap_boundary_kernel) that rounds r
+// to storage once more.
+template <int SP>
+__device__ __forceinline__ void apply_cross_hops(const Geom& g, const BlockGeom& B, const void* delta,
+                                                 const void* links, const void* dets, int par,
+                                                 int i, const int x[4], int lex, cx<float> r[12])
+{
+    if (!delta) return;
+    cx<float> acc[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[c] = {0.f, 0.f};
+    bool any = false;
+    cross_hops<SP, 0>(g, B, delta, links, dets, par, i, x, lex, acc, any);
+    cross_hops<SP, 1>(g, B, delta, links, dets, par, i, x, lex, acc, any);
+    cross_hops<SP, 2>(g, B, delta, links, dets, par, i, x, lex, acc, any);
+    cross_hops<SP, 3>(g, B, delta, links, dets, par, i, x, lex, acc, any);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) r[c] = r[c] + scale(acc[c], 0.5f);  // hops carry -1/2
+}
+
 // 16-bit storage: registers for two waves per SIMD (two 256-site blocks per CU)
 template <int SP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SP == F32 ? 1 : 2)))
@@ -475,7 +531,7 @@ void sap_mr_eo_kernel(Geom g, BlockGeom B, int colour, int nmr,
                                                         const void* __restrict__ dets,
                                                         const void* __restrict__ clover,
                                                         const void* __restrict__ cloverinv,
-                                                        RhsStride bat)
+                                                        RhsStride bat, const void* odelta)
 {
     __shared__ float rl[24][kBMax];
     __shared__ float hb[4][12][kBMax];
@@ -485,6 +541,7 @@ void sap_mr_eo_kernel(Geom g, BlockGeom B, int colour, int nmr,
     rs = (char*)rs + rhs * bat.fstride;
     psis = (char*)psis + rhs * bat.fstride;
     delta = (char*)delta + rhs * bat.fstride;
+    if (odelta) odelta = (const char*)odelta + rhs * bat.fstride;
     const int t = threadIdx.x;
     const int nw = B.bvol >> 6;
     int b[4];
@@ -538,6 +595,7 @@ void sap_mr_eo_kernel(Geom g, BlockGeom B, int colour, int nmr,
 
     cx<float> r[12];
     load_spinor<SP>(rs, g.Vh, par, i, r);
+    apply_cross_hops<SP>(g, B, odelta, links, dets, par, i, x, lex, r);
     SiteOps<SP> so;  // A on even sites, A^-1 on odd sites
     so.load(g, ev ? clover : cloverinv, links, dets, par, i);
 
@@ -678,38 +736,6 @@ void sap_mr_eo_kernel(Geom g, BlockGeom B, int colour, int nmr,
     store_spinor<SP>(rs, g.Vh, par, i, res);
 }
 
-// acc += the hops of D delta that enter x's block from outside (without the -1/2), for
-// a site x of a block of colour 1 - `colour` (delta lives on the colour blocks)
-template <int SP, int MU>
-__device__ __forceinline__ void cross_hops(const Geom& g, const BlockGeom& B, const void* delta,
-                                           const void* links, const void* dets, int par, int i,
-                                           const int x[4], int lex, cx<float> acc[12], bool& any)
-{
-    cx<float> s[12], h[6], w[6], u[6], d;
-    if (x[MU] % B.bs[MU] == B.bs[MU] - 1) {
-        const int j = lex_fwd(g, x, lex, MU) >> 1;
-        load_spinor<SP>(delta, g.Vh, 1 - par, j, s);
-        project<float, MU, -1>(s, h);
-        if (MU == 0 && g.bc_t < 0 && x[0] == g.L[0] - 1)
-            for (int c = 0; c < 6; ++c) h[c] = {-h[c].re, -h[c].im};
-        load_link<SP>(links, dets, g.Vh, par, i, MU, u, d);
-        su3_mul<float, false>(u, d, h, w);
-        expand_add<float, MU, -1>(w, acc);
-        any = true;
-    }
-    if (x[MU] % B.bs[MU] == 0) {
-        const int j = lex_bwd(g, x, lex, MU) >> 1;
-        load_spinor<SP>(delta, g.Vh, 1 - par, j, s);
-        project<float, MU, +1>(s, h);
-        if (MU == 0 && g.bc_t < 0 && x[0] == 0)
-            for (int c = 0; c < 6; ++c) h[c] = {-h[c].re, -h[c].im};
-        load_link<SP>(links, dets, g.Vh, 1 - par, j, MU, u, d);
-        su3_mul<float, true>(u, d, h, w);
-        expand_add<float, MU, +1>(w, acc);
-        any = true;
-    }
-}
-
 // r(x) -= (D delta)(x) over the hops that enter x's block from outside
 template <int SP>
 __global__ __launch_bounds__(256) void sap_boundary_kernel(Geom g, BlockGeom B, int colour,
@@ -756,14 +782,23 @@ int cycles_impl(qdw_op* op, const BlockGeom& B, int ncy, int nmr, void* rs, void
     const dim3 gmr(B.nblk / 2 * nrhs), gbd(walk_blocks(g) * nrhs);
     for (int cy = 0; cy < ncy; ++cy)
         for (int c = 0; c < 2; ++c) {
-            if (eo)
-                sap_mr_eo_kernel<SP><<<gmr, B.bvol, 0, st>>>(g, B, c, nmr, rs, psis, delta,
-                                                             op->links[SP], op->det[SP],
-                                                             op->clover[SP], op->cloverinv[SP], bat);
-            else
-                sap_mr_kernel<SP><<<gmr, B.bvol, 0, st>>>(g, B, c, nmr, rs, psis, delta,
-                                                          op->links[SP], op->det[SP],
-                                                          op->clover[SP], bat, SapAdapt{});
+            if (eo) {
+                // the reduced block solve takes the hops of the other colour's last
+                // corrections into its residual as it loads it (cheaper there than a pass
+                // of its own: 191 against 168 + 33 us per colour at 24^3 x 48, FP16); after
+                // the last colour of the last cycle the residual is not used (only psi is),
+                // so that last update is not made
+                sap_mr_eo_kernel<SP><<<gmr, B.bvol, 0, st>>>(
+                    g, B, c, nmr, rs, psis, delta, op->links[SP], op->det[SP], op->clover[SP],
+                    op->cloverinv[SP], bat, cy == 0 && c == 0 ? nullptr : delta);
+                QDW_LAUNCH_CHECK();
+                continue;
+            }
+            // the plain block solve, at two waves per SIMD, hides the latency of those
+            // loads worse than a pass of their own (169 against 132 + 33 us)
+            sap_mr_kernel<SP><<<gmr, B.bvol, 0, st>>>(g, B, c, nmr, rs, psis, delta,
+                                                      op->links[SP], op->det[SP],
+                                                      op->clover[SP], bat, SapAdapt{});
             QDW_LAUNCH_CHECK();
             sap_boundary_kernel<SP><<<gbd, 2 * g.ts, 0, st>>>(g, B, c, rs, delta, op->links[SP],
                                                               op->det[SP], bat);
