@@ -86,8 +86,8 @@ __device__ __forceinline__ void hop_forward(float (*rl)[kBMax], const BlockGeom&
     }
 }
 
-template <int MU>
-__device__ __forceinline__ void hop_backward(float (*hb)[12][kBMax], const int l[4], int t,
+template <int MU, int N = kBMax>
+__device__ __forceinline__ void hop_backward(float (*hb)[12][N], const int l[4], int t,
                                              cx<float> v[12])
 {
     if (l[MU] > 0) {
@@ -251,8 +251,8 @@ __device__ __forceinline__ void push_and_forward(float (*hb)[12][kBMax], float (
 
 // The same hand-over and forward hop with the neighbour's lane given explicitly (-1: the
 // neighbour is outside the block), for blocks whose lanes are not numbered by site
-template <int SP, int MU>
-__device__ __forceinline__ void push_to(float (*hb)[12][kBMax], int dst, const cx<float> r[12],
+template <int SP, int MU, int N>
+__device__ __forceinline__ void push_to(float (*hb)[12][N], int dst, const cx<float> r[12],
                                         const cx<float> u[6], cx<float> d)
 {
     if (dst >= 0) {
@@ -267,8 +267,8 @@ __device__ __forceinline__ void push_to(float (*hb)[12][kBMax], int dst, const c
     }
 }
 
-template <int SP, int MU>
-__device__ __forceinline__ void forward_from(float (*rl)[kBMax], int src, const cx<float> u[6],
+template <int SP, int MU, int N>
+__device__ __forceinline__ void forward_from(float (*rl)[N], int src, const cx<float> u[6],
                                              cx<float> d, cx<float> v[12])
 {
     if (src >= 0) {
@@ -521,7 +521,7 @@ void sap_mr_kernel(Geom g, BlockGeom B, int colour, int nmr,
 //   chi_o = A_oo^-1 (r_o - D_oe chi_e) = A_oo^-1 (r_o + 1/2 H chi_e)
 // after which the block residual is (the MR residual, 0). Even lanes hold A, odd lanes
 // A^-1 in registers; every application of H is one pass of the in-block hops over LDS.
-template <int SP>
+template <int SP, bool SPLIT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SP == F32 ? 1 : 2)))
 void sap_mr_eo_kernel(Geom g, BlockGeom B, int colour, int nmr,
                                                         void* __restrict__ rs,
@@ -533,8 +533,15 @@ void sap_mr_eo_kernel(Geom g, BlockGeom B, int colour, int nmr,
                                                         const void* __restrict__ cloverinv,
                                                         RhsStride bat, const void* odelta)
 {
-    __shared__ float rl[24][kBMax];
-    __shared__ float hb[4][12][kBMax];
+    // Hand-over buffers. Lanes numbered by parity (SPLIT, below): a hop pass writes rl only
+    // from its sending half and hb only for its receiving half, so both are indexed by the
+    // lane's place within its half and take half the room; that pays for two sets used in
+    // turn, and a pass then needs no barrier at its end (the set it wrote is next written
+    // two passes later, after both barriers of the pass between). Lanes numbered by site:
+    // one full-size set and a third barrier per pass.
+    constexpr int NB = SPLIT ? 2 : 1, NL = SPLIT ? kBMax / 2 : kBMax;
+    __shared__ float rl[NB][24][NL];
+    __shared__ float hb[NB][4][12][NL];
     __shared__ double red[4][3];
     const int rhs = (int)blockIdx.x % bat.nrhs, blk = (int)blockIdx.x / bat.nrhs;
     if (bat.gate && !bat.gate[(long)rhs * bat.gstride]) return;
@@ -559,7 +566,7 @@ void sap_mr_eo_kernel(Geom g, BlockGeom B, int colour, int nmr,
     // other, so whole wavefronts skip the half they have no part in. With an odd x3
     // extent lanes are numbered by site (correct, without the saving).
     const int half = B.bvol >> 1;
-    const bool split = (B.bs[3] & 1) == 0;
+    constexpr bool split = SPLIT;  // launched so only for an even x3 block extent
     const int bpar = (b[0] * B.bs[0] + b[1] * B.bs[1] + b[2] * B.bs[2] + b[3] * B.bs[3]) & 1;
     auto local = [&](int site, int lc[4]) {
         int r = site;
@@ -585,13 +592,16 @@ void sap_mr_eo_kernel(Geom g, BlockGeom B, int colour, int nmr,
     const int par = (x[0] + x[1] + x[2] + x[3]) & 1;
     const int i = lex >> 1;
     const bool ev = par == 0;
-    // lanes of the +mu neighbours inside the block (the other parity), -1 at the block edge
+    // places in the hand-over buffers of the +mu neighbours inside the block (the other
+    // parity; with SPLIT, within that parity's half), -1 at the block edge, and of this lane
     int nbl[4];
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
         const int sn = site + B.lstride[mu];
-        nbl[mu] = l[mu] < B.bs[mu] - 1 ? (split ? (1 - par) * half + (sn >> 1) : sn) : -1;
+        nbl[mu] = l[mu] < B.bs[mu] - 1 ? (split ? (sn >> 1) : sn) : -1;
     }
+    const int tl = split ? t - par * half : t;
+    int set = 0;  // hand-over set of the next pass (SPLIT: alternating)
 
     cx<float> r[12];
     load_spinor<SP>(rs, g.Vh, par, i, r);
@@ -607,11 +617,14 @@ void sap_mr_eo_kernel(Geom g, BlockGeom B, int colour, int nmr,
     // src is non-zero on the lanes of `from` only
     auto hops = [&](int from, const cx<float> src[12], cx<float> vh[12]) {
         const bool sends = par == from;
+        float (*rb)[NL] = rl[set];
+        float (*hbb)[12][NL] = hb[set];
+        if (SPLIT) set ^= 1;
         if (sends) {
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
-                rl[2 * c][t] = src[c].re;
-                rl[2 * c + 1][t] = src[c].im;
+                rb[2 * c][tl] = src[c].re;
+                rb[2 * c + 1][tl] = src[c].im;
             }
         }
         __syncthreads();  // rl holds src
@@ -621,31 +634,31 @@ void sap_mr_eo_kernel(Geom g, BlockGeom B, int colour, int nmr,
         so.opaque();
         if (sends) {
             so.template link<0>(u, d);
-            push_to<SP, 0>(hb, nbl[0], src, u, d);
+            push_to<SP, 0, NL>(hbb, nbl[0], src, u, d);
             so.template link<1>(u, d);
-            push_to<SP, 1>(hb, nbl[1], src, u, d);
+            push_to<SP, 1, NL>(hbb, nbl[1], src, u, d);
             so.template link<2>(u, d);
-            push_to<SP, 2>(hb, nbl[2], src, u, d);
+            push_to<SP, 2, NL>(hbb, nbl[2], src, u, d);
             so.template link<3>(u, d);
-            push_to<SP, 3>(hb, nbl[3], src, u, d);
+            push_to<SP, 3, NL>(hbb, nbl[3], src, u, d);
         } else {
             so.template link<0>(u, d);
-            forward_from<SP, 0>(rl, nbl[0], u, d, vh);
+            forward_from<SP, 0, NL>(rb, nbl[0], u, d, vh);
             so.template link<1>(u, d);
-            forward_from<SP, 1>(rl, nbl[1], u, d, vh);
+            forward_from<SP, 1, NL>(rb, nbl[1], u, d, vh);
             so.template link<2>(u, d);
-            forward_from<SP, 2>(rl, nbl[2], u, d, vh);
+            forward_from<SP, 2, NL>(rb, nbl[2], u, d, vh);
             so.template link<3>(u, d);
-            forward_from<SP, 3>(rl, nbl[3], u, d, vh);
+            forward_from<SP, 3, NL>(rb, nbl[3], u, d, vh);
         }
         __syncthreads();  // every pushed half spinor is in hb
         if (!sends) {
-            hop_backward<0>(hb, l, t, vh);
-            hop_backward<1>(hb, l, t, vh);
-            hop_backward<2>(hb, l, t, vh);
-            hop_backward<3>(hb, l, t, vh);
+            hop_backward<0, NL>(hbb, l, tl, vh);
+            hop_backward<1, NL>(hbb, l, tl, vh);
+            hop_backward<2, NL>(hbb, l, tl, vh);
+            hop_backward<3, NL>(hbb, l, tl, vh);
         }
-        __syncthreads();  // rl and hb are free again
+        if (!SPLIT) __syncthreads();  // rl and hb are free again
     };
     const cx<float> z = {0.f, 0.f};
     cx<float> w[12], vh[12], res[12], chi[12];
@@ -788,9 +801,15 @@ int cycles_impl(qdw_op* op, const BlockGeom& B, int ncy, int nmr, void* rs, void
                 // of its own: 191 against 168 + 33 us per colour at 24^3 x 48, FP16); after
                 // the last colour of the last cycle the residual is not used (only psi is),
                 // so that last update is not made
-                sap_mr_eo_kernel<SP><<<gmr, B.bvol, 0, st>>>(
-                    g, B, c, nmr, rs, psis, delta, op->links[SP], op->det[SP], op->clover[SP],
-                    op->cloverinv[SP], bat, cy == 0 && c == 0 ? nullptr : delta);
+                const void* od = cy == 0 && c == 0 ? nullptr : delta;
+                if (B.bs[3] % 2 == 0)
+                    sap_mr_eo_kernel<SP, true><<<gmr, B.bvol, 0, st>>>(
+                        g, B, c, nmr, rs, psis, delta, op->links[SP], op->det[SP], op->clover[SP],
+                        op->cloverinv[SP], bat, od);
+                else
+                    sap_mr_eo_kernel<SP, false><<<gmr, B.bvol, 0, st>>>(
+                        g, B, c, nmr, rs, psis, delta, op->links[SP], op->det[SP], op->clover[SP],
+                        op->cloverinv[SP], bat, od);
                 QDW_LAUNCH_CHECK();
                 continue;
             }
