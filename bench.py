@@ -8,6 +8,8 @@ each read once), inputs resident in HBM.
 
 Also reported, each timed on its own outside the K steps:
   * D in FP32 and FP16 storage, D^+ in FP64, and FP64 D on 4 fields in one launch;
+  * the link-storage control: FP64 D and D^+ with full 3x3 links (18 reals) against the
+    two-row storage, both in the one-lane-per-site form;
   * the 32^3 x 64 normal-equation solve to FP64 true residual 1e-10: plain FP64 CG
     against FP32, FP16 and BF16 regular steps with FP64 reset steps, and the BF16 -> FP32
     -> FP64 precision cascade; and the even-odd reduced normal equations D^+ D^ psi_e =
@@ -33,7 +35,7 @@ Also reported, each timed on its own outside the K steps:
     on one core, and CGNE / GCR / SAP-GCR solves at small lattices beside the GPU's.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-solves]
-                       [--legs multi,cgne,nn,gcr,sap,batch] [--autotune] [--calibrate]
+                       [--legs links,multi,cgne,nn,gcr,sap,batch] [--autotune] [--calibrate]
 """
 from __future__ import annotations
 
@@ -185,6 +187,34 @@ def solve_record(info):
     return {"s": round(info["t_sec"], 4), "steps": info["n_steps"], "status": info["status"],
             "resets_or_restarts": info["nreset"], "rel_res_true": info["rel_res_true"],
             "dw_fp64": info["n_dw_hi"], "dw_low": info["n_dw_lo"]}
+
+
+def links_control(op, qdw, psi, shape=(128, 4, 0, 0, 0)):
+    """The link-storage control at 32^3 x 64: FP64 D and D^+ with the links read as full 3x3
+    matrices (18 reals) against the two-row storage (12 reals + det U, third row rebuilt in
+    the kernel), both in the one-lane-per-site form with a plain hop loop on the same walk
+    (the only form the control exists in). Nominal bytes per site 1536 and 1376. The
+    operator's FP64 shape is restored afterwards."""
+    keep = qdw.get_dw_shape(op, "f64")
+    x, y = op.pack(psi, "f64"), op.new_field("f64")
+    qdw.set_full_links(op)
+    rec = {"shape": list(shape)}
+    try:
+        qdw.set_dw_shape(op, "f64", *shape)
+        for name, fn, per_site in (
+                ("two_row_13", lambda: qdw.dw_apply(op, x, y, "f64"), 1376),
+                ("full_18", lambda: qdw.dw_apply_full_links(op, x, y), 1536),
+                ("two_row_13_dag", lambda: qdw.dw_dag_apply(op, x, y, "f64"), 1376),
+                ("full_18_dag", lambda: qdw.dw_apply_full_links(op, x, y, dagger=True), 1536)):
+            for _ in range(5):
+                fn()
+            d = time_launches(fn, 50)
+            rec[name] = {"ms": round(d * 1e3, 4), "GB_s_nominal": round(per_site * op.V / d / 1e9, 1)}
+    finally:
+        qdw.set_dw_shape(op, "f64", *keep)
+        op._full_links = None
+    log("  link-storage control: %s" % rec)
+    return rec
 
 
 def multi_rhs(op, qdw, psi, n=4):
@@ -434,10 +464,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solves", action="store_true")
     ap.add_argument("--no-nn", action="store_true", help="skip training the learned preconditioner")
-    ap.add_argument("--legs", default="multi,cgne,nn,gcr,sap,batch",
-                    help="comma-separated legs to run after the D timing (multi: D on 4 "
-                         "fields in one launch; cgne, nn, gcr, batch: solves; sap: SAP "
-                         "applications); kernel traces of one leg use this")
+    ap.add_argument("--legs", default="links,multi,cgne,nn,gcr,sap,batch",
+                    help="comma-separated legs to run after the D timing (links: the "
+                         "full-matrix link control; multi: D on 4 fields in one launch; "
+                         "cgne, nn, gcr, batch: solves; sap: SAP applications); kernel "
+                         "traces of one leg use this")
     ap.add_argument("--autotune", action="store_true",
                     help="pick the 32^3x64 D-kernel shapes with the autotuner instead of the "
                          "pinned ones (its own launches then join any kernel trace)")
@@ -553,6 +584,8 @@ def main():
         legs.discard("nn")
     if legs:
         log("solves: %s ..." % sorted(legs))
+    if "links" in legs:
+        out["dw_links_control_f64"] = links_control(op, qdw, psi)
     if "multi" in legs:
         out["dw_multi_rhs_f64"] = multi_rhs(op, qdw, psi)
     if "cgne" in legs:

@@ -120,6 +120,22 @@ int qdw_unpack(const qdw_op* op, const void* eo, double* canonical, qdw_prec pre
 int dw_apply(qdw_op* op, const void* in, void* out, qdw_prec prec, void* stream);
 int dw_dag_apply(qdw_op* op, const void* in, void* out, qdw_prec prec, void* stream);
 
+/* Uncompressed control for the link storage (Sec. 1: the hopping term reads every link;
+ * not an operation of the paper): the FP64 operator with each link read as its full 3x3
+ * matrix, 18 reals, instead of two rows and det U with the third row rebuilt in the kernel.
+ * qdw_full_links_bytes: device bytes of the full FP64 links of op (0 for a null op).
+ * qdw_set_full_links: forms them in dev_mem (device, caller-owned, 16-byte aligned, at
+ * least qdw_full_links_bytes; op keeps using it until qdw_destroy or the next call) from
+ * op's compressed FP64 links, the third row as d conj(row0 x row1) like the D kernels;
+ * asynchronous on stream. dw_apply_full_links: out = D in (dagger != 0: D^+ in), FP64
+ * eo-SoA fields (device, distinct), in a one-lane-per-site kernel with a plain hop loop on
+ * the walk of op's FP64 shape (128-site tiles in chunks of 4 slices when that shape is the
+ * marching form); QDW_EINVAL before qdw_set_full_links. Results equal dw_apply's to the
+ * last bits of FP64 rounding. */
+size_t qdw_full_links_bytes(const qdw_op* op);
+int qdw_set_full_links(qdw_op* op, void* dev_mem, size_t bytes, void* stream);
+int dw_apply_full_links(qdw_op* op, const void* in, void* out, int dagger, void* stream);
+
 /* Even-odd reduced operator (the matrix of Sec. 3 is stored even sites first, Fig. 3
  * left; its Schur complement on the even sites): out_e = D^ in_e with
  * D^ = A_ee - D_eo A_oo^-1 D_oe, and D^+ = gamma_5 D^ gamma_5. Only the even half of `in`

@@ -28,6 +28,7 @@
 #include <chrono>
 #include <cstdio>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "qdw_host.h"
@@ -472,6 +473,108 @@ int dispatch(qdw_op* op, const RhsTable& tab, int nrhs, int prec, bool dag, hipS
     }
 }
 
+// ------------------------------------------------------------------ uncompressed control
+//
+// The same operator with every FP64 link read as its full 3x3 matrix (18 reals, 9 chunks
+// per link, no row rebuilt in the kernel): the control for the two-row storage. Only the
+// one-lane-per-site form with a plain hop loop exists for it; it takes the walk of the
+// operator's FP64 shape when that is a one-lane-per-site shape, else 128-site tiles in
+// chunks of 4 slices, and is compared with the compressed kernel in the same form.
+
+// full links, [par * 4 + mu][site / 64][9][site % 64] chunks of one complex number each:
+// rows 0, 1 as stored and row 2 = d conj(row0 x row1), formed as the compressed kernels
+// form it
+__global__ __launch_bounds__(256) void full_links_kernel(Geom g, const void* links, const void* dets,
+                                                         void* full)
+{
+    const long n = (long)g.Vh * 8;
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (long)gridDim.x * blockDim.x) {
+        const int row = (int)(q / g.Vh), i = (int)(q - (long)row * g.Vh);
+        cx<double> u[6], d;
+        load_link<F64>(links, dets, g.Vh, row >> 2, i, row & 3, u, d);
+        const cx<double> m[9] = {u[0], u[1], u[2], u[3], u[4], u[5],
+                                 d * conj_(cmadd(u[1] * u[5], -u[2], u[4])),
+                                 d * conj_(cmadd(u[2] * u[3], -u[0], u[5])),
+                                 d * conj_(cmadd(u[0] * u[4], -u[1], u[3]))};
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            Chunk<F64> c;
+            c.v[0] = m[k].re;
+            c.v[1] = m[k].im;
+            store_chunk<F64>(full, chunk_at(g.Vh, 9, row, k, i), c);
+        }
+    }
+}
+
+template <bool DAG>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1)))
+void dw_full_kernel(Geom g, const void* __restrict__ in, void* __restrict__ out,
+                    const void* __restrict__ full, const void* __restrict__ clover)
+{
+    int par, i;
+    if (!walk_site(g, xcd_tile(blockIdx.x, gridDim.x), threadIdx.x, par, i)) return;
+    int x[4], lex;
+    eo_coords(g, par, i, x, lex);
+    cx<double> hop[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) hop[c] = {0.0, 0.0};
+    auto one = [&](auto mu_c, auto fwd_c, int ii, int ll, const int xx[4]) {
+        constexpr int MU = decltype(mu_c)::value;
+        constexpr bool FWD = decltype(fwd_c)::value;
+        constexpr int SG = (FWD != DAG) ? -1 : +1;
+        const int j = (FWD ? lex_fwd(g, xx, ll, MU) : lex_bwd(g, xx, ll, MU)) >> 1;
+        cx<double> sp[12], m[9], h[6], w[6];
+        load_spinor<F64>(in, g.Vh, 1 - par, j, sp);
+        const int lrow = (FWD ? par : 1 - par) * 4 + MU, li = FWD ? ii : j;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const Chunk<F64> c = load_chunk_cached<F64>(full, chunk_at(g.Vh, 9, lrow, k, li));
+            m[k] = {c.v[0], c.v[1]};
+        }
+        project<double, MU, SG>(sp, h);
+        if (MU == 0 && g.bc_t < 0 && xx[0] == (FWD ? g.L[0] - 1 : 0)) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) h[c] = -h[c];
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const cx<double> h0 = h[3 * a], h1 = h[3 * a + 1], h2 = h[3 * a + 2];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                if (FWD)
+                    w[3 * a + r] = cmadd(cmadd(m[3 * r] * h0, m[3 * r + 1], h1), m[3 * r + 2], h2);
+                else
+                    w[3 * a + r] = cmadd_conj(cmadd_conj(cmul_conj(m[r], h0), m[3 + r], h1), m[6 + r], h2);
+            }
+        }
+        expand_add<double, MU, SG>(w, hop);
+    };
+    // the eight hops as a runtime loop over opaque site indices (as dw_kernel)
+#pragma unroll 1
+    for (int k = 0; k < 8; ++k) {
+        int ii = i, ll = lex, xx[4] = {x[0], x[1], x[2], x[3]};
+        asm volatile("" : "+v"(ii), "+v"(ll), "+v"(xx[0]), "+v"(xx[1]), "+v"(xx[2]), "+v"(xx[3]));
+        using T = std::true_type;
+        using F = std::false_type;
+        switch (k) {
+        case 0: one(std::integral_constant<int, 0>{}, T{}, ii, ll, xx); break;
+        case 1: one(std::integral_constant<int, 0>{}, F{}, ii, ll, xx); break;
+        case 2: one(std::integral_constant<int, 1>{}, T{}, ii, ll, xx); break;
+        case 3: one(std::integral_constant<int, 1>{}, F{}, ii, ll, xx); break;
+        case 4: one(std::integral_constant<int, 2>{}, T{}, ii, ll, xx); break;
+        case 5: one(std::integral_constant<int, 2>{}, F{}, ii, ll, xx); break;
+        case 6: one(std::integral_constant<int, 3>{}, T{}, ii, ll, xx); break;
+        default: one(std::integral_constant<int, 3>{}, F{}, ii, ll, xx); break;
+        }
+    }
+    cx<double> sp[12], acc[12];
+    load_spinor<F64>(in, g.Vh, par, i, sp);
+    clover54_apply<F64>(clover, g.Vh, par, i, g.cdiag, sp, acc);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[c] = acc[c] - scale(hop[c], 0.5);
+    store_spinor<F64>(out, g.Vh, par, i, acc);
+}
+
 int apply_checked(qdw_op* op, const void* in, void* out, qdw_prec prec, bool dag, void* stream)
 {
     QDW_CHECK(op && in && out, QDW_EINVAL, "dw_apply: null argument");
@@ -527,6 +630,46 @@ extern "C" int dw_apply(qdw_op* op, const void* in, void* out, qdw_prec prec, vo
 extern "C" int dw_dag_apply(qdw_op* op, const void* in, void* out, qdw_prec prec, void* stream)
 {
     return apply_checked(op, in, out, prec, true, stream);
+}
+
+extern "C" size_t qdw_full_links_bytes(const qdw_op* op)
+{
+    return op ? (size_t)padded(op->g.Vh) * 8 * 9 * 16 : 0;
+}
+
+extern "C" int qdw_set_full_links(qdw_op* op, void* dev_mem, size_t bytes, void* stream)
+{
+    QDW_CHECK(op && dev_mem, QDW_EINVAL, "qdw_set_full_links: null argument");
+    QDW_CHECK(bytes >= qdw_full_links_bytes(op), QDW_EWORKSPACE,
+              "qdw_set_full_links: block smaller than qdw_full_links_bytes()");
+    QDW_CHECK(((uintptr_t)dev_mem & 15) == 0, QDW_EINVAL,
+              "qdw_set_full_links: the block must be 16-byte aligned");
+    hipStream_t st = (hipStream_t)stream;
+    full_links_kernel<<<1024, 256, 0, st>>>(op->g, op->links[F64], op->det[F64], dev_mem);
+    QDW_LAUNCH_CHECK();
+    op->full_links = dev_mem;
+    return QDW_OK;
+}
+
+extern "C" int dw_apply_full_links(qdw_op* op, const void* in, void* out, int dagger, void* stream)
+{
+    QDW_CHECK(op && in && out, QDW_EINVAL, "dw_apply_full_links: null argument");
+    QDW_CHECK(in != out, QDW_EINVAL, "dw_apply_full_links: in and out must be distinct fields");
+    QDW_CHECK(op->full_links, QDW_EINVAL,
+              "dw_apply_full_links: no full links (call qdw_set_full_links first)");
+    Geom g = op->g;
+    const auto& sh = op->dw_shape[F64];
+    if (sh.march) set_walk(g, 128, g.L[0] % 4 == 0 ? 4 : 1, 0);
+    else set_walk(g, sh.ts, sh.nt, sh.walk);
+    hipStream_t st = (hipStream_t)stream;
+    if (dagger)
+        dw_full_kernel<true><<<walk_blocks(g), 2 * g.ts, 0, st>>>(g, in, out, op->full_links,
+                                                                   op->clover54[F64]);
+    else
+        dw_full_kernel<false><<<walk_blocks(g), 2 * g.ts, 0, st>>>(g, in, out, op->full_links,
+                                                                    op->clover54[F64]);
+    QDW_LAUNCH_CHECK();
+    return QDW_OK;
 }
 
 extern "C" int dw_schur_apply(qdw_op* op, const void* in, void* out, qdw_prec prec, void* stream)

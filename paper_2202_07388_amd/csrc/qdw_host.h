@@ -20,6 +20,7 @@ struct qdw_op {
     void* clover[4];
     void* cloverinv[4];    // per precision: inverses of the clover blocks (same format)
     void* clover54[4];     // per precision: the compact clover form the D kernels read
+    void* full_links;      // optional, caller-owned: FP64 links as full 3x3 matrices
     // per precision: shape of the D kernel (sites per parity of a workgroup, time slices
     // per walk chunk, software-pipelined hop loop, walk order, marching form); other site
     // kernels use g

@@ -115,6 +115,9 @@ _OPTIONAL: list = [
     ("sap_eo_apply", [_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int * 4),
                       ctypes.c_int, _P, ctypes.c_size_t, _P], ctypes.c_int),
     ("qdw_sap_noalloc_max_bytes", [], ctypes.c_size_t),
+    ("qdw_full_links_bytes", [_P], ctypes.c_size_t),
+    ("qdw_set_full_links", [_P, _P, ctypes.c_size_t, _P], ctypes.c_int),
+    ("dw_apply_full_links", [_P, _P, _P, ctypes.c_int, _P], ctypes.c_int),
     ("sap_apply_noalloc", [_P, _P, _P, ctypes.c_int, ctypes.c_int,
                            ctypes.POINTER(ctypes.c_int * 4), ctypes.c_int, _P], ctypes.c_int),
     ("qdw_axpby", [_P, ctypes.c_double, _P, ctypes.c_double, _P, ctypes.c_int, _P], ctypes.c_int),
@@ -228,6 +231,7 @@ class Op:
             self._h = None
         self._dev_mem = None
         self._host_mem = None
+        self._full_links = None
 
     def __del__(self):
         try:
@@ -511,6 +515,23 @@ def sap_apply(op: Op, rho, phi, ncy: int = 5, nmr: int = 4, bs=(4, 4, 4, 4),
     _check(fn(op.handle, _ptr(rho), _ptr(phi), ncy, nmr, ctypes.byref(b), PREC[sdtype],
               _ptr(ws), ws.numel(), _stream()), name)
     return phi
+
+
+def set_full_links(op: Op):
+    """Form op's FP64 links as full 3x3 matrices (the uncompressed control) in a device
+    block taken from torch and kept on op."""
+    torch = _torch()
+    n = int(load().qdw_full_links_bytes(op.handle))
+    op._full_links = torch.empty(n, dtype=torch.uint8, device=op.device)
+    _check(load().qdw_set_full_links(op.handle, _ptr(op._full_links), n, _stream()),
+           "qdw_set_full_links")
+
+
+def dw_apply_full_links(op: Op, x, y, dagger: bool = False):
+    """y = D x (D^+ x) in FP64 with the full-matrix links of set_full_links."""
+    _check(load().dw_apply_full_links(op.handle, _ptr(x), _ptr(y), int(dagger), _stream()),
+           "dw_apply_full_links")
+    return y
 
 
 def sap_apply_noalloc(op: Op, rho, phi, ncy: int = 5, nmr: int = 4, bs=(4, 4, 4, 4),

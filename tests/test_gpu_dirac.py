@@ -50,6 +50,33 @@ def test_dw_parity(case, prec, dag):
         assert maxrel(got, want) <= 1e-13
 
 
+@pytest.mark.parametrize("dag", [False, True])
+def test_full_links_control(case, dag):
+    """The uncompressed control (links read as full 3x3 matrices) against the oracle at the
+    FP64 bar, and against the compressed kernel: the third rows are formed by the same
+    FP64 expression, so only the order of the final sums can differ (a few ulp)."""
+    dims, gop, oop, psi = case
+    x = gop.pack(psi, "f64")
+    qdw.set_full_links(gop)
+    got = gop.new_field("f64")
+    qdw.dw_apply_full_links(gop, x, got, dagger=dag)
+    ref = gop.new_field("f64")
+    (qdw.dw_dag_apply if dag else qdw.dw_apply)(gop, x, ref, "f64")
+    g = gop.unpack(got, "f64").cpu().numpy()
+    want = (oop.dw_dag if dag else oop.dw)(psi)
+    assert rel(g, want) <= TOL["f64"] and maxrel(g, want) <= TOL["f64"]
+    assert maxrel(g, gop.unpack(ref, "f64").cpu().numpy()) <= 1e-14
+
+
+def test_full_links_need_setting_first():
+    dims = (4, 4, 4, 4)
+    su3, th = syn.gauge_field(dims, 0.3, 0.1, 17)
+    gop = qdw.Op(dims, su3, th, 0.1, 1.5, -1)
+    x = gop.pack(syn.gaussian_spinor(dims, 18), "f64")
+    with pytest.raises(qdw.QdwError, match="full links"):
+        qdw.dw_apply_full_links(gop, x, gop.new_field("f64"))
+
+
 def test_pack_unpack_round_trip():
     dims = (6, 4, 4, 6)
     su3, th = syn.gauge_field(dims, 0.3, 0.1, 3)
