@@ -101,6 +101,14 @@ def test_schur_entry_points_reject_null_without_gpu(lib):
     assert lib.dw_schur_dag_apply(None, None, None, 0, None) == -1
 
 
+def test_full_link_control_rejects_null_without_gpu(lib):
+    assert lib.qdw_full_links_bytes(None) == 0
+    assert lib.qdw_set_full_links(None, None, 0, None) == -1
+    assert b"qdw_set_full_links" in lib.qdw_last_error()
+    assert lib.dw_apply_full_links(None, None, None, 0, None) == -1
+    assert b"dw_apply_full_links" in lib.qdw_last_error()
+
+
 def test_sap_eo_rejects_bad_arguments_without_gpu(lib):
     import ctypes
     bs = (ctypes.c_int * 4)(4, 4, 4, 4)
