@@ -186,9 +186,14 @@ void dw_kernel(Geom g, RhsTable tab, int nrhs, const void* __restrict__ links,
 // The lane's own spinor of a slice is loaded once, as the +t neighbour one step earlier,
 // and kept in registers for the clover term and the hand-over (a reload a step later
 // would find it evicted from L2); the t link likewise within a step.
-// Only the spatial hops read neighbours from memory; the neighbouring tiles' workgroups
-// march through the same slices at the same time, so those come from L2. One barrier per
-// step: the LDS buffers are double-buffered by slice parity (see the step comments).
+// Only the spatial hops read neighbours from memory, and they are done one step early: in
+// the step that loads slice t+1 (every lane its own site, all workgroups of an XCD at about
+// the same time), the lane also forms A psi and the six spatial hops of its site at t+1,
+// while those spinors are still in L2; the time hops are added in the next step, once the
+// partner has handed them over. Gathering a slice in the step after it was loaded found
+// most of it evicted (an XCD streams more than its 4 MB L2 per step) and read it from HBM
+// a second time. One barrier per step: the LDS buffers are double-buffered by slice
+// parity (see the step comments).
 template <int P, bool DAG, bool PIPE>
 __device__ __forceinline__ void march_site_hops(const Geom& g, const void* in, const void* links,
                                                 const void* dets, int par, int i, const int x[4],
@@ -279,9 +284,19 @@ __global__ __launch_bounds__(256) void dw_march_kernel(Geom g, RhsTable tab, int
         su3_mul<R, true>(u, d, h, w);
         put6(pw, slot, partner, w);
     };
+    // A psi plus the six spatial hops (scaled by -1/2) of this lane's site at slice tt,
+    // whose spinor `sp` the lane holds
+    auto site_part = [&](int tt, const cx<R> sp[12], cx<R> acc[12]) {
+        const int i = tt * g.S + k;
+        int x[4], lex;
+        eo_coords(g, par, i, x, lex);
+        clover54_apply<P>(clover, g.Vh, par, i, (R)g.cdiag, sp, acc);
+        march_site_hops<P, DAG, PIPE>(g, in, links, dets, par, i, x, lex, acc);
+    };
     // the lane's own spinor of the current slice stays in registers from the step that
-    // loaded it for the partner (a reload one step later would come from HBM again)
-    cx<R> own[12];
+    // loaded it for the partner (a reload one step later would come from HBM again), and
+    // so does the accumulator of the current slice, begun in the step before
+    cx<R> own[12], acc[12];
     if (valid) {
         const int tp = t0 == 0 ? g.L[0] - 1 : t0 - 1;
         cx<R> u[6], d;
@@ -289,6 +304,7 @@ __global__ __launch_bounds__(256) void dw_march_kernel(Geom g, RhsTable tab, int
         load_link<P>(links, dets, g.Vh, par, tp * g.S + k, 0, u, d);
         push(tp, t0 & 1, own, u, d);
         load_spinor<P>(in, g.Vh, par, t0 * g.S + k, own);
+        site_part(t0, own, acc);
     }
     for (int step = 0; step < g.nt; ++step) {
         const int t = t0 + step;
@@ -305,23 +321,18 @@ __global__ __launch_bounds__(256) void dw_march_kernel(Geom g, RhsTable tab, int
         __syncthreads();
         if (valid) {
             const int i = t * g.S + k;
-            int x[4], lex;
-            eo_coords(g, par, i, x, lex);
+            const int x0 = t;  // the time coordinate of the site
             // the site's forward t link serves the +t hop and the hand-over below
             cx<R> u0[6], d0;
             load_link<P>(links, dets, g.Vh, par, i, 0, u0, d0);
             // (2) the partner's -t hop at t+1; slot (t+1)&1 was read one step ago, before
-            //     this step's barrier. Done first, so that the lane's own spinor is dead once
-            //     the clover term has used it (the accumulator then starts from A psi and the
-            //     hops are added scaled by -1/2: one 12-complex array fewer live)
+            //     this step's barrier
             if (step + 1 < g.nt) push(t, (t + 1) & 1, own, u0, d0);
-            cx<R> acc[12];
-            clover54_apply<P>(clover, g.Vh, par, i, (R)g.cdiag, own, acc);
             {
                 // +t: U_0(x) times the projected neighbour from the partner
                 cx<R> h[6], w[6];
                 get6(hp, (t + 1) & 1, h);
-                const R f = (g.bc_t < 0 && x[0] == g.L[0] - 1) ? (R)0.5 : (R)-0.5;
+                const R f = (g.bc_t < 0 && x0 == g.L[0] - 1) ? (R)0.5 : (R)-0.5;
 #pragma unroll
                 for (int q = 0; q < 6; ++q) h[q] = scale(h[q], f);
                 su3_mul<R, false>(u0, d0, h, w);
@@ -332,10 +343,14 @@ __global__ __launch_bounds__(256) void dw_march_kernel(Geom g, RhsTable tab, int
                 for (int q = 0; q < 6; ++q) w[q] = scale(w[q], (R)-0.5);
                 expand_add<R, 0, SGB>(w, acc);
             }
-            march_site_hops<P, DAG, PIPE>(g, in, links, dets, par, i, x, lex, acc);
             store_spinor<P>(out, g.Vh, par, i, acc);
+            // (3) the next slice's clover term and spatial hops, on the spinors loaded in
+            //     this step
+            if (step + 1 < g.nt) {
 #pragma unroll
-            for (int q = 0; q < 12; ++q) own[q] = nxt[q];
+                for (int q = 0; q < 12; ++q) own[q] = nxt[q];
+                site_part(tn, own, acc);
+            }
         }
     }
 }
