@@ -142,8 +142,9 @@ def test_traffic_record_is_consistent_and_current():
         assert bench.measured_traffic(bench.PINNED_SHAPES["f64"]) is None
         return
     assert bench.measured_traffic(bench.PINNED_SHAPES["f64"]) == t["bytes_per_launch"]
-    # at least the compulsory stored bytes (1216 per site read, one spinor written)
-    assert t["bytes_per_launch"] >= (1216 + 192) * 2 ** 21
+    # at least the compulsory stored bytes (1040 per site read: spinor 192, four links of
+    # 12 reals and a determinant double, the 54-real clover; one spinor written)
+    assert t["read_bytes"] >= 1040 * 2 ** 21 and t["write_bytes"] >= 192 * 2 ** 21
 
 
 def test_operator_memory_comes_from_the_caller(lib):
