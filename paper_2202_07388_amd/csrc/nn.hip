@@ -706,11 +706,17 @@ __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, c
     };
     if constexpr (CIN == 8) {
         // The inputs of one path for this lane -- the neighbour spinors of its two channels
-        // as stored (bf16, widened when used) and the link -- in two stages: the loads of
-        // path p + 1 are issued before the work on path p, so a whole path's transport and
-        // mixing cover their latency. The stages alternate by name (no indexed arrays).
-        struct Stage {
+        // as stored (bf16, widened when used), the link and the path's weight block -- are
+        // loaded ahead of their use: the spinors two paths ahead (three stages), the link and
+        // the weights one path ahead (two stages), so the gathered spinors have two paths'
+        // transports and products to arrive in. Within one path the weights are issued
+        // first, the link next and the spinors last: loads complete in issue order, so the
+        // wait for the weights before the path's barrier leaves the link and spinor loads
+        // in flight. The stages rotate by name (no indexed arrays).
+        struct SpStage {
             u32x4 s0[3], s1[3];
+        };
+        struct LkStage {
             cx<float> u[6], d;
             float sg;
         };
@@ -720,11 +726,12 @@ __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, c
         // would become a wait for all loads in flight, the prefetched ones included
         const g_cu4* const c0 = (const g_cu4*)in[cg];
         const g_cu4* const c1 = (const g_cu4*)in[cg + 4];
-        auto fetch = [&](int p, Stage& S) {
+        // the spinors of path p: the lane's own site for p = 0, else the neighbour
+        auto fetch_sp = [&](int p, SpStage& S) {
             int j = i, pp = par;
-            S.sg = 1.f;
             if (p > 0) {
-                nn_path_setup(g, par, i, x, lex, p, links, dets, j, S.sg, S.u, S.d);
+                const int mu = (p - 1) >> 1;
+                j = ((((p - 1) & 1) == 0) ? lex_fwd(g, x, lex, mu) : lex_bwd(g, x, lex, mu)) >> 1;
                 pp = 1 - par;
             }
             const long b0 = chunk_at(g.Vh, 3, pp, 0, j);
@@ -734,11 +741,15 @@ __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, c
                 S.s1[k] = c1[b0 + (long)k * kSB];
             }
         };
+        // the link and boundary sign of path p (1..8)
+        auto fetch_lk = [&](int p, LkStage& L) {
+            int j;
+            nn_path_setup(g, par, i, x, lex, p, links, dets, j, L.sg, L.u, L.d);
+        };
         // the weight block of path p: each of the 256 lanes loads 32 contiguous bytes of it
-        // together with the spinor loads of that path, and stores them into the block's
-        // LDS buffer once the path before it is done (one workgroup barrier per path; the
-        // loads stay in registers meanwhile, in flight during the transport and the
-        // matrix-core step)
+        // and stores them into the block's LDS buffer once the path before it is done (one
+        // workgroup barrier per path; the loads stay in registers meanwhile, in flight
+        // during the transport and the matrix-core step)
         const int tid = threadIdx.x;
         auto load_w = [&](int p, u32x4 r[2]) {
             const g_cu4* src = (const g_cu4*)((const char*)Bl + (long)p * kWBlock) + 2 * tid;
@@ -750,34 +761,35 @@ __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, c
             dst[0] = r[0];
             dst[1] = r[1];
         };
-        // path p0 from stage `cur` while the loads of path p0 + 1 go into `nxt`; the wave
-        // writes and then reads only its own rows of the tile, so a wave-level sync orders
-        // them. Every lane issues the loads, the lanes of padded sites too (their site index is
-        // below the padded row length and their neighbours are those of site 0, so the
-        // loads stay in bounds; the data are not used): with the same loads in flight on
-        // every path through the code, the compiler waits for exactly the loads an
-        // instruction needs instead of all of them
-        auto path = [&](int p0, Stage& cur, Stage& nxt) {
+        // path p0 from the spinor stage sc and the link stage lc, while the weights and link
+        // of path p0 + 1 and the spinors of path p0 + 2 are loaded; the wave writes and then
+        // reads only its own rows of the tile, so a wave-level sync orders them. Every lane
+        // issues the loads, the lanes of padded sites too (their site index is below the
+        // padded row length and their neighbours are those of site 0, so the loads stay in
+        // bounds; the data are not used): with the same loads in flight on every path
+        // through the code, the compiler waits for exactly the loads an instruction needs
+        auto path = [&](int p0, const SpStage& sc, SpStage& sn2, const LkStage& lc, LkStage& ln) {
             u32x4 wn[2];
             if (p0 + 1 < kPaths) {
-                fetch(p0 + 1, nxt);
                 load_w(p0 + 1, wn);
+                fetch_lk(p0 + 1, ln);
             }
+            if (p0 + 2 < kPaths) fetch_sp(p0 + 2, sn2);
             if (!real) {
                 nn_put_rows<LS>(tile, sl, cg * 8, zero12);
                 nn_put_rows<LS>(tile, sl, (cg + 4) * 8, zero12);
             } else if (p0 == 0) {
-                nn_put_rows_raw<LS>(tile, sl, cg * 8, cur.s0);
-                nn_put_rows_raw<LS>(tile, sl, (cg + 4) * 8, cur.s1);
+                nn_put_rows_raw<LS>(tile, sl, cg * 8, sc.s0);
+                nn_put_rows_raw<LS>(tile, sl, (cg + 4) * 8, sc.s1);
             } else {
                 const bool fwd = ((p0 - 1) & 1) == 0;
                 cx<float> w[12], m[9];
                 LinkBF lb;
-                nn_link_matrix(cur.u, cur.d, cur.sg, m);
+                nn_link_matrix(lc.u, lc.d, lc.sg, m);
                 nn_link_bf16(fwd, m, lb);
-                nn_transport_dot2(lb, cur.s0, w);
+                nn_transport_dot2(lb, sc.s0, w);
                 nn_put_rows<LS>(tile, sl, cg * 8, w);
-                nn_transport_dot2(lb, cur.s1, w);
+                nn_transport_dot2(lb, sc.s1, w);
                 nn_put_rows<LS>(tile, sl, (cg + 4) * 8, w);
             }
             wave_sync();  // the wave's own rows, by its other lanes
@@ -791,22 +803,30 @@ __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, c
                 __syncthreads();
             }
         };
-        Stage SA, SB;
+        SpStage S0, S1, S2;
+        LkStage LA, LB;  // path 0 has no link: LA first holds path 2's
         {
             u32x4 w0[2];
             load_w(0, w0);
-            fetch(0, SA);
+            fetch_sp(0, S0);
+            fetch_sp(1, S1);
             store_w(0, w0);
         }
         __syncthreads();
-        // unrolled for the same reason: the stages alternate by name, and the last path
-        // issues no loads
+        // unrolled, so that the stage of each path is fixed at compile time; the last
+        // two paths issue fewer loads
 #pragma unroll
         for (int p0 = 0; p0 < kPaths; ++p0) {
-            if (p0 & 1)
-                path(p0, SB, SA);
-            else
-                path(p0, SA, SB);
+            const int r3 = p0 % 3;
+            if (p0 & 1) {
+                if (r3 == 0) path(p0, S0, S2, LB, LA);
+                else if (r3 == 1) path(p0, S1, S0, LB, LA);
+                else path(p0, S2, S1, LB, LA);
+            } else {
+                if (r3 == 0) path(p0, S0, S2, LA, LB);
+                else if (r3 == 1) path(p0, S1, S0, LA, LB);
+                else path(p0, S2, S1, LA, LB);
+            }
         }
     } else {
         // paths wave, wave + 4, wave + 8 of the single channel, one batch
