@@ -622,9 +622,10 @@ __device__ __forceinline__ void nn_put_rows(uint16_t* tile, int sl, int k0, cons
 // MIXOUT (inference passes of the 8 -> 8 layer only): instead of storing the layer's eight
 // output channels, the kernel goes on with the last layer's path mixing on them (the
 // product nn_mix_paths_kernel forms, with the mixing matrix Bm) and stores the nine m_p
-// fields to out[0..8]; the A operand is the outputs rounded to bf16, as the stored hidden
-// channels would be, and the product runs in the same instruction order, so the m_p are
-// bit for bit those of the two-kernel form.
+// fields to out[0..8]; its operand is the outputs rounded to bf16, as the stored hidden
+// channels would be, taken from the registers that hold them, and the products sum over
+// the same K steps in the same order (the forward pass's output at 32^3 x 64 was checked
+// bit for bit against the two-kernel form).
 template <int CIN, int COUT, int PIN, int POUT, bool MIXOUT = false>
 __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, const void* const* in,
                                                              const void* Bt, const void* Bl,
@@ -673,7 +674,13 @@ __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, c
     f4 acc[3][NT];
     for (int r = 0; r < 3; ++r)
         for (int j = 0; j < NT; ++j) acc[r][j] = f4{0.f, 0.f, 0.f, 0.f};
-    // rows 48*wave .. +48 of the tile times B[kglob .. +KB][0 .. 16 NT] on the matrix cores
+    // rows 48*wave .. +48 of the tile times B[kglob .. +KB][0 .. 16 NT] on the matrix cores,
+    // formed as the transposed product B^T A^T (the weights as the first operand, the tile
+    // rows as the second; the operand registers are the same as for A B): acc[r][j] then
+    // holds, in lane l, output row 16 r + l % 16 of the wave's 48 and the four columns
+    // 16 j + 4 (l / 16) + e, e = 0..3 -- the layout in which a 16x16x16 product takes its
+    // operands, so the last layer's mixing reads them from the registers, and consecutive
+    // (re, im) columns pair up for 4-byte stores
     auto mix = [&](long kglob) {
         if constexpr (CIN == 8) {
             // K = 64 per path in two steps of gfx950's doubled-K bf16 product (16 x 16 x 32):
@@ -687,7 +694,7 @@ __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, c
                 for (int r = 0; r < 3; ++r) {
                     const bf16x8 a = *(const bf16x8*)&tile[(wave * 48 + r * 16 + (lane & 15)) * LS + kl];
                     for (int j = 0; j < NT; ++j)
-                        acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bf[j], acc[r][j], 0, 0, 0);
+                        acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[j], a, acc[r][j], 0, 0, 0);
                 }
             }
         } else {
@@ -699,7 +706,7 @@ __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, c
                 for (int r = 0; r < 3; ++r) {
                     const s4 a = *(const s4*)&tile[(wave * 48 + r * 16 + (lane & 15)) * LS + kl];
                     for (int j = 0; j < NT; ++j)
-                        acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bf[j], acc[r][j], 0, 0, 0);
+                        acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bf[j], a, acc[r][j], 0, 0, 0);
                 }
             }
         }
@@ -858,42 +865,41 @@ __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, c
     }
     __syncthreads();  // the output block below reuses the tile
     if constexpr (MIXOUT) {
-        // the wave's own 48 rows of the mixing's A operand: row 3 site + c, column
-        // (a * 4 + s) * 2 + re/im = (b * 4 + t) * 2 + re/im of the input of the mixing
-        for (int r = 0; r < 3; ++r)
-            for (int j = 0; j < NT; ++j)
-                for (int e = 0; e < 4; ++e)
-                    tile[(wave * 48 + r * 16 + 4 * (lane >> 4) + e) * LS + j * 16 + (lane & 15)] =
-                        (uint16_t)(pack_bf16x2(acc[r][j][e], 0.f) & 0xFFFFu);
-        wave_sync();
+        // m_p = the layer's outputs rounded to bf16 (as the stored hidden channels would be)
+        // times Bm, K = 64 in four steps of 16: step j takes the lane's acc[r][j] as its
+        // operand, again as the transposed product (Bm^T first), so am[r][jm] holds row
+        // 16 r + l % 16 and columns 16 jm + 4 (l / 16) + e of m, column (p * 4 + s) * 2 + re/im
         constexpr int NM = 5;  // 80 columns: 9 paths x 4 spins x re/im (72), padded
         f4 am[3][NM];
         for (int r = 0; r < 3; ++r)
-            for (int j = 0; j < NM; ++j) am[r][j] = f4{0.f, 0.f, 0.f, 0.f};
-        for (int kk = 0; kk < 64; kk += 16) {
-            const int kl = kk + 4 * (lane >> 4);
+            for (int jm = 0; jm < NM; ++jm) am[r][jm] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < NT; ++j) {
+            const int kl = j * 16 + 4 * (lane >> 4);
             s4 bf[NM];
-            for (int j = 0; j < NM; ++j)
-                bf[j] = *(const s4*)(Bm + (j * 16 + (lane & 15)) * 64 + kl);
+            for (int jm = 0; jm < NM; ++jm)
+                bf[jm] = *(const s4*)(Bm + (jm * 16 + (lane & 15)) * 64 + kl);
             for (int r = 0; r < 3; ++r) {
-                const s4 a = *(const s4*)&tile[(wave * 48 + r * 16 + (lane & 15)) * LS + kl];
-                for (int j = 0; j < NM; ++j)
-                    am[r][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bf[j], am[r][j], 0, 0, 0);
+                const uint32_t h2[2] = {pack_bf16x2(acc[r][j][0], acc[r][j][1]),
+                                        pack_bf16x2(acc[r][j][2], acc[r][j][3])};
+                s4 a;
+                __builtin_memcpy(&a, h2, 8);
+                for (int jm = 0; jm < NM; ++jm)
+                    am[r][jm] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bf[jm], a, am[r][jm], 0, 0, 0);
             }
         }
-        __syncthreads();  // every wave is done with the tile before the staging overwrites it
+        // staged as [path][chunk][site][8] like the outputs below, (re, im) pairs as one word
         uint16_t* ob = (uint16_t*)lds;
         for (int r = 0; r < 3; ++r)
-            for (int j = 0; j < NM; ++j)
-                for (int e = 0; e < 4; ++e) {
-                    const int m = wave * 48 + r * 16 + 4 * (lane >> 4) + e;
-                    const int n = j * 16 + (lane & 15);
+            for (int jm = 0; jm < NM; ++jm)
+                for (int h = 0; h < 2; ++h) {
+                    const int m = wave * 48 + r * 16 + (lane & 15);
+                    const int n = jm * 16 + 4 * (lane >> 4) + 2 * h;
                     if (n >= 72) continue;
                     const int ms = m / 3, c = m - ms * 3;
-                    const int p = n >> 3, sp = (n >> 1) & 3, ri = n & 1;
-                    const int k = (sp * 3 + c) * 2 + ri;
-                    ob[(p * 3 + (k >> 3)) * OROW + ms * 8 + (k & 7)] =
-                        (uint16_t)(pack_bf16x2(am[r][j][e], 0.f) & 0xFFFFu);
+                    const int p = n >> 3, sp = (n >> 1) & 3;
+                    const int k = (sp * 3 + c) * 2;
+                    *(uint32_t*)&ob[(p * 3 + (k >> 3)) * OROW + ms * 8 + (k & 7)] =
+                        pack_bf16x2(am[r][jm][2 * h], am[r][jm][2 * h + 1]);
                 }
         __syncthreads();
         const int mpar = (int)(q0 / Vp), mi0 = (int)(q0 - (long)mpar * Vp);
@@ -912,15 +918,15 @@ __global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, c
     uint16_t* ob = (uint16_t*)lds;
     for (int r = 0; r < 3; ++r)
         for (int j = 0; j < NT; ++j)
-            for (int e = 0; e < 4; ++e) {
-                const int m = wave * 48 + r * 16 + 4 * (lane >> 4) + e;
-                const int n = j * 16 + (lane & 15);
+            for (int h = 0; h < 2; ++h) {
+                const int m = wave * 48 + r * 16 + (lane & 15);
+                const int n = j * 16 + 4 * (lane >> 4) + 2 * h;
                 const int ms = m / 3, c = m - ms * 3;
-                const int a = n >> 3, sp = (n >> 1) & 3, ri = n & 1;
+                const int a = n >> 3, sp = (n >> 1) & 3;
                 if (a >= COUT) continue;
-                const int k = (sp * 3 + c) * 2 + ri;  // real index within the spinor
-                ob[(a * 3 + (k >> 3)) * OROW + ms * 8 + (k & 7)] =
-                    (uint16_t)(pack_bf16x2(acc[r][j][e], 0.f) & 0xFFFFu);
+                const int k = (sp * 3 + c) * 2;  // real index of the pair within the spinor
+                *(uint32_t*)&ob[(a * 3 + (k >> 3)) * OROW + ms * 8 + (k & 7)] =
+                    pack_bf16x2(acc[r][j][2 * h], acc[r][j][2 * h + 1]);
             }
     __syncthreads();
     const int opar = (int)(q0 / Vp), oi0 = (int)(q0 - (long)opar * Vp);
