@@ -626,12 +626,14 @@ __device__ __forceinline__ void nn_put_rows(uint16_t* tile, int sl, int k0, cons
 // channels would be, taken from the registers that hold them, and the products sum over
 // the same K steps in the same order (the forward pass's output at 32^3 x 64 was checked
 // bit for bit against the two-kernel form).
+// Occupancy: the one-channel layer is held to 128 registers, four waves per SIMD, where its
+// gathers (two or three paths per wave, one after the other) hide behind the other waves
+// (the compiler's own choice, 132, allows three); the eight-channel layers keep theirs.
 template <int CIN, int COUT, int PIN, int POUT, bool MIXOUT = false>
-__global__ __launch_bounds__(256) void nn_layer_fused_kernel(Geom g, int Kpad, const void* const* in,
-                                                             const void* Bt, const void* Bl,
-                                                             void* const* out, const void* links,
-                                                             const void* dets,
-                                                             const uint16_t* Bm = nullptr)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CIN == 1 ? 4 : 1)))
+void nn_layer_fused_kernel(Geom g, int Kpad, const void* const* in, const void* Bt,
+                           const void* Bl, void* const* out, const void* links,
+                           const void* dets, const uint16_t* Bm = nullptr)
 {
     constexpr int PB = CIN == 1 ? kPaths : 1;          // paths per batch
     constexpr int KB = (PB * CIN * 8 + 15) & ~15;      // columns per batch (80 or 64)
