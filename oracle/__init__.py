@@ -21,9 +21,11 @@ Contents, each written from its definition (stencil loops live in ``oracle.c``):
 * ``nn_*``: a gauge-covariant linear network of parallel-transport layers, forward and
   analytic adjoint (not from the paper).
 
-Parity status: see each function's docstring; the only unpinned conventions are the
-U(1) charge in the clover term (q = 1, single c_sw for the combined U(3) link) and the
-iteration counts of mixed-precision and learned solves.
+Parity status: see each function's docstring; every function here is pinned by the CPU
+tests. The U(1) charge in the clover term (q = 1, a single c_sw for the combined U(3)
+link) is a reading of the paper, which fixes neither; its arithmetic is pinned by the
+constant abelian flux. Mixed-precision and learned solves have no counterpart here (their
+solutions are judged by the FP64 true residual of this operator).
 """
 from __future__ import annotations
 
