@@ -428,13 +428,15 @@ __global__ __launch_bounds__(256) void nn_pack_g_kernel(Geom g, int Cout, int Np
 //
 // The production forward pass (bf16 operands) fuses transport and mixing: a workgroup
 // owns 64 consecutive sites q (192 rows (q, c)); for each batch of paths (one path when
-// Cin = 8, all nine when Cin = 1) its lanes transport the input channels into an LDS tile
-// of the rows' columns for that batch, then the four wavefronts multiply the tile by the
-// batch's rows of B on the matrix cores, 48 rows each, accumulating in FP32. Columns are
-// visited in the same order as by the unfused kernels, so both give the same sums; the
-// difference is that A never goes to HBM. A lane always transports for the same site
-// (lane mod 64): its coordinates are computed once, and with Cin = 8 one link load serves
-// the lane's two channels.
+// Cin = 8, all nine when Cin = 1) its lanes transport the input channels into the rows'
+// columns for that batch, then the four wavefronts multiply them by the batch's rows of B
+// on the matrix cores, 48 rows each, accumulating in FP32 -- with Cin = 1 through an LDS
+// tile (the waves share the paths), with Cin = 8 straight from the registers the
+// transports leave (each wave transports the 16 sites whose rows it multiplies). Columns
+// are visited in the same order as by the unfused kernels, so both give the same sums; the
+// difference is that A never goes to HBM. A lane always transports for the same site: its
+// coordinates are computed once, and with Cin = 8 one link load serves the lane's two
+// channels.
 
 // neighbour index, boundary sign and link of path p (1..8) at site (par, i)
 __device__ __forceinline__ void nn_path_setup(const Geom& g, int par, int i, const int x[4], int lex,
@@ -569,15 +571,6 @@ constexpr int tile_stride(int kb)
     return ls;
 }
 
-// orders the LDS accesses of one wavefront's lanes (writes before, reads after), without
-// waiting for the other wavefronts of the workgroup
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // first row q (site) of the 64-site block of this workgroup in the forward kernels, whose
 // grid is one workgroup per block of either parity: blocks of the two parities alternate
 // (the even and odd sites of one index range are lexicographic neighbours along x3), and
@@ -587,22 +580,6 @@ __device__ __forceinline__ long nn_block_q0(int Vp)
 {
     const int w = xcd_tile(blockIdx.x, gridDim.x);
     return (long)(w & 1) * Vp + (long)(w >> 1) * 64;
-}
-
-// the same rows straight from a spinor stored as bf16 pairs (the identity path)
-template <int LS>
-__device__ __forceinline__ void nn_put_rows_raw(uint16_t* tile, int sl, int k0, const u32x4 raw[3])
-{
-    uint32_t v[12];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        v[4 * k] = raw[k].x;
-        v[4 * k + 1] = raw[k].y;
-        v[4 * k + 2] = raw[k].z;
-        v[4 * k + 3] = raw[k].w;
-    }
-    for (int c = 0; c < 3; ++c)
-        *(uint4*)&tile[(sl * 3 + c) * LS + k0] = uint4{v[c], v[3 + c], v[6 + c], v[9 + c]};
 }
 
 // the three rows (site sl, colour c) of one (path, channel) group, as bf16, into the tile
@@ -616,6 +593,34 @@ __device__ __forceinline__ void nn_put_rows(uint16_t* tile, int sl, int k0, cons
         r.z = pack_bf16x2(w[6 + c].re, w[6 + c].im);
         r.w = pack_bf16x2(w[9 + c].re, w[9 + c].im);
         *(uint4*)&tile[(sl * 3 + c) * LS + k0] = r;
+    }
+}
+
+// the same rows as the matrix-core operands of colours 0..2: (re, im) of spins 0..3 as bf16
+// (the eight columns of one channel that a lane supplies for its site)
+__device__ __forceinline__ void nn_rows(const cx<float> w[12], bf16x8 T[3])
+{
+    for (int c = 0; c < 3; ++c) {
+        const uint32_t v[4] = {pack_bf16x2(w[c].re, w[c].im), pack_bf16x2(w[3 + c].re, w[3 + c].im),
+                               pack_bf16x2(w[6 + c].re, w[6 + c].im), pack_bf16x2(w[9 + c].re, w[9 + c].im)};
+        __builtin_memcpy(&T[c], v, 16);
+    }
+}
+
+// the same straight from a spinor stored as bf16 pairs (the identity path)
+__device__ __forceinline__ void nn_rows_raw(const u32x4 raw[3], bf16x8 T[3])
+{
+    uint32_t v[12];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        v[4 * k] = raw[k].x;
+        v[4 * k + 1] = raw[k].y;
+        v[4 * k + 2] = raw[k].z;
+        v[4 * k + 3] = raw[k].w;
+    }
+    for (int c = 0; c < 3; ++c) {
+        const uint32_t t[4] = {v[c], v[3 + c], v[6 + c], v[9 + c]};
+        __builtin_memcpy(&T[c], t, 16);
     }
 }
 
@@ -641,10 +646,11 @@ void nn_layer_fused_kernel(Geom g, int Kpad, const void* const* in, const void* 
     constexpr int NT = COUT * 8 >= 16 ? COUT * 8 / 16 : 1;  // 16-column tiles of N
     static_assert(CIN == 1 || CIN == 8, "channel counts of the network");
     static_assert(CIN == 1 || (KB == 64 && NT == 4), "the LDS weight image is a 64 x 64 block");
-    // LDS: the transported tile during the batches (with Cin = 8 followed by two 8 KiB
-    // buffers for the weight blocks of the current and the next path), then the output
-    // block (COUT channels x 24 reals x 64 sites, bf16)
-    constexpr int TILE_B = 192 * LS * 2, W_B = CIN == 8 ? 2 * kWBlock : 0;
+    // LDS: Cin = 1, the transported tile of the batch; Cin = 8, two 8 KiB buffers for the
+    // weight blocks of the current and the next path (its transports go to the matrix
+    // cores from the registers); then the output block (COUT channels x 24 reals x 64
+    // sites, bf16)
+    constexpr int TILE_B = CIN == 1 ? 192 * LS * 2 : 0, W_B = CIN == 8 ? 2 * kWBlock : 0;
     // output staging in bf16: one row per (channel, 16-byte chunk) of 64 sites x 8 halves,
     // padded by one chunk so that consecutive rows start 4 banks apart
     static_assert(POUT == BF16S, "the layers' outputs are bf16 hidden channels");
@@ -658,12 +664,26 @@ void nn_layer_fused_kernel(Geom g, int Kpad, const void* const* in, const void* 
     // Cin = 8: the weight block of path p is in buffer p & 1, as [k/8][n][k%8] (bf16)
     uint16_t* const wbuf = (uint16_t*)(lds + TILE_B);
     const uint16_t* wb = wbuf;
+    // the site (0..63) and colour of output row 16 r + i (i < 16) of a wave's 48 rows:
+    // Cin = 1, the tile's rows 3 site + colour; Cin = 8, colour-major (row tile r is colour
+    // r of the wave's 16 sites), the order in which its transports reach the matrix cores
+    auto row_site = [&](int r, int i, int& site, int& c) {
+        if constexpr (CIN == 8) {
+            site = wave * 16 + i;
+            c = r;
+        } else {
+            const int m = wave * 48 + r * 16 + i;
+            site = m / 3;
+            c = m - site * 3;
+        }
+    };
     const int Vp = padded(g.Vh);
     const long q0 = nn_block_q0(Vp);
-    // this lane's transport site: Cin = 8, the wave's own 16 sites (the rows its matrix-core
-    // products read), four lanes per site, channels cg and cg + 4 per lane, so a wave's
-    // transport and products need no other wave (the workgroup meets once per path, for
-    // the shared weight block); Cin = 1, all 64 sites, paths split over the waves
+    // this lane's transport site: Cin = 8, the wave's own 16 sites, four lanes per site,
+    // channels cg and cg + 4 per lane, so that a lane's transports are the very operand
+    // registers it supplies to the wave's products (no LDS between them, and the workgroup
+    // meets once per path only, for the shared weight block); Cin = 1, all 64 sites, paths
+    // split over the waves
     const int sl = CIN == 8 ? wave * 16 + (lane & 15) : lane;
     const int cg = lane >> 4;
     const long qs = q0 + sl;
@@ -676,40 +696,23 @@ void nn_layer_fused_kernel(Geom g, int Kpad, const void* const* in, const void* 
     f4 acc[3][NT];
     for (int r = 0; r < 3; ++r)
         for (int j = 0; j < NT; ++j) acc[r][j] = f4{0.f, 0.f, 0.f, 0.f};
-    // rows 48*wave .. +48 of the tile times B[kglob .. +KB][0 .. 16 NT] on the matrix cores,
-    // formed as the transposed product B^T A^T (the weights as the first operand, the tile
-    // rows as the second; the operand registers are the same as for A B): acc[r][j] then
-    // holds, in lane l, output row 16 r + l % 16 of the wave's 48 and the four columns
-    // 16 j + 4 (l / 16) + e, e = 0..3 -- the layout in which a 16x16x16 product takes its
-    // operands, so the last layer's mixing reads them from the registers, and consecutive
-    // (re, im) columns pair up for 4-byte stores
-    auto mix = [&](long kglob) {
-        if constexpr (CIN == 8) {
-            // K = 64 per path in two steps of gfx950's doubled-K bf16 product (16 x 16 x 32):
-            // each lane reads 8 consecutive k of its row of the tile and of its column of the
-            // path's weight block ([k/8][n][k%8] in LDS)
-            for (int kk = 0; kk < KB; kk += 32) {
-                const int kl = kk + 8 * (lane >> 4);
-                bf16x8 bf[NT];
+    // The products are formed transposed, B^T A^T (the weights as the first operand, the
+    // transported rows as the second; the operand registers are the same as for A B):
+    // acc[r][j] then holds, in lane l, output row 16 r + l % 16 of the wave's 48 and the
+    // four columns 16 j + 4 (l / 16) + e, e = 0..3 -- the layout in which a 16x16x16
+    // product takes its operands, so the last layer's mixing reads them from the
+    // registers, and consecutive (re, im) columns pair up for 4-byte stores.
+    // Cin = 1: rows 48*wave .. +48 of the tile times B[0 .. KB][0 .. 16 NT]
+    auto mix_tile = [&]() {
+        for (int kk = 0; kk < KB; kk += 16) {
+            const int kl = kk + 4 * (lane >> 4);
+            s4 bf[NT];
+            for (int j = 0; j < NT; ++j)
+                bf[j] = *(const s4*)((const uint16_t*)Bt + (long)(j * 16 + (lane & 15)) * Kpad + kl);
+            for (int r = 0; r < 3; ++r) {
+                const s4 a = *(const s4*)&tile[(wave * 48 + r * 16 + (lane & 15)) * LS + kl];
                 for (int j = 0; j < NT; ++j)
-                    bf[j] = *(const bf16x8*)&wb[((kl >> 3) * 64 + j * 16 + (lane & 15)) * 8];
-                for (int r = 0; r < 3; ++r) {
-                    const bf16x8 a = *(const bf16x8*)&tile[(wave * 48 + r * 16 + (lane & 15)) * LS + kl];
-                    for (int j = 0; j < NT; ++j)
-                        acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[j], a, acc[r][j], 0, 0, 0);
-                }
-            }
-        } else {
-            for (int kk = 0; kk < KB; kk += 16) {
-                const int kl = kk + 4 * (lane >> 4);
-                s4 bf[NT];
-                for (int j = 0; j < NT; ++j)
-                    bf[j] = *(const s4*)((const uint16_t*)Bt + (long)(j * 16 + (lane & 15)) * Kpad + kglob + kl);
-                for (int r = 0; r < 3; ++r) {
-                    const s4 a = *(const s4*)&tile[(wave * 48 + r * 16 + (lane & 15)) * LS + kl];
-                    for (int j = 0; j < NT; ++j)
-                        acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bf[j], a, acc[r][j], 0, 0, 0);
-                }
+                    acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bf[j], a, acc[r][j], 0, 0, 0);
             }
         }
     };
@@ -784,12 +787,15 @@ void nn_layer_fused_kernel(Geom g, int Kpad, const void* const* in, const void* 
                 fetch_lk(p0 + 1, ln);
             }
             if (p0 + 2 < kPaths) fetch_sp(p0 + 2, sn2);
+            // the matrix cores' second operand for row tile (colour) c: this lane's site,
+            // channel cg (T0) or cg + 4 (T1), the four spins' (re, im) as bf16 -- exactly
+            // the 8 consecutive columns of its row that a lane supplies in the product
+            bf16x8 T0[3], T1[3];
             if (!real) {
-                nn_put_rows<LS>(tile, sl, cg * 8, zero12);
-                nn_put_rows<LS>(tile, sl, (cg + 4) * 8, zero12);
+                for (int c = 0; c < 3; ++c) T0[c] = T1[c] = bf16x8{};
             } else if (p0 == 0) {
-                nn_put_rows_raw<LS>(tile, sl, cg * 8, sc.s0);
-                nn_put_rows_raw<LS>(tile, sl, (cg + 4) * 8, sc.s1);
+                nn_rows_raw(sc.s0, T0);
+                nn_rows_raw(sc.s1, T1);
             } else {
                 const bool fwd = ((p0 - 1) & 1) == 0;
                 cx<float> w[12], m[9];
@@ -797,13 +803,24 @@ void nn_layer_fused_kernel(Geom g, int Kpad, const void* const* in, const void* 
                 nn_link_matrix(lc.u, lc.d, lc.sg, m);
                 nn_link_bf16(fwd, m, lb);
                 nn_transport_dot2(lb, sc.s0, w);
-                nn_put_rows<LS>(tile, sl, cg * 8, w);
+                nn_rows(w, T0);
                 nn_transport_dot2(lb, sc.s1, w);
-                nn_put_rows<LS>(tile, sl, (cg + 4) * 8, w);
+                nn_rows(w, T1);
             }
-            wave_sync();  // the wave's own rows, by its other lanes
             wb = wbuf + (p0 & 1) * (kWBlock / 2);
-            mix((long)p0 * 64);
+            // K = 64 per path in two steps of gfx950's doubled-K bf16 product (16 x 16 x 32),
+            // channels 0..3 then 4..7; each lane reads 8 consecutive k of its column of the
+            // path's weight block ([k/8][n][k%8] in LDS)
+            for (int h = 0; h < 2; ++h) {
+                const int kl = 32 * h + 8 * (lane >> 4);
+                bf16x8 bf[NT];
+                for (int j = 0; j < NT; ++j)
+                    bf[j] = *(const bf16x8*)&wb[((kl >> 3) * 64 + j * 16 + (lane & 15)) * 8];
+                for (int r = 0; r < 3; ++r)
+                    for (int j = 0; j < NT; ++j)
+                        acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[j], h ? T1[r] : T0[r],
+                                                                           acc[r][j], 0, 0, 0);
+            }
             if (p0 + 1 < kPaths) {
                 // the next block into the other buffer (last read by every wave before the
                 // previous barrier); the barrier also orders the wave's tile reads above
@@ -863,7 +880,7 @@ void nn_layer_fused_kernel(Geom g, int Kpad, const void* const* in, const void* 
         for (int rr = threadIdx.x; rr < 192; rr += 256)
             *(uint4*)&tile[rr * LS + kPaths * 8] = uint4{0u, 0u, 0u, 0u};
         __syncthreads();  // the waves filled each other's rows
-        mix(0);
+        mix_tile();
     }
     __syncthreads();  // the output block below reuses the tile
     if constexpr (MIXOUT) {
@@ -894,10 +911,10 @@ void nn_layer_fused_kernel(Geom g, int Kpad, const void* const* in, const void* 
         for (int r = 0; r < 3; ++r)
             for (int jm = 0; jm < NM; ++jm)
                 for (int h = 0; h < 2; ++h) {
-                    const int m = wave * 48 + r * 16 + (lane & 15);
+                    int ms, c;
+                    row_site(r, lane & 15, ms, c);
                     const int n = jm * 16 + 4 * (lane >> 4) + 2 * h;
                     if (n >= 72) continue;
-                    const int ms = m / 3, c = m - ms * 3;
                     const int p = n >> 3, sp = (n >> 1) & 3;
                     const int k = (sp * 3 + c) * 2;
                     *(uint32_t*)&ob[(p * 3 + (k >> 3)) * OROW + ms * 8 + (k & 7)] =
@@ -921,9 +938,9 @@ void nn_layer_fused_kernel(Geom g, int Kpad, const void* const* in, const void* 
     for (int r = 0; r < 3; ++r)
         for (int j = 0; j < NT; ++j)
             for (int h = 0; h < 2; ++h) {
-                const int m = wave * 48 + r * 16 + (lane & 15);
+                int ms, c;
+                row_site(r, lane & 15, ms, c);
                 const int n = j * 16 + 4 * (lane >> 4) + 2 * h;
-                const int ms = m / 3, c = m - ms * 3;
                 const int a = n >> 3, sp = (n >> 1) & 3;
                 if (a >= COUT) continue;
                 const int k = (sp * 3 + c) * 2;  // real index of the pair within the spinor
