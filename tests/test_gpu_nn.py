@@ -257,3 +257,48 @@ def test_random_weights_16x8c3(net16, f32, tol, gtol):
     for l in range(3):
         assert rel(got_w[l], grads[l]) <= gtol, (l, rel(got_w[l], grads[l]))
     assert rel(gop.unpack(gi).cpu().numpy(), 2.0 * gin) <= gtol
+
+
+@pytest.mark.parametrize("kind", ["error", "dnorm"])
+def test_train_step_loss_and_first_adam_step(kind):
+    """One training step against the oracle: the returned batch loss (before the update)
+    is the mean over the pairs of |N(r) - e|^2 / |e|^2 ("error") or |D(N(r) - e)|^2 /
+    |D e|^2 ("dnorm") with the oracle's network and operator, within the bf16 mixing's
+    error; and the first Adam step from a zero state moves every weight by lr against the
+    sign of its gradient (bias-corrected m / sqrt(v) = g / |g| at step 1), checked on the
+    components whose oracle gradient is large enough for the bf16 gradient's sign to be
+    certain."""
+    import torch
+    dims = (4, 4, 4, 4)
+    gop, oop, _, _ = make_pair(dims, -0.05, 1.7, 0.3, seed=71)
+    W = oracle.nn_identity_weights(seed=5, scale=0.3)
+    rs = [syn.gaussian_spinor(dims, 72 + k) for k in range(2)]
+    es = [syn.gaussian_spinor(dims, 82 + k) for k in range(2)]
+    want, grad = 0.0, None
+    for r, e in zip(rs, es):
+        out, acts = oracle.nn_forward(oop, W, r)
+        d = out - e
+        if kind == "error":
+            den = np.vdot(e, e).real
+            L, g = np.vdot(d, d).real / den, d / den
+        else:
+            Dd, De = oop.dw(d), oop.dw(e)
+            den = np.vdot(De, De).real
+            L, g = np.vdot(Dd, Dd).real / den, oop.dw_dag(Dd) / den
+        want += L / len(rs)
+        gl, _ = oracle.nn_backward(oop, W, acts, g)
+        grad = gl if grad is None else [a + b for a, b in zip(grad, gl)]
+    w = qdw.nn_weights_tensor(W)
+    w0 = w.detach().cpu().numpy().copy()
+    adam = torch.zeros(4 * qdw.nn_weight_count(), dtype=torch.float32, device=w.device)
+    lr = 1e-2
+    got = qdw.nn_train_step(gop, w, adam, 1, lr, [gop.pack(r) for r in rs],
+                            [gop.pack(e) for e in es], "f64", kind)
+    assert abs(got - want) <= 5e-2 * want, (got, want)
+    delta = w.detach().cpu().numpy().astype(np.float64) - w0
+    gflat = np.concatenate([x.reshape(-1) for x in grad])
+    gri = np.stack([gflat.real, gflat.imag], axis=-1).reshape(-1)
+    sure = np.abs(gri) > 0.05 * np.abs(gri).max()
+    assert sure.sum() >= 100
+    assert np.abs(delta[sure] + lr * np.sign(gri[sure])).max() <= 1e-3 * lr
+    assert np.abs(delta).max() <= lr * (1 + 1e-3)

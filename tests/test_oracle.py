@@ -579,6 +579,21 @@ def test_nn_identity_init(opn):
     assert np.array_equal(out, r)
 
 
+def test_nn_loss_with_identity_network(opn):
+    """With the identity network (N(r) = r, pinned above) the loss is the relative squared
+    distance: 0 for e = r, exactly 4 for e = -r (N(r) - e = 2 r), and |r - e|^2 / |e|^2 in
+    general, with dL/d conj(out) = (r - e) / |e|^2."""
+    W = oracle.nn_identity_weights()
+    r = syn.gaussian_spinor(DN, 10)
+    e = syn.gaussian_spinor(DN, 11)
+    assert oracle.nn_loss(opn, W, r, r)[0] == 0.0
+    assert abs(oracle.nn_loss(opn, W, r, -r)[0] - 4.0) < 1e-14
+    L, g, _ = oracle.nn_loss(opn, W, r, e)
+    ne2 = np.linalg.norm(e.reshape(-1)) ** 2
+    assert abs(L - np.linalg.norm((r - e).reshape(-1)) ** 2 / ne2) < 1e-14 * L
+    assert np.abs(g - (r - e) / ne2).max() < 1e-15
+
+
 def test_nn_transport_adjoint_pairs(opn):
     a = syn.gaussian_spinor(DN, 2)
     b = syn.gaussian_spinor(DN, 3)
