@@ -823,8 +823,8 @@ void nn_layer_fused_kernel(Geom g, int Kpad, const void* const* in, const void* 
             }
             if (p0 + 1 < kPaths) {
                 // the next block into the other buffer (last read by every wave before the
-                // previous barrier); the barrier also orders the wave's tile reads above
-                // before its rewrite by the next path
+                // previous barrier); the barrier also keeps every wave's reads of this path's
+                // block ahead of its rewrite at the end of the next path
                 store_w(p0 + 1, wn);
                 __syncthreads();
             }
