@@ -130,6 +130,43 @@ def train(op: "qdw.Op", rhos, errs, store: str, epochs: int, batch: int, lr: flo
     return w, losses
 
 
+STATE_FORMAT = "qdw-nn-1-8-8-1"
+
+
+def save_state(path: str, weights, adam=None, step: int = 0, meta=None) -> None:
+    """Write the network's weights (the library's FP32 interleaved layout) and, to resume
+    training, the Adam moments and step count to a safetensors file (tensors and string
+    metadata only: loading it runs no code from the file)."""
+    from safetensors.torch import save_file
+    tensors = {"weights": weights.detach().to("cpu").contiguous()}
+    if adam is not None:
+        tensors["adam"] = adam.detach().to("cpu").contiguous()
+    md = {"format": STATE_FORMAT, "step": str(int(step))}
+    md.update({str(k): str(v) for k, v in (meta or {}).items()})
+    save_file(tensors, path, metadata=md)
+
+
+def load_state(path: str, device=None):
+    """Read what save_state wrote: (weights, adam or None, step, metadata), the tensors on
+    `device` (CPU if None). Refuses a file of another format or with tensors of the wrong
+    size for the 1-8-8-1 network."""
+    from safetensors import safe_open
+    with safe_open(path, framework="pt", device="cpu") as f:
+        md = dict(f.metadata() or {})
+        if md.get("format") != STATE_FORMAT:
+            raise ValueError("%s: not a network state file (format %r)" % (path, md.get("format")))
+        keys = set(f.keys())
+        w = f.get_tensor("weights")
+        adam = f.get_tensor("adam") if "adam" in keys else None
+    n = qdw.nn_weight_count()
+    if w.numel() != 2 * n or (adam is not None and adam.numel() != 4 * n):
+        raise ValueError("%s: tensor sizes do not match the 1-8-8-1 network" % path)
+    if device is not None:
+        w = w.to(device)
+        adam = adam.to(device) if adam is not None else None
+    return w, adam, int(md.get("step", "0")), md
+
+
 def _time_forward(dims, reps: int = 5):
     """Time the network's forward pass (bf16 matrix-core mixing) on a random field of the
     given extents, with the identity-path initial weights plus noise."""

@@ -395,6 +395,85 @@ def autotune(op: Op, prec: str = "f64", nrhs: int = 1) -> str:
     return buf.value.decode()
 
 
+# ------------------------------------------------------------------ autotune cache
+#
+# The tuner times every candidate shape (tens of milliseconds at 32^3 x 64); its choice
+# depends on the lattice, the precision, the number of fields per launch, the device and the
+# D kernels themselves, so a cache entry is keyed by all five and a kernel source change
+# misses the cache.
+
+_TUNE_SOURCES = ("dirac.hip", "dirac_core.h", "qdw_internal.h")
+
+
+def kernel_version() -> str:
+    """A short hash of the D kernels' sources next to the library (empty if absent)."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in _TUNE_SOURCES:
+        f = os.path.join(_HERE, "csrc", name)
+        if not os.path.exists(f):
+            return ""
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def tune_key(dims, prec: str, nrhs: int, device: str, kernels: str) -> str:
+    return "%s|%s|nrhs%d|%s|%s" % ("x".join(str(int(v)) for v in dims), prec, int(nrhs),
+                                   device, kernels)
+
+
+def read_tune_cache(path: str, key: str):
+    """The cached (ts, nt, pipe, walk, march) for key, or None (no file, no entry, or an
+    entry that is not five integers)."""
+    import json
+    try:
+        with open(path) as fh:
+            entries = json.load(fh).get("entries", {})
+    except (OSError, ValueError, AttributeError):
+        return None
+    shape = entries.get(key) if isinstance(entries, dict) else None
+    if isinstance(shape, list) and len(shape) == 5 and all(isinstance(v, int) for v in shape):
+        return tuple(shape)
+    return None
+
+
+def write_tune_cache(path: str, key: str, shape) -> None:
+    """Add or replace one entry; the file is rewritten whole through a temporary file, so
+    a reader never sees a partial file."""
+    import json
+    data = {"version": 1, "entries": {}}
+    try:
+        with open(path) as fh:
+            old = json.load(fh)
+        if isinstance(old, dict) and isinstance(old.get("entries"), dict):
+            data["entries"] = old["entries"]
+    except (OSError, ValueError):
+        pass
+    data["entries"][key] = [int(v) for v in shape]
+    tmp = "%s.tmp%d" % (path, os.getpid())
+    with open(tmp, "w") as fh:
+        json.dump(data, fh, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def autotune_cached(op: Op, prec: str = "f64", nrhs: int = 1, path: str | None = None):
+    """Set the D-kernel shape for this operator from the cache file when it holds one for
+    this lattice, precision, field count, device and kernel version; otherwise run the
+    tuner and store its choice. Returns ("cached" or "tuned", shape)."""
+    torch = _torch()
+    path = path or os.path.join(_HERE, "dw_shapes.json")
+    key = tune_key(op.dims, prec, nrhs, torch.cuda.get_device_name(op.device), kernel_version())
+    shape = read_tune_cache(path, key)
+    if shape is not None:
+        set_dw_shape(op, prec, *shape)
+        return "cached", shape
+    autotune(op, prec, nrhs)
+    shape = get_dw_shape(op, prec)
+    write_tune_cache(path, key, shape)
+    return "tuned", shape
+
+
 def set_dw_shape(op: Op, prec: str, ts: int, nt: int, pipe: int, walk: int = 0, march: int = 0):
     """Pin the D kernel's shape for one precision (what the autotuner would choose)."""
     _check(load().qdw_set_dw_shape(op.handle, PREC[prec], ts, nt, pipe, walk, march),
