@@ -375,7 +375,7 @@ def solve_from(op: Op, eta, x0, psi, solver: str = "gcr", res: float = 1e-10, **
     against eta. Every step runs in the library's kernels."""
     if solver not in ("gcr", "cgne"):
         raise QdwError("solve_from: solver 'gcr' or 'cgne'")
-    t = op.new_field("f64")
+    t = op.new_field("f64") if solver == "cgne" else None
 
     def apply(x, out):
         if solver == "gcr":
@@ -477,7 +477,8 @@ def read_tune_cache(path: str, key: str):
 
 def write_tune_cache(path: str, key: str, shape) -> None:
     """Add or replace one entry; the file is rewritten whole through a temporary file, so
-    a reader never sees a partial file."""
+    a reader never sees a partial file (of two processes writing at once, the later write
+    keeps only its own new entry)."""
     import json
     data = {"version": 1, "entries": {}}
     try:
