@@ -477,8 +477,8 @@ def read_tune_cache(path: str, key: str):
 
 def write_tune_cache(path: str, key: str, shape) -> None:
     """Add or replace one entry; the file is rewritten whole through a temporary file, so
-    a reader never sees a partial file (of two processes writing at once, the later write
-    keeps only its own new entry)."""
+    a reader never sees a partial file; an entry that another process writes between this
+    call's read and its write is lost."""
     import json
     data = {"version": 1, "entries": {}}
     try:
